@@ -1,0 +1,274 @@
+"""Plain FP64 CPU oracle for PDCS (restarted, reflected-Halpern, adaptive-step
+PDHG for conic programs; Lin, Xiong, Ge, Ye).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The GPU product
+path (``paper_2505_00311_amd``) never imports it and shares no code with it.
+
+The arithmetic lives in ``pdcs_oracle.c`` (C99, double precision, single
+thread); this module only compiles it with gcc and marshals numpy arrays
+through ctypes.  An instance is any object with the attributes
+``n, m, n_box, row_ptr, col, val, c, h, l, u, xcone_type, xcone_dim,
+rcone_type, rcone_dim``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pdcs_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+ZERO, FREE, NONNEG, SOC, EXP, EXP_DUAL = range(6)
+OPTIMAL, ITER_LIMIT, TIME_LIMIT, NUMERICAL = range(4)
+
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_dbl = ctypes.c_double
+_pd = ctypes.POINTER(ctypes.c_double)
+_pi32 = ctypes.POINTER(ctypes.c_int32)
+_pi64 = ctypes.POINTER(ctypes.c_int64)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+             "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("n", _i64), ("m", _i64), ("nnz", _i64), ("n_box", _i64),
+                ("row_ptr", _pi64), ("col", _pi32), ("val", _pd),
+                ("c", _pd), ("h", _pd), ("l", _pd), ("u", _pd),
+                ("n_xcones", _i64), ("xcone_type", _pi32), ("xcone_dim", _pi64),
+                ("n_rcones", _i64), ("rcone_type", _pi32), ("rcone_dim", _pi64)]
+
+
+class Settings(ctypes.Structure):
+    _fields_ = [("tol", _dbl), ("max_iter", _i64), ("check_every", _i32),
+                ("ruiz_iters", _i32), ("pock_chambolle", _i32), ("beta_mode", _i32),
+                ("beta_const", _dbl), ("beta_grow", _dbl), ("beta_shrink", _dbl),
+                ("step_reduce_exp", _dbl), ("step_grow_exp", _dbl),
+                ("restart_sufficient", _dbl), ("restart_necessary", _dbl),
+                ("restart_artificial", _dbl), ("max_attempts", _i32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("status", _i32), ("iterations", _i64), ("attempts", _i64),
+                ("restarts", _i64), ("pobj", _dbl), ("dobj", _dbl), ("err_p", _dbl),
+                ("err_d", _dbl), ("err_gap", _dbl), ("omega", _dbl), ("eta", _dbl)]
+
+
+class _Trace(ctypes.Structure):
+    _fields_ = [("cap", _i64), ("count", _i64), ("attempts", _pi32), ("eta_used", _pd),
+                ("beta", _pd), ("omega", _pd), ("check_code", _pi32), ("check_kkt", _pd),
+                ("n_snap", _i64), ("snap_iter", _pi64), ("snap_x", _pd), ("snap_y", _pd)]
+
+
+_lib_handle = None
+
+
+def _lib():
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        L.orc_settings_default.argtypes = [ctypes.POINTER(Settings)]
+        L.orc_proj_soc.argtypes = [_i64, _pd, _pd, _pd]
+        L.orc_proj_exp.argtypes = [_pd, _pd, _pd]
+        L.orc_proj_exp_dual.argtypes = [_pd, _pd, _pd]
+        L.orc_proj_blocks.argtypes = [_i64, _pi32, _pi64, ctypes.c_int, _pd, _pd]
+        L.orc_proj_blocks.restype = None
+        L.orc_scaling.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(Settings), _pd, _pd]
+        L.orc_kkt.argtypes = [ctypes.POINTER(_Problem), _pd, _pd, _pd, _pd, _pd, _pd, _pd]
+        L.orc_onepdhg.argtypes = [ctypes.POINTER(_Problem), _pd, _pd, _dbl, _dbl, _pd, _pd]
+        L.orc_solve.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(Settings), _pd, _pd,
+                                _dbl, _pd, _pd, ctypes.POINTER(_Info), ctypes.POINTER(_Trace)]
+        _lib_handle = L
+    return _lib_handle
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct)) if a is not None else None
+
+
+class _Keep:
+    """Holds the contiguous copies a ctypes struct points into."""
+
+    def __init__(self):
+        self.refs = []
+
+    def arr(self, a, dtype):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=dtype)
+        self.refs.append(a)
+        return a
+
+
+def _problem(inst, keep: _Keep) -> _Problem:
+    rp = keep.arr(inst.row_ptr, np.int64)
+    col = keep.arr(inst.col, np.int32)
+    val = keep.arr(inst.val, np.float64)
+    c = keep.arr(inst.c, np.float64)
+    h = keep.arr(inst.h, np.float64)
+    nb = int(inst.n_box)
+    l = keep.arr(inst.l if nb else np.zeros(1), np.float64)
+    u = keep.arr(inst.u if nb else np.zeros(1), np.float64)
+    xt = keep.arr(inst.xcone_type, np.int32)
+    xd = keep.arr(inst.xcone_dim, np.int64)
+    rt = keep.arr(inst.rcone_type, np.int32)
+    rd = keep.arr(inst.rcone_dim, np.int64)
+    return _Problem(int(inst.n), int(inst.m), int(val.size), nb,
+                    _ptr(rp, ctypes.c_int64), _ptr(col, ctypes.c_int32), _ptr(val, ctypes.c_double),
+                    _ptr(c, ctypes.c_double), _ptr(h, ctypes.c_double),
+                    _ptr(l, ctypes.c_double), _ptr(u, ctypes.c_double),
+                    int(xt.size), _ptr(xt, ctypes.c_int32), _ptr(xd, ctypes.c_int64),
+                    int(rt.size), _ptr(rt, ctypes.c_int32), _ptr(rd, ctypes.c_int64))
+
+
+def default_settings(**overrides) -> Settings:
+    s = Settings()
+    _lib().orc_settings_default(ctypes.byref(s))
+    for k, v in overrides.items():
+        if not hasattr(s, k):
+            raise KeyError(k)
+        setattr(s, k, v)
+    return s
+
+
+# ---------------------------------------------------------------- projections
+def proj_soc(v, d=None):
+    """Projection onto D K_soc (Theorem 1). Returns (projection, case)."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    dd = None if d is None else np.ascontiguousarray(d, dtype=np.float64)
+    out = np.empty_like(v)
+    case = _lib().orc_proj_soc(v.size, _ptr(v, ctypes.c_double), _ptr(dd, ctypes.c_double),
+                               _ptr(out, ctypes.c_double))
+    return out, case
+
+
+def proj_exp(v, d=None):
+    """Projection onto D K_exp (Theorem 3). Returns (projection, case)."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    dd = None if d is None else np.ascontiguousarray(d, dtype=np.float64)
+    out = np.empty(3)
+    case = _lib().orc_proj_exp(_ptr(v, ctypes.c_double), _ptr(dd, ctypes.c_double),
+                               _ptr(out, ctypes.c_double))
+    return out, case
+
+
+def proj_exp_dual(v, d=None):
+    """Projection onto D K_exp^* (Remark of Appendix A.2). Returns (projection, case)."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    dd = None if d is None else np.ascontiguousarray(d, dtype=np.float64)
+    out = np.empty(3)
+    case = _lib().orc_proj_exp_dual(_ptr(v, ctypes.c_double), _ptr(dd, ctypes.c_double),
+                                    _ptr(out, ctypes.c_double))
+    return out, case
+
+
+def proj_blocks(types, dims, v, d=None, dual=False):
+    """Projection onto a product of (scaled) cones, eq. (6)."""
+    t = np.ascontiguousarray(types, dtype=np.int32)
+    k = np.ascontiguousarray(dims, dtype=np.int64)
+    out = np.array(v, dtype=np.float64, copy=True)
+    dd = None if d is None else np.ascontiguousarray(d, dtype=np.float64)
+    _lib().orc_proj_blocks(t.size, _ptr(t, ctypes.c_int32), _ptr(k, ctypes.c_int64),
+                           1 if dual else 0, _ptr(dd, ctypes.c_double), _ptr(out, ctypes.c_double))
+    return out
+
+
+# ---------------------------------------------------------------- problem-level
+def scaling(inst, settings: Settings | None = None):
+    keep = _Keep()
+    P = _problem(inst, keep)
+    s = settings or default_settings()
+    e = np.empty(int(inst.m))
+    f = np.empty(int(inst.n))
+    _lib().orc_scaling(ctypes.byref(P), ctypes.byref(s), _ptr(e, ctypes.c_double),
+                       _ptr(f, ctypes.c_double))
+    return e, f
+
+
+def kkt(inst, x, y):
+    """eq. (PDCS_terminate_tolerance) at unscaled (x, y)."""
+    keep = _Keep()
+    P = _problem(inst, keep)
+    x = keep.arr(x, np.float64)
+    y = keep.arr(y, np.float64)
+    out = [ctypes.c_double() for _ in range(5)]
+    _lib().orc_kkt(ctypes.byref(P), _ptr(x, ctypes.c_double), _ptr(y, ctypes.c_double),
+                   *[ctypes.byref(o) for o in out])
+    ep, ed, eg, po, do = (o.value for o in out)
+    return {"err_p": ep, "err_d": ed, "err_gap": eg, "pobj": po, "dobj": do}
+
+
+def onepdhg(inst, x, y, tau, sigma):
+    """One PDHG step, eq. (5), on the unscaled problem."""
+    keep = _Keep()
+    P = _problem(inst, keep)
+    x = keep.arr(x, np.float64)
+    y = keep.arr(y, np.float64)
+    xh = np.empty(int(inst.n))
+    yh = np.empty(int(inst.m))
+    _lib().orc_onepdhg(ctypes.byref(P), _ptr(x, ctypes.c_double), _ptr(y, ctypes.c_double),
+                       float(tau), float(sigma), _ptr(xh, ctypes.c_double),
+                       _ptr(yh, ctypes.c_double))
+    return xh, yh
+
+
+def solve(inst, settings: Settings | None = None, x0=None, y0=None, omega0: float = 0.0,
+          log_cap: int = 0, snap_iters=None):
+    """Algorithm 1 with rescaling.  Returns a dict with x, y, info fields and,
+    if requested, the decision log and iterate snapshots."""
+    keep = _Keep()
+    P = _problem(inst, keep)
+    s = settings or default_settings()
+    n, m = int(inst.n), int(inst.m)
+    x0a = keep.arr(x0, np.float64)
+    y0a = keep.arr(y0, np.float64)
+    x = np.empty(n)
+    y = np.empty(m)
+    info = _Info()
+    tr = None
+    logs = None
+    if log_cap or snap_iters is not None:
+        cap = max(int(log_cap), 1)
+        snaps = np.ascontiguousarray(snap_iters if snap_iters is not None else [], dtype=np.int64)
+        logs = {"attempts": np.zeros(cap, np.int32), "eta_used": np.zeros(cap),
+                "beta": np.zeros(cap), "omega": np.zeros(cap),
+                "check_code": np.zeros(cap, np.int32), "check_kkt": np.zeros(cap),
+                "snap_iter": snaps, "snap_x": np.zeros((max(snaps.size, 1), n)),
+                "snap_y": np.zeros((max(snaps.size, 1), m))}
+        tr = _Trace(cap, 0, _ptr(logs["attempts"], ctypes.c_int32),
+                    _ptr(logs["eta_used"], ctypes.c_double), _ptr(logs["beta"], ctypes.c_double),
+                    _ptr(logs["omega"], ctypes.c_double),
+                    _ptr(logs["check_code"], ctypes.c_int32),
+                    _ptr(logs["check_kkt"], ctypes.c_double), int(snaps.size),
+                    _ptr(snaps, ctypes.c_int64), _ptr(logs["snap_x"], ctypes.c_double),
+                    _ptr(logs["snap_y"], ctypes.c_double))
+    rc = _lib().orc_solve(ctypes.byref(P), ctypes.byref(s), _ptr(x0a, ctypes.c_double),
+                          _ptr(y0a, ctypes.c_double), float(omega0), _ptr(x, ctypes.c_double),
+                          _ptr(y, ctypes.c_double), ctypes.byref(info),
+                          ctypes.byref(tr) if tr is not None else None)
+    if rc != 0:
+        raise ValueError(f"oracle rejected the problem (code {rc})")
+    res = {k: getattr(info, k) for k, _ in _Info._fields_}
+    res["x"], res["y"] = x, y
+    if logs is not None:
+        cnt = tr.count
+        for k in ("attempts", "eta_used", "beta", "omega", "check_code", "check_kkt"):
+            logs[k] = logs[k][:cnt]
+        res["log"] = logs
+    return res

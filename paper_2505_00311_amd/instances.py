@@ -1,0 +1,325 @@
+"""Seeded synthetic conic-program instances.
+
+This module only draws problem data.  It holds none of the solver's arithmetic
+(no projection, scaling, step or KKT formula) and is the one module that both
+the GPU path's tests/benchmark and the CPU oracle's tests take inputs from.
+
+Every generator builds a problem of the form of the paper's eq. (1),
+    min <c,x>  s.t.  G x - h in K_d^*,  l <= x_1 <= u,  x_2 in K_p,
+and, where stated, plants a primal-dual optimum: it draws x* in X, lambda* in
+the dual of X, a slack s* in K_d^* and y* in K_d with <x*,lambda*> = 0 and
+<s*,y*> = 0 blockwise, then sets h = G x* - s* and c = G^T y* + lambda*.  The
+planted objective <c, x*> is then the optimal value.
+
+Cone type codes: ZERO 0, FREE 1, NONNEG 2, SOC 3, EXP 4, EXP_DUAL 5.
+A row block of type T states G x - h in T.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+ZERO, FREE, NONNEG, SOC, EXP, EXP_DUAL = range(6)
+
+
+@dataclass
+class Instance:
+    n: int
+    m: int
+    n_box: int
+    row_ptr: np.ndarray          # int64 [m+1]
+    col: np.ndarray              # int32 [nnz]
+    val: np.ndarray              # float64 [nnz]
+    c: np.ndarray                # float64 [n]
+    h: np.ndarray                # float64 [m]
+    l: np.ndarray                # float64 [n_box]
+    u: np.ndarray                # float64 [n_box]
+    xcone_type: np.ndarray       # int32
+    xcone_dim: np.ndarray        # int64
+    rcone_type: np.ndarray       # int32
+    rcone_dim: np.ndarray        # int64
+    x_star: np.ndarray | None = None
+    y_star: np.ndarray | None = None
+    opt: float | None = None
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.val.size)
+
+    def dense(self) -> np.ndarray:
+        A = np.zeros((self.m, self.n))
+        for i in range(self.m):
+            s, e = self.row_ptr[i], self.row_ptr[i + 1]
+            A[i, self.col[s:e]] += self.val[s:e]
+        return A
+
+
+# ----------------------------------------------------------------- matrices
+def csr_from_coo(m, n, rows, cols, vals):
+    """Row-sorted CSR with duplicates summed."""
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    vals = np.asarray(vals, dtype=np.float64)
+    key = rows * n + cols
+    order = np.argsort(key, kind="stable")
+    key, vals = key[order], vals[order]
+    uk, start = np.unique(key, return_index=True)
+    v = np.add.reduceat(vals, start) if vals.size else vals
+    r = uk // n
+    cidx = (uk % n).astype(np.int32)
+    rp = np.zeros(m + 1, dtype=np.int64)
+    np.add.at(rp, r + 1, 1)
+    return np.cumsum(rp), cidx, v
+
+
+def bernoulli_csr(rng, m, n, density):
+    """Exactly-Bernoulli(density) sparsity pattern with N(0,1) values."""
+    nnz_target = rng.binomial(m * n, density)
+    flat = rng.choice(m * n, size=nnz_target, replace=False) if m * n > 0 else np.zeros(0, int)
+    flat.sort()
+    rows, cols = flat // n, flat % n
+    return csr_from_coo(m, n, rows, cols, rng.standard_normal(flat.size))
+
+
+def powerlaw_csr(rng, m, n, mean_row_nnz=20, alpha=0.8):
+    """Rows with 1 + Poisson(mean-1) entries; columns drawn with weight
+    (rank+1)^-alpha over a random permutation (duplicates in a row dropped)."""
+    perm = rng.permutation(n)
+    w = (np.arange(n, dtype=np.float64) + 1.0) ** (-alpha)
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    k = 1 + rng.poisson(mean_row_nnz - 1, size=m)
+    total = int(k.sum())
+    ranks = np.minimum(np.searchsorted(cdf, rng.random(total), side="right"), n - 1)
+    cols = perm[ranks].astype(np.int64)
+    rows = np.repeat(np.arange(m, dtype=np.int64), k)
+    key = np.unique(rows * n + cols)
+    rows, cols = key // n, key % n
+    rp = np.zeros(m + 1, dtype=np.int64)
+    np.add.at(rp, rows + 1, 1)
+    return np.cumsum(rp), cols.astype(np.int32), rng.standard_normal(key.size)
+
+
+def csr_matvec(rp, col, val, x):
+    rows = np.repeat(np.arange(rp.size - 1), np.diff(rp))
+    out = np.zeros(rp.size - 1)
+    np.add.at(out, rows, val * x[col])
+    return out
+
+
+def csr_rmatvec(rp, col, val, y, n):
+    rows = np.repeat(np.arange(rp.size - 1), np.diff(rp))
+    out = np.zeros(n)
+    np.add.at(out, col, val * y[rows])
+    return out
+
+
+# ----------------------------------------------------------- planted pairs
+def _pair_block(rng, typ, k):
+    """(p, d) with p in the cone `typ`, d in its dual cone and <p, d> = 0."""
+    if typ == ZERO:
+        return np.zeros(k), rng.standard_normal(k)
+    if typ == FREE:
+        return rng.standard_normal(k), np.zeros(k)
+    if typ == NONNEG:
+        act = rng.random(k) < 0.5
+        mag = np.abs(rng.standard_normal(k))
+        return np.where(act, 0.0, mag), np.where(act, np.abs(rng.standard_normal(k)), 0.0)
+    if typ == SOC:
+        w = rng.standard_normal(k - 1)
+        nw = np.linalg.norm(w)
+        kind = rng.integers(3)
+        if kind == 0:   # boundary, complementary boundary pair
+            a = rng.uniform(0.5, 2.0)
+            return np.concatenate([[nw], w]), a * np.concatenate([[nw], -w])
+        if kind == 1:   # interior primal
+            return np.concatenate([[nw + rng.uniform(0.5, 2.0)], w]), np.zeros(k)
+        return np.zeros(k), np.concatenate([[nw + rng.uniform(0.5, 2.0)], w])
+    if typ in (EXP, EXP_DUAL):
+        rho = rng.standard_normal()
+        sp, rd = rng.uniform(0.5, 2.0, size=2)
+        p = sp * np.array([rho, 1.0, np.exp(rho)])           # in K_exp, boundary
+        d = rd * np.array([-1.0, rho - 1.0, np.exp(-rho)])   # in K_exp^*, boundary
+        return (p, d) if typ == EXP else (d, p)
+    raise ValueError(typ)
+
+
+def _split(vec, dims):
+    out, o = [], 0
+    for k in dims:
+        out.append(slice(o, o + int(k)))
+        o += int(k)
+    return out
+
+
+def plant(rng, n, m, n_box, row_ptr, col, val, xtypes, xdims, rtypes, rdims,
+          box_kind="finite", name=""):
+    """Complete (G, cones) to an instance with a planted optimum."""
+    xtypes = np.asarray(xtypes, np.int32)
+    xdims = np.asarray(xdims, np.int64)
+    rtypes = np.asarray(rtypes, np.int32)
+    rdims = np.asarray(rdims, np.int64)
+    assert int(xdims.sum()) == n - n_box and int(rdims.sum()) == m
+    x = np.zeros(n)
+    lam = np.zeros(n)
+    l = np.zeros(n_box)
+    u = np.zeros(n_box)
+    if n_box:
+        lo = -rng.uniform(0.0, 2.0, n_box)
+        hi = rng.uniform(0.0, 2.0, n_box)
+        if box_kind == "mixed":     # some one-sided and free entries
+            kind = rng.integers(4, size=n_box)
+            lo = np.where(kind == 1, -np.inf, lo)
+            hi = np.where(kind == 2, np.inf, hi)
+            lo = np.where(kind == 3, -np.inf, lo)
+            hi = np.where(kind == 3, np.inf, hi)
+        l[:], u[:] = lo, hi
+        state = rng.integers(3, size=n_box)        # 0 at l, 1 at u, 2 inside
+        state = np.where((state == 0) & ~np.isfinite(lo), 2, state)
+        state = np.where((state == 1) & ~np.isfinite(hi), 2, state)
+        mag = rng.uniform(0.5, 2.0, n_box)
+        lo_f = np.where(np.isfinite(lo), lo, -3.0)
+        hi_f = np.where(np.isfinite(hi), hi, 3.0)
+        inside = lo_f + rng.uniform(0.2, 0.8, n_box) * (hi_f - lo_f)
+        x[:n_box] = np.where(state == 0, lo_f, np.where(state == 1, hi_f, inside))
+        lam[:n_box] = np.where(state == 0, mag, np.where(state == 1, -mag, 0.0))
+    for t, sl in zip(xtypes, _split(None, xdims)):
+        p, d = _pair_block(rng, int(t), sl.stop - sl.start)
+        x[n_box + sl.start:n_box + sl.stop] = p
+        lam[n_box + sl.start:n_box + sl.stop] = d
+    s = np.zeros(m)
+    y = np.zeros(m)
+    for t, sl in zip(rtypes, _split(None, rdims)):
+        p, d = _pair_block(rng, int(t), sl.stop - sl.start)
+        s[sl], y[sl] = p, d
+    gx = csr_matvec(row_ptr, col, val, x)
+    h = gx - s
+    c = csr_rmatvec(row_ptr, col, val, y, n) + lam
+    return Instance(n=n, m=m, n_box=n_box, row_ptr=np.asarray(row_ptr, np.int64),
+                    col=np.asarray(col, np.int32), val=np.asarray(val, np.float64), c=c, h=h,
+                    l=l, u=u, xcone_type=xtypes, xcone_dim=xdims, rcone_type=rtypes,
+                    rcone_dim=rdims, x_star=x, y_star=y, opt=float(c @ x), name=name)
+
+
+# ------------------------------------------------------------ workloads
+def small_mixed(seed, n=40, m=24, density=0.2, n_box=6, box_kind="mixed"):
+    """A small instance touching every cone type on both sides."""
+    rng = np.random.default_rng(seed)
+    rp, ci, v = bernoulli_csr(rng, m, n, density)
+    rest = n - n_box
+    xt, xd = [], []
+    pattern = [(NONNEG, 5), (SOC, 4), (EXP, 3), (SOC, 7), (EXP_DUAL, 3), (FREE, 2), (ZERO, 1)]
+    i = 0
+    while rest > 0:
+        t, k = pattern[i % len(pattern)]
+        k = min(k, rest)
+        if t in (EXP, EXP_DUAL) and k != 3:
+            t = NONNEG
+        xt.append(t), xd.append(k)
+        rest -= k
+        i += 1
+    rt, rd = [], []
+    rest = m
+    rpattern = [(ZERO, 3), (NONNEG, 4), (SOC, 5), (EXP, 3), (EXP_DUAL, 3), (FREE, 1)]
+    i = 0
+    while rest > 0:
+        t, k = rpattern[i % len(rpattern)]
+        k = min(k, rest)
+        if t in (EXP, EXP_DUAL) and k != 3:
+            t = NONNEG
+        rt.append(t), rd.append(k)
+        rest -= k
+        i += 1
+    return plant(rng, n, m, n_box, rp, ci, v, xt, xd, rt, rd, box_kind=box_kind,
+                 name=f"small_mixed(seed={seed})")
+
+
+def lp_soc_small(seed):
+    """The small single-instance workload: n=1000 variables, m=500 rows, G at 1%
+    Bernoulli density with N(0,1) entries; x: 500 nonnegative + 50 SOC(10);
+    rows: 250 equality + 250 inequality; planted optimum."""
+    rng = np.random.default_rng(seed)
+    n, m = 1000, 500
+    rp, ci, v = bernoulli_csr(rng, m, n, 0.01)
+    xt = [NONNEG] + [SOC] * 50
+    xd = [500] + [10] * 50
+    return plant(rng, n, m, 0, rp, ci, v, xt, xd, [ZERO, NONNEG], [250, 250],
+                 name="lp_soc_n1000_m500")
+
+
+def large_mixed(seed, n=1_000_000, m=500_000, n_box=None, n_soc_x=None, n_soc_r=None,
+                n_exp_r=None, mean_row_nnz=20):
+    """The large single-instance workload (defaults: n=1e6, m=5e5, ~1e7 nnz).
+
+    Rows hold 1 + Poisson(19) entries whose columns follow power-law degrees
+    (weight (rank+1)^-0.8 over a random permutation); entries are N(0,1) times a
+    per-row scale 10^U(-3,3).  Cones: 1e5 box entries; 1e4 SOC blocks of dim
+    U{3..100} on x and 1e4 of dim U{3..40} on rows; 1e4 exponential-cone row
+    blocks; the other rows split into equality and inequality rows and the
+    other entries of x are nonnegative.  All counts shrink with n."""
+    rng = np.random.default_rng(seed)
+    sc = n / 1_000_000
+    n_box = int(round(100_000 * sc)) if n_box is None else n_box
+    n_soc_x = int(round(10_000 * sc)) if n_soc_x is None else n_soc_x
+    n_soc_r = int(round(10_000 * sc)) if n_soc_r is None else n_soc_r
+    n_exp_r = int(round(10_000 * sc)) if n_exp_r is None else n_exp_r
+    rp, ci, v = powerlaw_csr(rng, m, n, mean_row_nnz=mean_row_nnz)
+    rowscale = 10.0 ** rng.uniform(-3.0, 3.0, m)
+    v = v * np.repeat(rowscale, np.diff(rp))
+    sx = rng.integers(3, 101, size=n_soc_x)
+    sr = rng.integers(3, 41, size=n_soc_r)
+    n_nonneg_x = n - n_box - int(sx.sum())
+    assert n_nonneg_x >= 0
+    xt = [NONNEG] + [SOC] * n_soc_x
+    xd = [n_nonneg_x] + list(sx)
+    rest = m - int(sr.sum()) - 3 * n_exp_r
+    assert rest >= 0
+    n_eq = rest // 2
+    # interleave row blocks so that cone types are spread over the row range
+    blocks = [(SOC, int(k)) for k in sr] + [(EXP, 3)] * n_exp_r
+    order = rng.permutation(len(blocks))
+    rt = [ZERO, NONNEG] + [blocks[i][0] for i in order]
+    rd = [n_eq, rest - n_eq] + [blocks[i][1] for i in order]
+    keep = [i for i, k in enumerate(rd) if k > 0]
+    rt = [rt[i] for i in keep]
+    rd = [rd[i] for i in keep]
+    return plant(rng, n, m, n_box, rp, ci, v, xt, xd, rt, rd,
+                 name=f"large_mixed_n{n}_m{m}")
+
+
+def tiny_lp(seed, n=3, m=3):
+    """min c^T x s.t. G x - h >= 0, l <= x <= u (finite box): a bounded LP
+    small enough for vertex enumeration."""
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((m, n))
+    rows, cols = np.nonzero(np.ones((m, n)))
+    rp, ci, v = csr_from_coo(m, n, rows, cols, G[rows, cols])
+    x_in = rng.uniform(-0.5, 0.5, n)
+    h = G @ x_in - rng.uniform(0.1, 1.0, m)    # x_in strictly feasible
+    c = rng.standard_normal(n)
+    return Instance(n=n, m=m, n_box=n, row_ptr=rp, col=ci, val=v, c=c, h=h,
+                    l=-np.ones(n), u=np.ones(n), xcone_type=np.zeros(0, np.int32),
+                    xcone_dim=np.zeros(0, np.int64), rcone_type=np.array([NONNEG], np.int32),
+                    rcone_dim=np.array([m], np.int64), name=f"tiny_lp({seed})")
+
+
+def ball_socp(seed, n=4):
+    """min c^T x s.t. ||W (x - x0)|| <= r, W diagonal positive; x free.
+    Rows: one SOC block (r, W x - W x0); the first row of G is empty."""
+    rng = np.random.default_rng(seed)
+    W = rng.uniform(0.5, 2.0, n)
+    x0 = rng.standard_normal(n)
+    r = rng.uniform(0.5, 2.0)
+    c = rng.standard_normal(n)
+    rows = np.arange(1, n + 1)
+    cols = np.arange(n)
+    rp, ci, v = csr_from_coo(n + 1, n, rows, cols, W)
+    h = np.concatenate([[-r], W * x0])
+    return Instance(n=n, m=n + 1, n_box=n, row_ptr=rp, col=ci, val=v, c=c, h=h,
+                    l=np.full(n, -np.inf), u=np.full(n, np.inf),
+                    xcone_type=np.zeros(0, np.int32), xcone_dim=np.zeros(0, np.int64),
+                    rcone_type=np.array([SOC], np.int32), rcone_dim=np.array([n + 1], np.int64),
+                    name=f"ball_socp({seed})", meta={"W": W, "x0": x0, "r": r})

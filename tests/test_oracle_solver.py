@@ -1,0 +1,212 @@
+"""Pins of the oracle's problem-level functions (CPU only): termination
+measures (Section 5 eq. (PDCS_terminate_tolerance)), one PDHG step (Section
+2.1 eq. (5)), the diagonal rescaling (Section 3) and the full Algorithm 1."""
+import itertools
+
+import numpy as np
+import pytest
+
+from helpers import instance_from_dense, load_golden
+from paper_2505_00311_amd import instances as I
+
+
+# ------------------------------------------------------------------ KKT
+def _golden_instance(cs):
+    return instance_from_dense(cs["n"], cs["m"], cs["n_box"], cs["G"], cs["c"], cs["h"],
+                               cs["l"], cs["u"], cs["xcones"], cs["rcones"])
+
+
+def test_kkt_hand_examples(orc):
+    g = load_golden("kkt_hand.json")
+    for cs in g["cases"]:
+        inst = _golden_instance(cs)
+        k = orc.kkt(inst, np.array(cs["x"]), np.array(cs["y"]))
+        for key in ("err_p", "err_d", "err_gap", "pobj", "dobj"):
+            assert k[key] == pytest.approx(cs[key], rel=1e-15, abs=1e-15), (cs["note"], key)
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: I.small_mixed(0), lambda: I.small_mixed(3, box_kind="finite"),
+    lambda: I.lp_soc_small(20250501), lambda: I.large_mixed(5, n=3000, m=1500)])
+def test_kkt_zero_at_planted_optimum(orc, maker):
+    inst = maker()
+    k = orc.kkt(inst, inst.x_star, inst.y_star)
+    assert max(k["err_p"], k["err_d"], k["err_gap"]) < 1e-12
+    assert k["pobj"] == pytest.approx(inst.opt, rel=1e-12, abs=1e-12)
+
+
+def test_kkt_responds_to_perturbations(orc):
+    inst = I.small_mixed(1)
+    rng = np.random.default_rng(0)
+    base = orc.kkt(inst, inst.x_star, inst.y_star)
+    # moving y off the optimum breaks dual feasibility or the gap
+    for eps in (1e-4, 1e-2):
+        y = inst.y_star + eps * rng.standard_normal(inst.m)
+        k = orc.kkt(inst, inst.x_star, y)
+        assert max(k["err_d"], k["err_gap"]) > max(base["err_d"], base["err_gap"]) + eps * 1e-3
+    # scaling x by 2 leaves x in its cone but breaks G x - h in K_d^* or the gap
+    k = orc.kkt(inst, 2.0 * inst.x_star, inst.y_star)
+    assert max(k["err_p"], k["err_gap"]) > 1e-3
+
+
+# ------------------------------------------------------------ one PDHG step
+def test_onepdhg_hand_example(orc):
+    g = load_golden("onepdhg_2x2.json")
+    pr = g["problem"]
+    inst = instance_from_dense(pr["n"], pr["m"], pr["n_box"], pr["G"], pr["c"], pr["h"], [], [],
+                               pr["xcones"], pr["rcones"])
+    xh, yh = orc.onepdhg(inst, np.array(g["x"]), np.array(g["y"]), g["tau"], g["sigma"])
+    assert np.allclose(xh, g["x_hat"], rtol=1e-15, atol=1e-15)
+    assert np.allclose(yh, g["y_hat"], rtol=1e-15, atol=1e-15)
+
+
+def test_onepdhg_fixed_point_at_optimum(orc):
+    """A saddle point is a fixed point of eq. (5) for any step sizes."""
+    inst = I.small_mixed(2)
+    for tau, sigma in ((0.1, 0.1), (0.5, 0.02), (0.01, 2.0)):
+        xh, yh = orc.onepdhg(inst, inst.x_star, inst.y_star, tau, sigma)
+        assert np.allclose(xh, inst.x_star, atol=1e-11)
+        assert np.allclose(yh, inst.y_star, atol=1e-11)
+
+
+# ---------------------------------------------------------------- scaling
+def test_scaling_ruiz_equilibrates(orc):
+    """Enough Ruiz passes drive every row and column infinity norm of E G F to 1."""
+    inst = I.small_mixed(4, n=60, m=30, density=0.3)
+    s = orc.default_settings(ruiz_iters=60, pock_chambolle=0)
+    e, f = orc.scaling(inst, s)
+    A = np.abs(inst.dense()) * e[:, None] * f[None, :]
+    rows = A.max(axis=1)
+    cols = A.max(axis=0)
+    assert np.allclose(rows[rows > 0], 1.0, atol=1e-6)
+    assert np.allclose(cols[cols > 0], 1.0, atol=1e-6)
+
+
+def test_scaling_pock_chambolle_closed_form(orc):
+    """With no Ruiz pass, one alpha=1 Pock-Chambolle pass on a rank-one |u v^T|
+    gives e_i = (|u_i| sum|v|)^-1/2, f_j = (|v_j| sum|u|)^-1/2."""
+    rng = np.random.default_rng(3)
+    u = rng.uniform(0.5, 3, 5) * rng.choice([-1, 1], 5)
+    v = rng.uniform(0.5, 3, 7) * rng.choice([-1, 1], 7)
+    G = np.outer(u, v)
+    inst = instance_from_dense(7, 5, 7, G, np.ones(7), np.ones(5), [-1] * 7, [1] * 7, [],
+                               [[2, 5]])
+    e, f = orc.scaling(inst, orc.default_settings(ruiz_iters=0, pock_chambolle=1))
+    assert np.allclose(e, 1 / np.sqrt(np.abs(u) * np.abs(v).sum()), rtol=1e-14)
+    assert np.allclose(f, 1 / np.sqrt(np.abs(v) * np.abs(u).sum()), rtol=1e-14)
+
+
+def test_scaling_empty_rows_and_columns_keep_one(orc):
+    G = np.array([[0.0, 4.0, 0.0], [0.0, 0.0, 0.0]])
+    inst = instance_from_dense(3, 2, 3, G, np.ones(3), np.ones(2), [-1] * 3, [1] * 3, [],
+                               [[2, 2]])
+    e, f = orc.scaling(inst, orc.default_settings(ruiz_iters=1, pock_chambolle=0))
+    assert e[1] == 1.0 and f[0] == 1.0 and f[2] == 1.0
+    assert e[0] == 0.5 and f[1] == 0.5          # one pass: 1/sqrt(4) each
+
+
+# ------------------------------------------------------------------ solve
+def _check_solution(inst, r, tol):
+    assert r["status"] == 0
+    assert max(r["err_p"], r["err_d"], r["err_gap"]) <= tol
+    assert r["pobj"] == pytest.approx(inst.opt, rel=10 * tol, abs=10 * tol)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_solve_recovers_planted_objective(orc, seed):
+    inst = I.small_mixed(seed)
+    r = orc.solve(inst)
+    _check_solution(inst, r, 1e-6)
+
+
+def test_solve_lp_soc_small_workload(orc):
+    inst = I.lp_soc_small(20250501)
+    r = orc.solve(inst)
+    _check_solution(inst, r, 1e-6)
+
+
+def test_solve_tight_tolerance(orc):
+    inst = I.small_mixed(1)
+    r = orc.solve(inst, orc.default_settings(tol=1e-9))
+    assert r["status"] == 0
+    assert r["pobj"] == pytest.approx(inst.opt, rel=1e-8, abs=1e-8)
+
+
+def _lp_vertex_enumeration(inst):
+    """min c^T x over {G x >= h, l <= x <= u}: best feasible vertex."""
+    A = inst.dense()
+    n = inst.n
+    rows = [(A[i], inst.h[i]) for i in range(inst.m)]
+    rows += [(np.eye(n)[j], inst.l[j]) for j in range(n)]
+    rows += [(-np.eye(n)[j], -inst.u[j]) for j in range(n)]
+    best = np.inf
+    for act in itertools.combinations(range(len(rows)), n):
+        M = np.array([rows[i][0] for i in act])
+        if abs(np.linalg.det(M)) < 1e-12:
+            continue
+        x = np.linalg.solve(M, np.array([rows[i][1] for i in act]))
+        if all(a @ x >= b - 1e-9 for a, b in rows):
+            best = min(best, inst.c @ x)
+    return best
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_solve_tiny_lp_vs_vertex_enumeration(orc, seed):
+    inst = I.tiny_lp(seed, n=3, m=3)
+    ref = _lp_vertex_enumeration(inst)
+    r = orc.solve(inst, orc.default_settings(tol=1e-9))
+    assert r["status"] == 0
+    assert r["pobj"] == pytest.approx(ref, rel=1e-7, abs=1e-7)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_solve_ball_socp_closed_form(orc, seed):
+    """min c^T x s.t. ||W (x - x0)|| <= r has x* = x0 - r W^-2 c / ||W^-1 c||."""
+    inst = I.ball_socp(seed)
+    W, x0, rad = inst.meta["W"], inst.meta["x0"], inst.meta["r"]
+    xs = x0 - rad * (inst.c / W ** 2) / np.linalg.norm(inst.c / W)
+    r = orc.solve(inst, orc.default_settings(tol=1e-9))
+    assert r["status"] == 0
+    assert np.allclose(r["x"], xs, atol=1e-6)
+    assert r["pobj"] == pytest.approx(inst.c @ xs, rel=1e-8, abs=1e-8)
+
+
+def test_solve_constant_beta_modes_converge(orc):
+    inst = I.small_mixed(3)
+    for beta in (0.0, 0.5, 1.0):
+        r = orc.solve(inst, orc.default_settings(beta_mode=1, beta_const=beta, max_iter=200000))
+        _check_solution(inst, r, 1e-6)
+
+
+def test_solve_status_codes(orc):
+    inst = I.small_mixed(0)
+    r = orc.solve(inst, orc.default_settings(max_iter=100))
+    assert r["status"] == 1 and r["iterations"] == 100
+    r = orc.solve(inst, orc.default_settings(max_iter=0))
+    assert r["status"] == 1 and r["iterations"] == 0
+    # warm start at the planted optimum terminates before the first iteration
+    r = orc.solve(inst, x0=inst.x_star, y0=inst.y_star)
+    assert r["status"] == 0 and r["iterations"] == 0
+    # a NaN in the data ends in NUMERICAL, not in a crash or a hang
+    bad = I.small_mixed(0)
+    bad.c = bad.c.copy()
+    bad.c[3] = np.nan
+    r = orc.solve(bad, orc.default_settings(max_iter=500))
+    assert r["status"] == 3
+
+
+def test_solve_decision_log_is_consistent(orc):
+    inst = I.small_mixed(5)
+    s = orc.default_settings(max_iter=400)
+    r = orc.solve(inst, s, log_cap=400, snap_iters=[1, 64, 65, 400])
+    lg = r["log"]
+    assert lg["attempts"].size == 400 and np.all(lg["attempts"] >= 1)
+    assert np.all((lg["beta"] >= 0) & (lg["beta"] <= 1)) and np.all(lg["eta_used"] > 0)
+    checks = np.nonzero(lg["check_code"])[0] + 1
+    # checks every 64 inner iterations (restarts only happen at checks) plus the
+    # forced check at the iteration limit
+    assert np.all(checks[:-1] % 64 == 0) and checks[-1] == 400
+    # first check after the start: k = N >= 0.36 N, so some restart rule fires
+    assert (lg["check_code"][63] - 1) // 2 % 4 != 0
+    # the snapshot at iteration 65 follows a restart, so it differs from 64's
+    assert not np.allclose(lg["snap_x"][1], lg["snap_x"][2])
