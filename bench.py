@@ -1,0 +1,199 @@
+"""Benchmark of the PDCS hot path on one MI355X.
+
+Workload: the large single instance (n = 1e6 variables, m = 5e5 rows,
+~1e7 nonzeros with power-law column degrees, rows scaled over 1e-3..1e3; 1e5
+box entries, 2e4 SOC blocks, 1e4 exponential-cone row blocks; planted optimum),
+generated from a fixed seed.  A step is one check period of Algorithm 1: 64
+accepted PDHG iterations (primal pass, SpMV G x^, dual pass, step decision,
+SpMV G^T y^, Halpern/average update) followed by the restart/termination check.
+The problem is on the device before the timed region starts.
+
+Prints one JSON line (see the repository's benchmark contract).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-1e-6 rel. KKT & PDHG iter/s (plain FP64 vs chosen form), HBM GB/s"
+SEED_LARGE = 20250502
+HBM_PEAK_GBS = 8000.0
+CHECK = 64
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def spmv_bytes(rows, cols, nnz):
+    """Algorithmic HBM bytes of one CSR product in FP64: values and column
+    indices once (12 B/nnz), row pointers, the output, and x read once."""
+    return 12 * nnz + 8 * (rows + 1) + 8 * rows + 8 * cols
+
+
+def iteration_bytes(n, m, nnz):
+    """Algorithmic bytes of one accepted iteration (FP64 path as built): two
+    CSR products plus the vector traffic of the fused passes (primal pass: read
+    x, G^T y, c, scale; write x^ -- dual pass: read y, G x^, G x, h, scale; write
+    y^ -- Halpern/average: read x^, x, x0, G^T y^, G^T y, G^T y0, sum, write x,
+    G^T y, sum, and the same on the row side)."""
+    primal = 8 * 5 * n
+    dual = 8 * 6 * m
+    halpern = 8 * 10 * (n + m)
+    return spmv_bytes(m, n, nnz) + spmv_bytes(n, m, nnz) + primal + dual + halpern
+
+
+def time_spmv(pdcs, prob, inst, torch, transpose, reps=50):
+    """Average duration of one SpMV launch sequence, HIP events on the stream
+    the library launches on."""
+    n, m = inst.n, inst.m
+    xin = torch.randn(m if transpose else n, dtype=torch.float64, device="cuda")
+    yout = torch.empty(n if transpose else m, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(5):
+        prob.spmv(xin, yout, transpose=transpose)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(reps):
+        prob.spmv(xin, yout, transpose=transpose)
+    end.record(stream)
+    end.synchronize()
+    return start.elapsed_time(end) / 1e3 / reps
+
+
+def cpu_baseline(inst, iters):
+    """The oracle as it stands, single thread, on the first `iters` iterations."""
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    oracle.solve(inst, oracle.default_settings(max_iter=0))
+    t1 = time.perf_counter()
+    r = oracle.solve(inst, oracle.default_settings(max_iter=iters))
+    t2 = time.perf_counter()
+    run = (t2 - t1) - (t1 - t0)
+    return {"value": r["iterations"] / run, "unit": "iter/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {iters} PDHG iterations (one check period) of the same instance, "
+                      f"setup excluded; {run:.1f} s on 1 host thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-time-to-tol", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=64)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--m", type=int, default=500_000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "design is described in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2505_00311_amd import instances
+    from paper_2505_00311_amd import pdcs
+
+    torch.cuda.set_device(0)
+    t = time.perf_counter()
+    inst = instances.large_mixed(SEED_LARGE, n=args.n, m=args.m)
+    log(f"generated n={inst.n} m={inst.m} nnz={inst.nnz} in {time.perf_counter() - t:.1f}s")
+    t = time.perf_counter()
+    prob = pdcs.Problem(inst)
+    torch.cuda.synchronize()
+    create_s = time.perf_counter() - t
+    log(f"problem created (upload, G^T, plans) in {create_s:.2f}s")
+
+    # warmup: W check periods (also computes and caches the rescaling)
+    prob.solve(pdcs.settings_default(max_iter=CHECK * max(args.warmup, 1)))
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    # timed: K check periods from a cold start
+    K = args.steps
+    s = pdcs.settings_default(max_iter=CHECK * K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = prob.solve(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    iters = r["iterations"]
+    ips = iters / r["solve_s"]
+    ms_per_step = wall / K * 1e3
+    log(f"timed {K} steps: {iters} iterations, {r['attempts']} attempts, solve {r['solve_s']:.3f}s "
+        f"(wall {wall:.3f}s, setup {r['setup_s']:.3f}s) -> {ips:.1f} iter/s")
+
+    bytes_iter = iteration_bytes(inst.n, inst.m, inst.nnz)
+    hbm_gbs = bytes_iter * ips / 1e9
+
+    # dominant kernel: the G^T product (power-law rows), timed live
+    t_gt = time_spmv(pdcs, prob, inst, torch, transpose=True)
+    t_g = time_spmv(pdcs, prob, inst, torch, transpose=False)
+    b_gt = spmv_bytes(inst.n, inst.m, inst.nnz)
+    b_g = spmv_bytes(inst.m, inst.n, inst.nnz)
+    ach = b_gt / t_gt / 1e9
+    log(f"SpMV G^T {t_gt * 1e6:.1f} us ({ach:.0f} GB/s), G {t_g * 1e6:.1f} us ({b_g / t_g / 1e9:.0f} GB/s)")
+
+    out = {
+        "metric": METRIC,
+        "value": round(ips, 2),
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"large_mixed n={inst.n} m={inst.m} nnz={inst.nnz} "
+                               f"(power-law columns, 1e5 box, 2e4 SOC, 1e4 exp row blocks, seed {SEED_LARGE})",
+                   "form": "plain FP64", "step": "64 PDHG iterations + restart/termination check"},
+        "hbm_model_gbs": round(hbm_gbs, 1),
+        "hbm_model_frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
+        "bytes_per_iteration_model": bytes_iter,
+        "roofline": {"bound": "hbm", "kernel": "spmv G^T (spmv_rows_kernel + chunked long rows)",
+                     "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "launch_us": round(t_gt * 1e6, 2), "bytes_per_launch": b_gt,
+                     "spmv_G_us": round(t_g * 1e6, 2),
+                     "spmv_G_gbs": round(b_g / t_g / 1e9, 1)},
+    }
+
+    if not args.no_time_to_tol:
+        t0 = time.perf_counter()
+        rt = prob.solve(pdcs.settings_default(time_limit=150.0))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out["time_to_tol"] = {
+            "tol": 1e-6, "status": pdcs.SOLVE_STATUS[rt["status"]], "solve_s": round(rt["solve_s"], 3),
+            "setup_s": round(rt["setup_s"], 3), "wall_s": round(wall, 3),
+            "iterations": rt["iterations"], "restarts": rt["restarts"], "spmv": rt["spmv"],
+            "err_p": rt["err_p"], "err_d": rt["err_d"], "err_gap": rt["err_gap"],
+            "objective": rt["pobj"], "planted_objective": inst.opt,
+            "objective_rel_err": abs(rt["pobj"] - inst.opt) / max(1.0, abs(inst.opt))}
+        log(f"time to 1e-6: {rt['solve_s']:.2f}s, {rt['iterations']} iterations, status "
+            f"{pdcs.SOLVE_STATUS[rt['status']]}")
+
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_iters)
+        log(f"oracle: {out['cpu_baseline']['value']:.3f} iter/s")
+
+    prob.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

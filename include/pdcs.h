@@ -1,0 +1,210 @@
+/*
+ * pdcs.h -- C ABI of the MI355X (gfx950) PDCS hot path.
+ *
+ * PDCS (Lin, Xiong, Ge, Ye, "A Practical GPU-Enhanced Matrix-Free
+ * Primal-Dual Method for Large-Scale Conic Programs") solves the conic
+ * program of Section 2, eq. (1):
+ *
+ *     min <c, x>  s.t.  G x - h in K_d^*,  l <= x_1 <= u,  x_2 in K_p,
+ *
+ * with x = (x_1, x_2), x_1 the first n_box entries of x, by Algorithm 1 of
+ * Section 3 (adaptive-step PDHG, adaptive reflected Halpern iteration,
+ * weighted averaging, restarts, primal weight) on the diagonally rescaled
+ * problem of Section 3.  Every step of the iteration runs in this library's
+ * HIP kernels on one GPU.
+ *
+ * Conventions shared by all calls
+ *   - Every call returns a pdcs_status; 0 is success, negative values are
+ *     errors and pdcs_last_error() then holds a message (thread-local).  No
+ *     C++ exception crosses this boundary.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory of the current device (for example torch tensor
+ *     data_ptr()).  All arrays are dense, contiguous, row-major.
+ *   - hip_stream is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it; calls that return results to the host
+ *     synchronise it.
+ *   - Handles are owned by the library and released by the matching
+ *     *_destroy call.  A handle is used by one host thread at a time.
+ */
+#ifndef PDCS_H
+#define PDCS_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PDCS_OK = 0,
+    PDCS_ERR_INVALID_ARG = -1,   /* null pointer, negative size, bad enum, bad CSR     */
+    PDCS_ERR_DIMENSION = -2,     /* cone dimensions do not add up to n - n_box or m    */
+    PDCS_ERR_NONFINITE = -3,     /* NaN/inf in G, c or h (l, u may hold +-inf)         */
+    PDCS_ERR_OOM = -4,           /* device allocation failed                           */
+    PDCS_ERR_HIP = -5,           /* a HIP runtime call failed                          */
+    PDCS_ERR_NOT_SUPPORTED = -6  /* valid request outside what this build implements   */
+} pdcs_status;
+
+/* Disciplined cones of Section 1.2.  A block of dimension d.
+ *   SOC: (t, x) with ||x|| <= t, t first.  EXP, EXP_DUAL: d = 3, entries in the
+ *   (r, s, t) order of Appendix A.2.
+ * For x_2 a block of type T requires x_block in T.  For the rows a block of
+ * type T requires (G x - h)_block in T, i.e. it describes K_d^* and the dual
+ * variable y_block lies in T^* (ZERO <-> FREE, EXP <-> EXP_DUAL, NONNEG and SOC
+ * self-dual). */
+enum {
+    PDCS_CONE_ZERO = 0,
+    PDCS_CONE_FREE = 1,
+    PDCS_CONE_NONNEG = 2,
+    PDCS_CONE_SOC = 3,
+    PDCS_CONE_EXP = 4,
+    PDCS_CONE_EXP_DUAL = 5
+};
+
+/* Outcome of a solve (distinct from the call's pdcs_status). */
+enum {
+    PDCS_SOLVE_OPTIMAL = 0,     /* max(err_p, err_d, err_gap) <= tol                   */
+    PDCS_SOLVE_ITER_LIMIT = 1,  /* max_iter accepted iterations reached                */
+    PDCS_SOLVE_TIME_LIMIT = 2,  /* time_limit seconds reached (checked at checks)      */
+    PDCS_SOLVE_NUMERICAL = 3    /* a non-finite step-size or KKT quantity was detected */
+};
+
+/* Problem data of eq. (1), CSR for G (rows sorted or not; duplicates are not
+ * merged).  nnz must be below 2^31.  In pdcs_problem_create every pointer is
+ * host memory; in pdcs_problem_create_device the bulk arrays (row_ptr, col,
+ * val, c, h, l, u) are device memory and the cone lists stay on the host.
+ * The caller keeps ownership; the library copies what it needs. */
+typedef struct {
+    int64_t n, m, nnz, n_box;
+    const int64_t *row_ptr;   /* [m+1], row_ptr[0] = 0, row_ptr[m] = nnz          */
+    const int32_t *col;       /* [nnz], 0 <= col < n                              */
+    const double *val;        /* [nnz]                                            */
+    const double *c;          /* [n]                                              */
+    const double *h;          /* [m]                                              */
+    const double *l, *u;      /* [n_box], -INFINITY / +INFINITY allowed           */
+    int64_t n_xcones;         /* blocks partitioning x_2 (entries n_box .. n-1)   */
+    const int32_t *xcone_type;
+    const int64_t *xcone_dim;
+    int64_t n_rcones;         /* blocks partitioning the m rows                   */
+    const int32_t *rcone_type;
+    const int64_t *rcone_dim;
+} pdcs_problem_desc;
+
+/* Algorithm 1 parameters.  The paper defers the step-size, reflection,
+ * restart, primal-weight and rescaling rules to its companion technical note;
+ * the fields below are the constants of the rules this library implements. */
+typedef struct {
+    double tol;                 /* termination on max(err_p, err_d, err_gap), Section 5  */
+    int64_t max_iter;           /* accepted PDHG iterations                              */
+    double time_limit;          /* seconds, <= 0 = none                                   */
+    int32_t check_every;        /* restart/termination check period (inner iterations)   */
+    int32_t ruiz_iters;         /* Ruiz infinity-norm passes of the rescaling            */
+    int32_t pock_chambolle;     /* 1: one Pock-Chambolle (alpha = 1) pass after Ruiz     */
+    int32_t beta_mode;          /* 0: adaptive reflection parameter, 1: constant         */
+    double beta_const;
+    double beta_grow, beta_shrink;
+    double step_reduce_exp, step_grow_exp;
+    double restart_sufficient, restart_necessary, restart_artificial;
+    int32_t max_attempts;       /* line-search attempts per iteration before NUMERICAL   */
+    int32_t out_on_device;      /* 1: x_out / y_out of pdcs_solve are device pointers    */
+} pdcs_settings;
+
+typedef struct {
+    int32_t status;             /* PDCS_SOLVE_*                                          */
+    int64_t iterations;         /* accepted PDHG iterations                              */
+    int64_t attempts;           /* step-size attempts (>= iterations)                    */
+    int64_t restarts;
+    int64_t spmv;               /* sparse products with G or G^T issued                  */
+    double pobj, dobj;          /* objectives of eq. (1) / eq. (2) at the output         */
+    double err_p, err_d, err_gap;
+    double omega, eta;          /* final primal weight and step size                     */
+    double setup_s;             /* rescaling and initialisation, seconds                 */
+    double solve_s;             /* iterations and checks, seconds                        */
+} pdcs_info;
+
+/* Optional decision log and iterate snapshots of pdcs_solve, host memory.
+ * Record k (0-based) describes accepted iteration k+1.  check_code is 0 when
+ * no check followed the iteration, else 1 + chosen + 2*reason + 8*stop, with
+ * chosen 0 = current iterate, 1 = average; reason 0 = no restart, 1 =
+ * sufficient decay, 2 = necessary decay and growth, 3 = artificial.  Snapshot
+ * i holds the unscaled current iterate after accepted iteration snap_iter[i]
+ * (ascending).  Asking for a log or snapshots makes the solve synchronise
+ * after every step attempt. */
+typedef struct {
+    int64_t cap;
+    int64_t count;              /* out */
+    int32_t *attempts;
+    double *eta_used;
+    double *beta;
+    double *omega;
+    int32_t *check_code;
+    double *check_kkt;
+    int64_t n_snap;
+    const int64_t *snap_iter;
+    double *snap_x;             /* [n_snap * n] */
+    double *snap_y;             /* [n_snap * m] */
+} pdcs_trace;
+
+typedef struct pdcs_problem pdcs_problem;
+
+/* Fills the default parameters (tol 1e-6, check every 64, 10 Ruiz passes and a
+ * Pock-Chambolle pass, adaptive reflection, PDLP-style step/restart/weight
+ * constants).  Errors: INVALID_ARG on NULL. */
+pdcs_status pdcs_settings_default(pdcs_settings *s);
+
+/* Validates the problem of eq. (1), copies it to the device, builds the CSR
+ * of G^T and the cone dispatch plans (the thread-, wavefront- and
+ * workgroup-level projection strategies of Section 4, Table 3).
+ * Errors: INVALID_ARG, DIMENSION, NONFINITE, OOM, HIP.  On error *out = NULL. */
+pdcs_status pdcs_problem_create(const pdcs_problem_desc *desc, void *hip_stream,
+                                pdcs_problem **out);
+
+/* As pdcs_problem_create, with the bulk arrays in device memory (see
+ * pdcs_problem_desc).  They are copied, so the caller may free them after the
+ * call returns. */
+pdcs_status pdcs_problem_create_device(const pdcs_problem_desc *desc, void *hip_stream,
+                                       pdcs_problem **out);
+
+void pdcs_problem_destroy(pdcs_problem *p);
+
+/* Algorithm 1 (Section 3) with diagonal rescaling, run to the tolerance of
+ * Section 5, eq. (PDCS_terminate_tolerance).  x0 [n] / y0 [m] (host, nullable:
+ * cold start from zero) are an unscaled starting point; omega0 <= 0 selects
+ * the default primal weight.  x_out [n] and y_out [m] receive the unscaled
+ * solution (host memory unless settings->out_on_device).  info and trace are
+ * nullable.  Errors: INVALID_ARG, OOM, HIP; the solve outcome is info->status. */
+pdcs_status pdcs_solve(pdcs_problem *p, const pdcs_settings *settings, const double *x0,
+                       const double *y0, double omega0, double *x_out, double *y_out,
+                       pdcs_info *info, pdcs_trace *trace);
+
+/* Rescaling factors of Section 3 that pdcs_solve uses with these settings:
+ * e_out [m] (rows, E) and f_out [n] (columns, F), host memory, G~ = E G F. */
+pdcs_status pdcs_scaling(pdcs_problem *p, const pdcs_settings *settings, double *e_out,
+                         double *f_out);
+
+/* Sparse product with the unscaled G (transpose = 0: y_dev[m] = G x_dev[n]) or
+ * G^T (transpose = 1: y_dev[n] = G^T x_dev[m]); device pointers, enqueued on
+ * hip_stream.  The products SpMV G x and G^T y of eq. (5). */
+pdcs_status pdcs_spmv(pdcs_problem *p, int transpose, const double *x_dev, double *y_dev,
+                      void *hip_stream);
+
+/* Termination measures of eq. (PDCS_terminate_tolerance) at the unscaled
+ * point (x_dev [n], y_dev [m], device memory).  out[5] (host) receives
+ * err_p, err_d, err_gap, primal objective, dual objective. */
+pdcs_status pdcs_kkt(pdcs_problem *p, const double *x_dev, const double *y_dev, double *out);
+
+/* Projection of v_dev (device, length sum(dims)) in place onto the product of
+ * diagonally rescaled cones D K_1 x ... x D K_nblocks (eq. (6); Theorem 1 for
+ * SOC, Theorem 3 for EXP, the Appendix A.2 remark for EXP_DUAL).  types and
+ * dims are host arrays; d_dev (device, nullable = identity) is the diagonal of
+ * D.  dual != 0 projects onto the product of the dual cones instead.
+ * Errors: INVALID_ARG, DIMENSION, HIP. */
+pdcs_status pdcs_project(int64_t nblocks, const int32_t *types, const int64_t *dims, int dual,
+                         const double *d_dev, double *v_dev, void *hip_stream);
+
+const char *pdcs_status_string(pdcs_status s);
+const char *pdcs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

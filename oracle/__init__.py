@@ -89,6 +89,8 @@ def _lib():
         L.orc_proj_exp_dual.argtypes = [_pd, _pd, _pd]
         L.orc_proj_blocks.argtypes = [_i64, _pi32, _pi64, ctypes.c_int, _pd, _pd]
         L.orc_proj_blocks.restype = None
+        L.orc_spmv.argtypes = [_i64, _pi64, _pi32, _pd, _pd, _pd]
+        L.orc_spmv.restype = None
         L.orc_scaling.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(Settings), _pd, _pd]
         L.orc_kkt.argtypes = [ctypes.POINTER(_Problem), _pd, _pd, _pd, _pd, _pd, _pd, _pd]
         L.orc_onepdhg.argtypes = [ctypes.POINTER(_Problem), _pd, _pd, _dbl, _dbl, _pd, _pd]
@@ -187,6 +189,18 @@ def proj_blocks(types, dims, v, d=None, dual=False):
     _lib().orc_proj_blocks(t.size, _ptr(t, ctypes.c_int32), _ptr(k, ctypes.c_int64),
                            1 if dual else 0, _ptr(dd, ctypes.c_double), _ptr(out, ctypes.c_double))
     return out
+
+
+def spmv(row_ptr, col, val, x):
+    """y = A x for a CSR matrix (plain definition)."""
+    rp = np.ascontiguousarray(row_ptr, np.int64)
+    ci = np.ascontiguousarray(col, np.int32)
+    v = np.ascontiguousarray(val, np.float64)
+    xx = np.ascontiguousarray(x, np.float64)
+    y = np.empty(rp.size - 1)
+    _lib().orc_spmv(rp.size - 1, _ptr(rp, ctypes.c_int64), _ptr(ci, ctypes.c_int32),
+                    _ptr(v, ctypes.c_double), _ptr(xx, ctypes.c_double), _ptr(y, ctypes.c_double))
+    return y
 
 
 # ---------------------------------------------------------------- problem-level

@@ -353,6 +353,11 @@ static void transpose(int64_t m, int64_t n, const int64_t *rp, const int32_t *ci
     free(next);
 }
 
+void orc_spmv(int64_t rows, const int64_t *rp, const int32_t *ci, const double *v, const double *x,
+              double *y) {
+    spmv(rows, rp, ci, v, x, y);
+}
+
 static double dot(int64_t n, const double *a, const double *b) {
     double s = 0.0;
     for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];

@@ -108,6 +108,10 @@ int orc_proj_exp_dual(const double *v, const double *d, double *out);
 void orc_proj_blocks(int64_t nblk, const int32_t *type, const int64_t *dim, int dual,
                      const double *d, double *v);
 
+/* y = A x for a CSR matrix (plain definition). */
+void orc_spmv(int64_t rows, const int64_t *rp, const int32_t *ci, const double *v, const double *x,
+              double *y);
+
 /* Diagonal rescaling E (rows, [m]) and F (columns, [n]). */
 int orc_scaling(const orc_problem *p, const orc_settings *s, double *e, double *f);
 

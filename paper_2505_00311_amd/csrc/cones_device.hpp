@@ -1,0 +1,265 @@
+// cones_device.hpp -- projections onto diagonally rescaled cones on gfx950.
+//
+//   exponential cone  : Section 3 Theorem 2 / Appendix A.2 Theorem 3, one thread
+//                       per cone (the thread-wise strategy of Section 4, Table 3);
+//   dual exponential  : Appendix A.2 Remark, Proj_{DK*}(v) = v + Proj_{D^-1 K}(-v);
+//   second-order cone : Section 3 Theorem 1, one wavefront per block (dims up
+//                       to 256, values in VGPRs) or one workgroup per block.
+//
+// The fourth case of Theorem 1 is solved in s = t / (1 - 2 lambda) on the
+// bracket (max(t,0), ||(t,x)||], where g(s) = sum_i (x_i dh_i)^2 / (dh_i^2 + a)^2
+// - s^2 with a = 1 - t/s is positive left of the root and negative right of it;
+// a Newton step safeguarded by bisection converges in a handful of reductions.
+#pragma once
+#include "device_common.hpp"
+
+namespace pdcs {
+
+constexpr double kEps = 2.220446049250313e-16;
+constexpr double kE = 2.718281828459045;
+
+// ------------------------------------------------------------- exponential
+__device__ __forceinline__ bool in_kexp(double r, double s, double t) {
+    if (s > 0.0) return t >= s * exp(r / s);
+    return s == 0.0 && t >= 0.0 && r <= 0.0;
+}
+
+__device__ __forceinline__ bool in_kexp_dual(double r, double s, double t) {
+    if (r < 0.0) return kE * t >= -r * exp(s / r);
+    return r == 0.0 && s >= 0.0 && t >= 0.0;
+}
+
+struct ExpPt {
+    double r0, s0, t0, dr, ds, dt, tau;
+};
+
+// s_p(rho), r_d(rho) of eq. (sp_rd) with tau = ds / dr.
+__device__ __forceinline__ void exp_sprd(const ExpPt &c, double rho, double &sp, double &rd) {
+    const double den = rho * rho - rho + c.tau * c.tau;
+    sp = (c.s0 * c.tau - c.r0 + c.r0 * rho) / (c.dr * den);
+    rd = c.ds * (c.tau * c.r0 - rho * c.s0) / den;
+}
+
+// e^{-|rho|} h(rho) of eq. (h_rho) and its derivative: same sign and roots as
+// h, no overflow for any rho.
+__device__ __forceinline__ void exp_hs(const ExpPt &c, double rho, double &f, double &df) {
+    const double den = rho * rho - rho + c.tau * c.tau;
+    const double ns = c.s0 * c.tau - c.r0 + c.r0 * rho;
+    const double nr = c.tau * c.r0 - rho * c.s0;
+    const double sp = ns / (c.dr * den);
+    const double rd = c.ds * nr / den;
+    const double dsp = (c.r0 * den - ns * (2.0 * rho - 1.0)) / (c.dr * den * den);
+    const double drd = c.ds * (-c.s0 * den - nr * (2.0 * rho - 1.0)) / (den * den);
+    if (rho >= 0.0) {
+        const double em = exp(-rho);
+        f = c.dt * sp - em * em * rd / c.dt - c.t0 * em;
+        df = c.dt * dsp + em * em * (2.0 * rd - drd) / c.dt + c.t0 * em;
+    } else {
+        const double ep = exp(rho);
+        f = c.dt * ep * ep * sp - rd / c.dt - c.t0 * ep;
+        df = c.dt * ep * ep * (2.0 * sp + dsp) - drd / c.dt - c.t0 * ep;
+    }
+}
+
+__device__ __forceinline__ double exp_hs_value(const ExpPt &c, double rho) {
+    double f, df;
+    exp_hs(c, rho, f, df);
+    return f;
+}
+
+// Newton's method on the sign bracket [xneg, xpos], with a bisection step
+// whenever Newton would leave the bracket, would not halve the step, or meets
+// a non-finite value; stops at a step of 4 ulp of max(1, |rho|).
+__device__ double exp_root(const ExpPt &c, double xneg, double xpos) {
+    double rho = 0.5 * (xneg + xpos);
+    double dxold = fabs(xpos - xneg), dx = dxold;
+    double f, df;
+    exp_hs(c, rho, f, df);
+    for (int it = 0; it < 200; ++it) {
+        if (f == 0.0) return rho;
+        if (f < 0.0)
+            xneg = rho;
+        else
+            xpos = rho;
+        const bool finite = isfinite(f) && isfinite(df) && df != 0.0;
+        const bool out = !finite || ((rho - xpos) * df - f) * ((rho - xneg) * df - f) > 0.0;
+        const bool slow = !finite || fabs(2.0 * f) > fabs(dxold * df);
+        dxold = dx;
+        if (out || slow) {
+            dx = 0.5 * (xpos - xneg);
+            rho = xneg + dx;
+        } else {
+            dx = f / df;
+            rho -= dx;
+        }
+        if (fabs(dx) <= 4.0 * kEps * fmax(1.0, fabs(rho))) return rho;
+        exp_hs(c, rho, f, df);
+    }
+    return rho;
+}
+
+// Projection of (r0, s0, t0) onto diag(dr, ds, dt) K_exp.
+__device__ void exp_project(double r0, double s0, double t0, double dr, double ds, double dt,
+                            double &pr, double &ps, double &pt) {
+    if (in_kexp(r0 / dr, s0 / ds, t0 / dt)) {              // case 1
+        pr = r0, ps = s0, pt = t0;
+        return;
+    }
+    if (in_kexp_dual(-dr * r0, -ds * s0, -dt * t0)) {      // case 2 (polar)
+        pr = ps = pt = 0.0;
+        return;
+    }
+    if (r0 <= 0.0 && s0 <= 0.0) {                         // case 3
+        pr = r0, ps = 0.0, pt = t0 > 0.0 ? t0 : 0.0;
+        return;
+    }
+    const ExpPt c{r0, s0, t0, dr, ds, dt, ds / dr};       // case 4
+    double xneg, xpos;
+    if (r0 > 0.0 && s0 > 0.0) {
+        xpos = r0 * ds / (s0 * dr);
+        xneg = 1.0 - s0 * ds / (r0 * dr);
+    } else if (s0 > 0.0) {
+        xpos = r0 * ds / (s0 * dr);
+        double step = 1.0;
+        xneg = xpos - step;
+        for (int j = 0; j < 1100 && !(exp_hs_value(c, xneg) < 0.0); ++j) {
+            step *= 2.0;
+            xneg = xpos - step;
+        }
+    } else {
+        xneg = 1.0 - s0 * ds / (r0 * dr);
+        double step = 1.0;
+        xpos = xneg + step;
+        for (int j = 0; j < 1100 && !(exp_hs_value(c, xpos) > 0.0); ++j) {
+            step *= 2.0;
+            xpos = xneg + step;
+        }
+    }
+    const double rho = exp_root(c, xneg, xpos);
+    double sp, rd;
+    exp_sprd(c, rho, sp, rd);
+    // v_p = s_p (dr rho, ds, dt e^rho); for rho > 0 t_p and s_p come from the
+    // t equation at the root, where e^rho would amplify s_p's rounding.
+    double tp;
+    if (rho > 0.0) {
+        const double em = exp(-rho);
+        tp = t0 + em * rd / dt;
+        if (tp < 0.0) tp = 0.0;
+        sp = em * tp / dt;
+    } else {
+        tp = dt * exp(rho) * sp;
+    }
+    pr = dr * rho * sp;
+    ps = ds * sp;
+    pt = tp;
+}
+
+__device__ __forceinline__ void exp_dual_project(double r0, double s0, double t0, double dr,
+                                                 double ds, double dt, double &pr, double &ps,
+                                                 double &pt) {
+    double qr, qs, qt;
+    exp_project(-r0, -s0, -t0, 1.0 / dr, 1.0 / ds, 1.0 / dt, qr, qs, qt);
+    pr = r0 + qr, ps = s0 + qs, pt = t0 + qt;
+}
+
+// ------------------------------------------------------- second-order cone
+// One block per wavefront; lane l holds entries l + 64 r, r < kSocRegs; entry
+// 0 (t) is in lane 0.  Inactive slots carry v = 0, d = 1.
+__device__ void soc_project_wave(int dim, const double (&v)[kSocRegs],
+                                 const double (&d)[kSocRegs], double (&p)[kSocRegs]) {
+    const int lane = threadIdx.x % kWave;
+    const double t = __shfl(v[0], 0, kWave);
+    const double d0 = __shfl(d[0], 0, kWave);
+    double x[kSocRegs], dh[kSocRegs];
+    double snd = 0.0, sndi = 0.0, snx = 0.0;
+#pragma unroll
+    for (int r = 0; r < kSocRegs; ++r) {
+        const int e = lane + kWave * r;
+        const bool on = e >= 1 && e < dim;
+        x[r] = on ? v[r] : 0.0;
+        dh[r] = on ? d[r] / d0 : 1.0;
+        snd += (dh[r] * x[r]) * (dh[r] * x[r]);
+        sndi += (x[r] / dh[r]) * (x[r] / dh[r]);
+        snx += x[r] * x[r];
+    }
+    const double nd = sqrt(wave_sum(snd));
+    const double ndi = sqrt(wave_sum(sndi));
+    const double nx2 = wave_sum(snx);
+    if (t <= 0.0 && nd <= -t) {                           // case 1: polar -> 0
+#pragma unroll
+        for (int r = 0; r < kSocRegs; ++r) p[r] = 0.0;
+        return;
+    }
+    if (ndi <= t) {                                       // case 2: inside
+#pragma unroll
+        for (int r = 0; r < kSocRegs; ++r) p[r] = v[r];
+        return;
+    }
+    if (t == 0.0) {                                       // case 3: lambda = 1/2
+        double s2 = 0.0;
+#pragma unroll
+        for (int r = 0; r < kSocRegs; ++r) {
+            const double q = x[r] / (dh[r] + 1.0 / dh[r]);
+            s2 += q * q;
+            p[r] = x[r] / (1.0 + 1.0 / (dh[r] * dh[r]));
+        }
+        s2 = sqrt(wave_sum(s2));
+        if (lane == 0) p[0] = s2;
+        return;
+    }
+    // case 4: root of g(s) on (max(t,0), ||(t,x)||]
+    double w[kSocRegs], h2[kSocRegs];
+#pragma unroll
+    for (int r = 0; r < kSocRegs; ++r) {
+        w[r] = (x[r] * dh[r]) * (x[r] * dh[r]);
+        h2[r] = dh[r] * dh[r];
+    }
+    const double lo = t > 0.0 ? t : 0.0, hi = sqrt(t * t + nx2);
+    double xpos = lo, xneg = hi;                          // g > 0 at lo, g <= 0 at hi
+    double s = 0.5 * (t + sqrt(nx2));
+    if (!(s > lo && s < hi)) s = 0.5 * (lo + hi);
+    double dxold = hi - lo, dx = dxold;
+    auto eval = [&](double ss, double &f, double &df) {
+        const double a = 1.0 - t / ss;
+        double g1 = 0.0, g2 = 0.0;
+#pragma unroll
+        for (int r = 0; r < kSocRegs; ++r) {
+            const double iq = 1.0 / (h2[r] + a);
+            const double u = w[r] * iq * iq;
+            g1 += u;
+            g2 += u * iq;
+        }
+        g1 = wave_sum(g1);
+        g2 = wave_sum(g2);
+        f = g1 - ss * ss;
+        df = -2.0 * (t / (ss * ss)) * g2 - 2.0 * ss;
+    };
+    double f, df;
+    eval(s, f, df);
+    for (int it = 0; it < 100; ++it) {
+        if (f == 0.0) break;
+        if (f > 0.0)
+            xpos = s;
+        else
+            xneg = s;
+        const bool finite = isfinite(f) && isfinite(df) && df != 0.0;
+        const bool out = !finite || ((s - xpos) * df - f) * ((s - xneg) * df - f) > 0.0;
+        const bool slow = !finite || fabs(2.0 * f) > fabs(dxold * df);
+        dxold = dx;
+        if (out || slow) {
+            dx = 0.5 * (xneg - xpos);
+            s = xpos + dx;
+        } else {
+            dx = f / df;
+            s -= dx;
+        }
+        if (fabs(dx) <= 4.0 * kEps * s) break;
+        eval(s, f, df);
+    }
+    const double a = 1.0 - t / s;
+#pragma unroll
+    for (int r = 0; r < kSocRegs; ++r) p[r] = x[r] / (1.0 + a / h2[r]);
+    if (lane == 0) p[0] = s;
+}
+
+}  // namespace pdcs

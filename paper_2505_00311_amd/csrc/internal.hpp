@@ -1,0 +1,201 @@
+// internal.hpp -- declarations shared by the HIP translation units of libpdcs.
+//
+// Layout in HBM (one problem, FP64):
+//   G   : CSR, int64 row_ptr[m+1], int32 col[nnz], double val[nnz] (+ scaled copy)
+//   G^T : CSR of the transpose built on the device (same layout, n rows)
+//   x-side vectors [n] and y-side vectors [m], structure of arrays, contiguous
+//   cone plans: tile lists that route each workgroup to one class of work
+//   (elementwise entries, wavefront-per-SOC, workgroup-per-SOC, thread-per-exp).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+namespace pdcs {
+
+constexpr int kBlock = 256;          // threads per workgroup of every pass kernel
+constexpr int kWave = 64;            // CDNA wavefront
+constexpr int kSocWaveMax = 256;     // SOC blocks up to this dim: one wavefront each
+constexpr int kSocRegs = kSocWaveMax / kWave;
+constexpr int kElemPerTile = 2048;   // entries per elementwise tile
+constexpr int kExpPerTile = kBlock;  // exponential cones per tile (one thread each)
+constexpr int kPartials = 6;         // per-tile partial slots: 3 sums, 3 maxima
+
+// cone type codes of the C ABI
+enum ConeType : int32_t { kZero = 0, kFree = 1, kNonneg = 2, kSoc = 3, kExp = 4, kExpDual = 5 };
+
+// tile kinds of a cone plan
+enum TileKind : int32_t {
+    kTileBox = 0,
+    kTileZero = 1,
+    kTileFree = 2,
+    kTileNonneg = 3,
+    kTileSocWave = 4,
+    kTileSocBlock = 5,
+    kTileExp = 6,
+    kTileExpDual = 7
+};
+
+struct Tile {
+    int32_t kind;
+    int32_t count;   // entries (elementwise), blocks (SOC wave, exp) or 1 (SOC block)
+    int64_t start;   // first entry (elementwise) or first block index
+};
+
+// Device view of a cone plan for one side (x or y).
+struct ConePlan {
+    int64_t ntiles = 0;
+    Tile *tiles = nullptr;
+    int64_t *soc_off = nullptr;   // global entry offset of each SOC block
+    int32_t *soc_dim = nullptr;
+    int64_t *exp_off = nullptr;   // global entry offset of each exp block
+};
+
+struct Csr {
+    int64_t rows = 0, cols = 0, nnz = 0;
+    int64_t *rp = nullptr;
+    int32_t *ci = nullptr;
+    double *v = nullptr;
+};
+
+// Launch plan of one sparse product: short rows take `lanes` lanes each; rows
+// longer than long_thr are cut into chunks of kLongChunk entries, one
+// workgroup per chunk, and summed per row in chunk order.
+constexpr int64_t kLongChunk = 4096;
+struct SpmvPlan {
+    int lanes = 8;
+    int64_t long_thr = 0;
+    int64_t n_long = 0;
+    int64_t n_chunks = 0;
+    int32_t *long_rows = nullptr;      // [n_long]
+    int64_t *long_chunk_ptr = nullptr; // [n_long+1]
+    int32_t *chunk_row = nullptr;      // [n_chunks] long-row index
+    int64_t *chunk_begin = nullptr;    // [n_chunks] first nnz
+    double *chunk_part = nullptr;      // [n_chunks]
+};
+
+// Iteration state kept on the device, read and written by the step kernels.
+struct DevState {
+    double eta, omega, tau, sigma;
+    double beta_prev, r_prev;
+    double eta_used, beta, ha, hb;    // last accepted step: Halpern weights (k+1)/(k+2), 1/(k+2)
+    double eta_sum;                   // sum of eta_used since the restart
+    double nx2, ny2, ip;              // reductions of the last attempt
+    long long n_iter, kin, attempts_total, max_iter;
+    int attempts_cur, halt, skip_update, status;
+    int check_every, max_attempts, beta_mode, pad0;
+    double beta_const, beta_grow, beta_shrink, step_reduce_exp, step_grow_exp;
+    long long log_cap;
+    int *log_attempts;
+    double *log_eta, *log_beta, *log_omega;
+};
+
+// Per-candidate raw KKT reductions (unscaled quantities), see kkt kernels.
+struct KktRaw {
+    double rows_sum[3];   // y.h, ||y - y_anchor||^2 (scaled), unused
+    double rows_max[3];   // max|r - P(r)|, max|Gx|, max|P(r)|
+    double cols_sum[3];   // c.x, l.lam+ - u.lam-, ||x - x_anchor||^2 (scaled)
+    double cols_max[3];   // max dist(lambda), max|G^T y|, unused
+};
+
+// ------------------------------------------------------------------ errors
+struct HipError {
+    hipError_t code;
+    std::string where;
+};
+[[noreturn]] void throw_hip(hipError_t e, const char *what, const char *file, int line);
+#define PDCS_HIP(call)                                                   \
+    do {                                                                 \
+        hipError_t _e = (call);                                          \
+        if (_e != hipSuccess) ::pdcs::throw_hip(_e, #call, __FILE__, __LINE__); \
+    } while (0)
+
+// ------------------------------------------------------------ launch wrappers
+// spmv.hip
+void spmv(const Csr &A, const SpmvPlan &plan, const double *x, double *y, const int *skip,
+          hipStream_t s);
+int choose_lanes(double avg_row_nnz);
+
+// setup.hip
+void transpose_csr(const Csr &A, Csr &At, hipStream_t s);   // At arrays preallocated
+void fill(double *p, int64_t n, double v, hipStream_t s);
+void rows_absmax_scaled(const Csr &A, const double *er, const double *ec, bool row_first,
+                        double *out, hipStream_t s);
+void rows_abssum_scaled(const Csr &A, const double *er, const double *ec, bool row_first,
+                        double *out, hipStream_t s);
+void divide_by_sqrt(double *e, const double *r, int64_t n, hipStream_t s);
+void scale_values(const Csr &A, const double *er, const double *ec, bool row_first, double *out,
+                  hipStream_t s);
+void scale_problem_vectors(int64_t n, int64_t m, int64_t n_box, const double *c,
+                           const double *h, const double *l, const double *u, const double *e,
+                           const double *f, double *cs, double *hs, double *ls, double *us,
+                           double *dx, double *dy, hipStream_t s);
+// out[0] += sum(a*a) style helpers: single-pass deterministic reductions
+void reduce_absmax(const double *a, int64_t n, double *out, hipStream_t s);
+void reduce_sumsq(const double *a, int64_t n, double *out, hipStream_t s);
+void check_finite(const double *a, int64_t n, int *flag, hipStream_t s);
+void div_vec(const double *a, const double *b, double *out, int64_t n, hipStream_t s);
+void mul_vec(const double *a, const double *b, double *out, int64_t n, hipStream_t s);
+void copy_vec(const double *a, double *out, int64_t n, hipStream_t s);
+
+// cone_pass.hip
+struct PrimalArgs {
+    const double *x, *aty, *cs, *ls, *us, *dx;
+    double *xh;
+    const DevState *st;
+};
+struct DualArgs {
+    const double *y, *gxh, *gx, *hs, *dy;
+    double *yh;
+    const DevState *st;
+};
+struct CandArgs {  // projection of src / div onto the scaled set, into dst
+    const double *src, *ls, *us, *d;
+    const DevState *st;   // div = st->eta_sum when use_avg
+    int use_avg;
+    double *dst;
+};
+struct KktRowsArgs {
+    const double *gxc, *h, *e, *yc, *ya;
+    double *tmp;
+};
+struct KktColsArgs {
+    const double *atyc, *c, *f, *l, *u, *xc, *xa;
+    double *tmp;
+};
+struct ProjArgs {
+    double *v;
+    const double *d;
+};
+void pass_primal(const ConePlan &p, const PrimalArgs &a, double *partials, hipStream_t s);
+void pass_dual(const ConePlan &p, const DualArgs &a, double *partials, hipStream_t s);
+void pass_candidate(const ConePlan &p, bool y_side, const CandArgs &a, double *partials,
+                    hipStream_t s);
+void pass_kkt_rows(const ConePlan &p, const KktRowsArgs &a, double *partials, hipStream_t s);
+void pass_kkt_cols(const ConePlan &p, const KktColsArgs &a, double *partials, hipStream_t s);
+void pass_project(const ConePlan &p, bool dual, const ProjArgs &a, double *partials,
+                  hipStream_t s);
+
+// iterate.hip
+void decide(DevState *st, const double *px, int64_t ntx, const double *py, int64_t nty,
+            hipStream_t s);
+struct HalpernArgs {
+    double *x, *aty, *xsum;
+    const double *xh, *atyh, *xa, *aty0;
+    double *y, *gx, *ysum;
+    const double *yh, *gxh, *ya, *gx0;
+    int64_t n, m;
+    const DevState *st;
+};
+void halpern(const HalpernArgs &a, hipStream_t s);
+void reduce_kkt(const double *prow, int64_t ntr, const double *pcol, int64_t ntc, KktRaw *out,
+                hipStream_t s);
+void restart_copy(int64_t n, int64_t m, const double *xc, const double *yc, const double *gxc,
+                  const double *atyc, double *x, double *y, double *xa, double *ya, double *gx,
+                  double *aty, double *gx0, double *aty0, double *xsum, double *ysum,
+                  hipStream_t s);
+void unscale(const double *xs, const double *f, double *out, int64_t n, hipStream_t s);
+void scale_in(const double *xu, const double *f, double *out, int64_t n, hipStream_t s);
+
+}  // namespace pdcs

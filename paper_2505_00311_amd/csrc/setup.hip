@@ -1,0 +1,285 @@
+// setup.hip -- once-per-problem work on the device: the CSR of G^T, the
+// diagonal rescaling of Section 3 (reading: Ruiz infinity-norm passes, then one
+// Pock-Chambolle pass with alpha = 1), the scaled problem vectors, input
+// validation and small deterministic reductions.
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include "device_common.hpp"
+
+namespace pdcs {
+
+static unsigned grid_for(int64_t n, int block = kBlock) {
+    int64_t g = (n + block - 1) / block;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+// ------------------------------------------------------------- transpose
+__global__ void iota_kernel(int32_t *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (int32_t)i;
+}
+
+// rp[j] = first position whose sorted key is >= j
+__global__ void rowptr_from_sorted(const int32_t *__restrict__ keys, int64_t nnz, int64_t nrows,
+                                   int64_t *__restrict__ rp) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > nnz) return;
+    const int64_t prev = k == 0 ? -1 : (int64_t)keys[k - 1];
+    const int64_t cur = k == nnz ? nrows : (int64_t)keys[k];
+    for (int64_t j = prev + 1; j <= cur; ++j) rp[j] = k;
+}
+
+// entry p of G^T is entry perm[p] of G; its column in G^T is that entry's row
+__global__ void gather_transpose(const int64_t *__restrict__ rp, int64_t m,
+                                 const double *__restrict__ v, const int32_t *__restrict__ perm,
+                                 int64_t nnz, int32_t *__restrict__ tci, double *__restrict__ tv) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nnz) return;
+    const int64_t k = perm[p];
+    int64_t lo = 0, hi = m;  // largest row i with rp[i] <= k
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) / 2;
+        if (rp[mid] <= k)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    tci[p] = (int32_t)lo;
+    tv[p] = v[k];
+}
+
+void transpose_csr(const Csr &A, Csr &At, hipStream_t s) {
+    const int64_t nnz = A.nnz;
+    if (nnz == 0) {
+        hipLaunchKernelGGL(rowptr_from_sorted, dim3(1), dim3(1), 0, s, (const int32_t *)nullptr,
+                           (int64_t)0, At.rows, At.rp);
+        PDCS_HIP(hipGetLastError());
+        return;
+    }
+    int32_t *keys_out = nullptr, *perm_in = nullptr, *perm_out = nullptr;
+    PDCS_HIP(hipMallocAsync((void **)&keys_out, sizeof(int32_t) * nnz, s));
+    PDCS_HIP(hipMallocAsync((void **)&perm_in, sizeof(int32_t) * nnz, s));
+    PDCS_HIP(hipMallocAsync((void **)&perm_out, sizeof(int32_t) * nnz, s));
+    hipLaunchKernelGGL(iota_kernel, dim3(grid_for(nnz)), dim3(kBlock), 0, s, perm_in, nnz);
+    unsigned bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) < A.cols) ++bits;
+    size_t tmp_bytes = 0;
+    PDCS_HIP(rocprim::radix_sort_pairs(nullptr, tmp_bytes, A.ci, keys_out, perm_in, perm_out,
+                                       (size_t)nnz, 0, bits, s));
+    void *tmp = nullptr;
+    PDCS_HIP(hipMallocAsync(&tmp, tmp_bytes, s));
+    // LSD radix sort is stable: entries of a column keep increasing row order
+    PDCS_HIP(rocprim::radix_sort_pairs(tmp, tmp_bytes, A.ci, keys_out, perm_in, perm_out,
+                                       (size_t)nnz, 0, bits, s));
+    hipLaunchKernelGGL(rowptr_from_sorted, dim3(grid_for(nnz + 1)), dim3(kBlock), 0, s, keys_out,
+                       nnz, At.rows, At.rp);
+    hipLaunchKernelGGL(gather_transpose, dim3(grid_for(nnz)), dim3(kBlock), 0, s, A.rp, A.rows,
+                       A.v, perm_out, nnz, At.ci, At.v);
+    PDCS_HIP(hipGetLastError());
+    PDCS_HIP(hipFreeAsync(tmp, s));
+    PDCS_HIP(hipFreeAsync(keys_out, s));
+    PDCS_HIP(hipFreeAsync(perm_in, s));
+    PDCS_HIP(hipFreeAsync(perm_out, s));
+}
+
+// ------------------------------------------------------------- rescaling
+// One wavefront per row.  For G (row_first) the entry is (e_i a_ij) f_j; for
+// G^T, whose rows are G's columns, the same product (e_i a_ij) f_j is formed.
+template <bool MAX>
+__global__ __launch_bounds__(kBlock) void rows_reduce_scaled(int64_t rows, const int64_t *__restrict__ rp,
+                                                             const int32_t *__restrict__ ci,
+                                                             const double *__restrict__ v,
+                                                             const double *__restrict__ srow,
+                                                             const double *__restrict__ scol,
+                                                             int row_first, double *__restrict__ out) {
+    const int64_t row = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+    const int lane = threadIdx.x % kWave;
+    if (row >= rows) return;
+    double acc = 0.0;
+    const double sr = srow[row];
+    for (int64_t k = rp[row] + lane; k < rp[row + 1]; k += kWave) {
+        const double a = row_first ? fabs(sr * v[k] * scol[ci[k]]) : fabs(scol[ci[k]] * v[k] * sr);
+        acc = MAX ? fmax(acc, a) : acc + a;
+    }
+    acc = MAX ? wave_max(acc) : wave_sum(acc);
+    if (lane == 0) out[row] = acc;
+}
+
+// er scales this matrix's rows and ec its columns; row_first says whether er
+// is G's row scale E (A = G) or its column scale F (A = G^T).
+void rows_absmax_scaled(const Csr &A, const double *er, const double *ec, bool row_first,
+                        double *out, hipStream_t s) {
+    if (A.rows == 0) return;
+    hipLaunchKernelGGL(rows_reduce_scaled<true>, dim3(grid_for(A.rows * kWave)), dim3(kBlock), 0,
+                       s, A.rows, A.rp, A.ci, A.v, er, ec, row_first ? 1 : 0, out);
+    PDCS_HIP(hipGetLastError());
+}
+
+void rows_abssum_scaled(const Csr &A, const double *er, const double *ec, bool row_first,
+                        double *out, hipStream_t s) {
+    if (A.rows == 0) return;
+    hipLaunchKernelGGL(rows_reduce_scaled<false>, dim3(grid_for(A.rows * kWave)), dim3(kBlock), 0,
+                       s, A.rows, A.rp, A.ci, A.v, er, ec, row_first ? 1 : 0, out);
+    PDCS_HIP(hipGetLastError());
+}
+
+__global__ void divide_by_sqrt_kernel(double *e, const double *r, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && r[i] > 0.0) e[i] /= sqrt(r[i]);
+}
+
+void divide_by_sqrt(double *e, const double *r, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(divide_by_sqrt_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, e, r, n);
+    PDCS_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(kBlock) void scale_values_kernel(int64_t rows, const int64_t *__restrict__ rp,
+                                                              const int32_t *__restrict__ ci,
+                                                              const double *__restrict__ v,
+                                                              const double *__restrict__ srow,
+                                                              const double *__restrict__ scol,
+                                                              int row_first,
+                                                              double *__restrict__ out) {
+    const int64_t row = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+    const int lane = threadIdx.x % kWave;
+    if (row >= rows) return;
+    const double sr = srow[row];
+    for (int64_t k = rp[row] + lane; k < rp[row + 1]; k += kWave)
+        out[k] = row_first ? sr * v[k] * scol[ci[k]] : scol[ci[k]] * v[k] * sr;
+}
+
+void scale_values(const Csr &A, const double *er, const double *ec, bool row_first, double *out,
+                  hipStream_t s) {
+    if (A.rows == 0) return;
+    hipLaunchKernelGGL(scale_values_kernel, dim3(grid_for(A.rows * kWave)), dim3(kBlock), 0, s,
+                       A.rows, A.rp, A.ci, A.v, er, ec, row_first ? 1 : 0, out);
+    PDCS_HIP(hipGetLastError());
+}
+
+__global__ void scale_vectors_kernel(int64_t n, int64_t m, int64_t nb, const double *c,
+                                     const double *h, const double *l, const double *u,
+                                     const double *e, const double *f, double *cs, double *hs,
+                                     double *ls, double *us, double *dx, double *dy) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        cs[i] = f[i] * c[i];
+        dx[i] = 1.0 / f[i];
+        if (i < nb) {
+            ls[i] = l[i] / f[i];
+            us[i] = u[i] / f[i];
+        }
+    }
+    if (i < m) {
+        hs[i] = e[i] * h[i];
+        dy[i] = 1.0 / e[i];
+    }
+}
+
+void scale_problem_vectors(int64_t n, int64_t m, int64_t nb, const double *c, const double *h,
+                           const double *l, const double *u, const double *e, const double *f,
+                           double *cs, double *hs, double *ls, double *us, double *dx, double *dy,
+                           hipStream_t s) {
+    const int64_t k = n > m ? n : m;
+    if (k == 0) return;
+    hipLaunchKernelGGL(scale_vectors_kernel, dim3(grid_for(k)), dim3(kBlock), 0, s, n, m, nb, c, h,
+                       l, u, e, f, cs, hs, ls, us, dx, dy);
+    PDCS_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ reductions
+constexpr int kRedBlocks = 512;
+
+template <int MODE>  // 0: sum of squares, 1: max abs
+__global__ __launch_bounds__(kBlock) void reduce_stage1(const double *__restrict__ a, int64_t n,
+                                                        double *__restrict__ part) {
+    double acc[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kBlock)
+        acc[0] = MODE == 0 ? acc[0] + a[i] * a[i] : fmax(acc[0], fabs(a[i]));
+    if (MODE == 0) {
+        block_sum_all<1>(acc);
+    } else {
+        __shared__ double red[kBlock / kWave];
+        double w = wave_max(acc[0]);
+        if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = w;
+        __syncthreads();
+        acc[0] = red[0];
+        for (int i = 1; i < kBlock / kWave; ++i) acc[0] = fmax(acc[0], red[i]);
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+}
+
+template <int MODE>
+__global__ void reduce_stage2(const double *__restrict__ part, double *__restrict__ out) {
+    if (threadIdx.x != 0) return;
+    double r = 0.0;
+    for (int i = 0; i < kRedBlocks; ++i) r = MODE == 0 ? r + part[i] : fmax(r, part[i]);
+    *out = r;
+}
+
+template <int MODE>
+static void reduce(const double *a, int64_t n, double *out, hipStream_t s) {
+    double *part = nullptr;
+    PDCS_HIP(hipMallocAsync((void **)&part, sizeof(double) * kRedBlocks, s));
+    hipLaunchKernelGGL(reduce_stage1<MODE>, dim3(kRedBlocks), dim3(kBlock), 0, s, a, n, part);
+    hipLaunchKernelGGL(reduce_stage2<MODE>, dim3(1), dim3(64), 0, s, part, out);
+    PDCS_HIP(hipGetLastError());
+    PDCS_HIP(hipFreeAsync(part, s));
+}
+
+void reduce_absmax(const double *a, int64_t n, double *out, hipStream_t s) { reduce<1>(a, n, out, s); }
+void reduce_sumsq(const double *a, int64_t n, double *out, hipStream_t s) { reduce<0>(a, n, out, s); }
+
+__global__ void check_finite_kernel(const double *a, int64_t n, int *flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !isfinite(a[i])) atomicOr(flag, 1);
+}
+
+void check_finite(const double *a, int64_t n, int *flag, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(check_finite_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, a, n, flag);
+    PDCS_HIP(hipGetLastError());
+}
+
+// -------------------------------------------------------------- elementwise
+__global__ void fill_kernel(double *p, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+void fill(double *p, int64_t n, double v, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, p, n, v);
+    PDCS_HIP(hipGetLastError());
+}
+
+__global__ void div_kernel(const double *a, const double *b, double *o, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) o[i] = a[i] / b[i];
+}
+void div_vec(const double *a, const double *b, double *out, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(div_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, a, b, out, n);
+    PDCS_HIP(hipGetLastError());
+}
+
+__global__ void mul_kernel(const double *a, const double *b, double *o, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) o[i] = a[i] * b[i];
+}
+void mul_vec(const double *a, const double *b, double *out, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(mul_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, a, b, out, n);
+    PDCS_HIP(hipGetLastError());
+}
+
+__global__ void copy_kernel(const double *a, double *o, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) o[i] = a[i];
+}
+void copy_vec(const double *a, double *out, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, a, out, n);
+    PDCS_HIP(hipGetLastError());
+}
+
+}  // namespace pdcs

@@ -1,0 +1,242 @@
+"""Python binding of libpdcs (include/pdcs.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts numpy arrays
+and torch device tensors into the pointers and sizes of the C ABI.  Loading
+fails loudly when libpdcs.so has not been built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpdcs.so")
+
+OK = 0
+SOLVE_STATUS = {0: "optimal", 1: "iteration_limit", 2: "time_limit", 3: "numerical"}
+
+_i64, _i32, _dbl, _vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
+_pd = ctypes.POINTER(ctypes.c_double)
+_pi32 = ctypes.POINTER(ctypes.c_int32)
+_pi64 = ctypes.POINTER(ctypes.c_int64)
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("n", _i64), ("m", _i64), ("nnz", _i64), ("n_box", _i64),
+                ("row_ptr", _vp), ("col", _vp), ("val", _vp), ("c", _vp), ("h", _vp),
+                ("l", _vp), ("u", _vp),
+                ("n_xcones", _i64), ("xcone_type", _pi32), ("xcone_dim", _pi64),
+                ("n_rcones", _i64), ("rcone_type", _pi32), ("rcone_dim", _pi64)]
+
+
+class Settings(ctypes.Structure):
+    _fields_ = [("tol", _dbl), ("max_iter", _i64), ("time_limit", _dbl),
+                ("check_every", _i32), ("ruiz_iters", _i32), ("pock_chambolle", _i32),
+                ("beta_mode", _i32), ("beta_const", _dbl), ("beta_grow", _dbl),
+                ("beta_shrink", _dbl), ("step_reduce_exp", _dbl), ("step_grow_exp", _dbl),
+                ("restart_sufficient", _dbl), ("restart_necessary", _dbl),
+                ("restart_artificial", _dbl), ("max_attempts", _i32), ("out_on_device", _i32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("status", _i32), ("iterations", _i64), ("attempts", _i64), ("restarts", _i64),
+                ("spmv", _i64), ("pobj", _dbl), ("dobj", _dbl), ("err_p", _dbl), ("err_d", _dbl),
+                ("err_gap", _dbl), ("omega", _dbl), ("eta", _dbl), ("setup_s", _dbl),
+                ("solve_s", _dbl)]
+
+
+class Trace(ctypes.Structure):
+    _fields_ = [("cap", _i64), ("count", _i64), ("attempts", _pi32), ("eta_used", _pd),
+                ("beta", _pd), ("omega", _pd), ("check_code", _pi32), ("check_kkt", _pd),
+                ("n_snap", _i64), ("snap_iter", _pi64), ("snap_x", _pd), ("snap_y", _pd)]
+
+
+class PdcsError(RuntimeError):
+    pass
+
+
+_lib = None
+
+SYMBOLS = ["pdcs_settings_default", "pdcs_problem_create", "pdcs_problem_create_device",
+           "pdcs_problem_destroy", "pdcs_solve", "pdcs_scaling", "pdcs_spmv", "pdcs_kkt",
+           "pdcs_project", "pdcs_status_string", "pdcs_last_error"]
+
+
+def load():
+    """Loads libpdcs.so; raises if it is missing (build it with build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise PdcsError(f"{LIB_PATH} is not built; run `python -m paper_2505_00311_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.pdcs_settings_default.argtypes = [ctypes.POINTER(Settings)]
+    L.pdcs_problem_create.argtypes = [ctypes.POINTER(ProblemDesc), _vp, ctypes.POINTER(_vp)]
+    L.pdcs_problem_create_device.argtypes = [ctypes.POINTER(ProblemDesc), _vp, ctypes.POINTER(_vp)]
+    L.pdcs_problem_destroy.argtypes = [_vp]
+    L.pdcs_problem_destroy.restype = None
+    L.pdcs_solve.argtypes = [_vp, ctypes.POINTER(Settings), _vp, _vp, _dbl, _vp, _vp,
+                             ctypes.POINTER(Info), ctypes.POINTER(Trace)]
+    L.pdcs_scaling.argtypes = [_vp, ctypes.POINTER(Settings), _vp, _vp]
+    L.pdcs_spmv.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
+    L.pdcs_kkt.argtypes = [_vp, _vp, _vp, _vp]
+    L.pdcs_project.argtypes = [_i64, _pi32, _pi64, ctypes.c_int, _vp, _vp, _vp]
+    L.pdcs_status_string.argtypes = [ctypes.c_int]
+    L.pdcs_status_string.restype = ctypes.c_char_p
+    L.pdcs_last_error.argtypes = []
+    L.pdcs_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != OK:
+        L = load()
+        raise PdcsError(f"{L.pdcs_status_string(rc).decode()}: {L.pdcs_last_error().decode()}")
+
+
+def settings_default(**overrides) -> Settings:
+    s = Settings()
+    _check(load().pdcs_settings_default(ctypes.byref(s)))
+    for k, v in overrides.items():
+        if not hasattr(s, k):
+            raise KeyError(k)
+        setattr(s, k, v)
+    return s
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """A problem handle (pdcs_problem_create / pdcs_problem_create_device)."""
+
+    def __init__(self, inst, stream=None, from_device=False):
+        L = load()
+        self._keep = []
+        self.n, self.m, self.n_box = int(inst.n), int(inst.m), int(inst.n_box)
+        self.stream = _stream(stream)
+
+        def host(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            self._keep.append(a)
+            return a
+
+        rp, col, val = host(inst.row_ptr, np.int64), host(inst.col, np.int32), host(inst.val, np.float64)
+        c, h = host(inst.c, np.float64), host(inst.h, np.float64)
+        l = host(inst.l if self.n_box else np.zeros(1), np.float64)
+        u = host(inst.u if self.n_box else np.zeros(1), np.float64)
+        if from_device:
+            import torch
+            dev = [torch.from_numpy(a).cuda() for a in (rp, col, val, c, h, l, u)]
+            torch.cuda.synchronize()
+            self._keep += dev
+            ptrs = [_dptr(t) for t in dev]
+        else:
+            ptrs = [ctypes.c_void_p(a.ctypes.data) for a in (rp, col, val, c, h, l, u)]
+        xt, xd = host(inst.xcone_type, np.int32), host(inst.xcone_dim, np.int64)
+        rt, rd = host(inst.rcone_type, np.int32), host(inst.rcone_dim, np.int64)
+        desc = ProblemDesc(self.n, self.m, int(val.size), self.n_box, *ptrs,
+                           int(xt.size), xt.ctypes.data_as(_pi32), xd.ctypes.data_as(_pi64),
+                           int(rt.size), rt.ctypes.data_as(_pi32), rd.ctypes.data_as(_pi64))
+        handle = ctypes.c_void_p()
+        fn = L.pdcs_problem_create_device if from_device else L.pdcs_problem_create
+        _check(fn(ctypes.byref(desc), self.stream, ctypes.byref(handle)))
+        self.handle = handle
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().pdcs_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ solve
+    def solve(self, settings: Settings | None = None, x0=None, y0=None, omega0: float = 0.0,
+              log_cap: int = 0, snap_iters=None, x_out=None, y_out=None):
+        """pdcs_solve.  Returns a dict of the info fields plus x, y (numpy, or the
+        given device tensors x_out/y_out) and, if requested, the decision log."""
+        L = load()
+        s = settings or settings_default()
+        on_dev = x_out is not None
+        s.out_on_device = 1 if on_dev else 0
+        if on_dev:
+            xo, yo = x_out, y_out
+            px, py = _dptr(xo), _dptr(yo)
+        else:
+            xo, yo = np.empty(self.n), np.empty(self.m)
+            px, py = ctypes.c_void_p(xo.ctypes.data), ctypes.c_void_p(yo.ctypes.data)
+        x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
+        y0a = None if y0 is None else np.ascontiguousarray(y0, dtype=np.float64)
+        info = Info()
+        tr, logs = None, None
+        if log_cap or snap_iters is not None:
+            cap = max(int(log_cap), 1)
+            snaps = np.ascontiguousarray(snap_iters if snap_iters is not None else [], np.int64)
+            logs = {"attempts": np.zeros(cap, np.int32), "eta_used": np.zeros(cap),
+                    "beta": np.zeros(cap), "omega": np.zeros(cap),
+                    "check_code": np.zeros(cap, np.int32), "check_kkt": np.zeros(cap),
+                    "snap_iter": snaps, "snap_x": np.zeros((max(snaps.size, 1), self.n)),
+                    "snap_y": np.zeros((max(snaps.size, 1), self.m))}
+            tr = Trace(cap, 0, logs["attempts"].ctypes.data_as(_pi32),
+                       logs["eta_used"].ctypes.data_as(_pd), logs["beta"].ctypes.data_as(_pd),
+                       logs["omega"].ctypes.data_as(_pd), logs["check_code"].ctypes.data_as(_pi32),
+                       logs["check_kkt"].ctypes.data_as(_pd), int(snaps.size),
+                       snaps.ctypes.data_as(_pi64), logs["snap_x"].ctypes.data_as(_pd),
+                       logs["snap_y"].ctypes.data_as(_pd))
+        _check(L.pdcs_solve(self.handle, ctypes.byref(s),
+                            None if x0a is None else ctypes.c_void_p(x0a.ctypes.data),
+                            None if y0a is None else ctypes.c_void_p(y0a.ctypes.data),
+                            float(omega0), px, py, ctypes.byref(info),
+                            ctypes.byref(tr) if tr is not None else None))
+        out = {k: getattr(info, k) for k, _ in Info._fields_}
+        out["x"], out["y"] = xo, yo
+        if logs is not None:
+            cnt = tr.count
+            for k in ("attempts", "eta_used", "beta", "omega", "check_code", "check_kkt"):
+                logs[k] = logs[k][:cnt]
+            out["log"] = logs
+        return out
+
+    def scaling(self, settings: Settings | None = None):
+        """pdcs_scaling -> (e [m], f [n])."""
+        e, f = np.empty(self.m), np.empty(self.n)
+        _check(load().pdcs_scaling(self.handle, ctypes.byref(settings or settings_default()),
+                                   ctypes.c_void_p(e.ctypes.data), ctypes.c_void_p(f.ctypes.data)))
+        return e, f
+
+    def spmv(self, x_dev, y_dev, transpose=False, stream=None):
+        """pdcs_spmv on device tensors: y = G x (or G^T x)."""
+        _check(load().pdcs_spmv(self.handle, 1 if transpose else 0, _dptr(x_dev), _dptr(y_dev),
+                                _stream(stream) if stream is not None else self.stream))
+
+    def kkt(self, x_dev, y_dev):
+        """pdcs_kkt at unscaled device tensors -> dict."""
+        out = np.empty(5)
+        _check(load().pdcs_kkt(self.handle, _dptr(x_dev), _dptr(y_dev),
+                               ctypes.c_void_p(out.ctypes.data)))
+        return dict(zip(("err_p", "err_d", "err_gap", "pobj", "dobj"), out.tolist()))
+
+
+def project(types, dims, v_dev, d_dev=None, dual=False, stream=None):
+    """pdcs_project: in-place projection of the device tensor v_dev."""
+    t = np.ascontiguousarray(types, np.int32)
+    k = np.ascontiguousarray(dims, np.int64)
+    _check(load().pdcs_project(int(t.size), t.ctypes.data_as(_pi32), k.ctypes.data_as(_pi64),
+                               1 if dual else 0, None if d_dev is None else _dptr(d_dev),
+                               _dptr(v_dev), _stream(stream)))

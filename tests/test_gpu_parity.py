@@ -1,0 +1,269 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on
+the same seeded inputs.
+
+Tolerances: projections, products and scalings are single evaluations with
+rounding-order differences only (relative 1e-12 of the block's scale); the
+iterate trajectory is held to 1e-10 relative over the first 200 iterations,
+and final objectives and KKT measures to 1e-6."""
+import numpy as np
+import pytest
+
+from paper_2505_00311_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_00311_amd import pdcs
+    pdcs.load()
+    return pdcs
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------------- projections
+def random_cone_vector(rng, types, dims, scale_range=1.5):
+    v = np.concatenate([rng.standard_normal(k) * 10 ** rng.uniform(-2, 2) for k in dims])
+    d = 10 ** rng.uniform(-scale_range, scale_range, v.size)
+    o = 0
+    for t, k in zip(types, dims):        # put some SOC points at t = 0, inside, in the polar
+        if t == 3 and k > 1:
+            u = rng.random()
+            if u < 0.15:
+                v[o] = 0.0
+            elif u < 0.3:
+                v[o] = 1.5 * np.linalg.norm(v[o + 1:o + k] * d[o] / d[o + 1:o + k])
+            elif u < 0.45:
+                v[o] = -1.5 * np.linalg.norm(v[o + 1:o + k] * d[o + 1:o + k] / d[o])
+        o += k
+    return v, d
+
+
+@pytest.mark.parametrize("dual", [False, True])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_project_matches_oracle(pd, orc, dual, seed):
+    rng = np.random.default_rng(seed)
+    types, dims = [], []
+    for _ in range(400):
+        t = int(rng.choice([0, 1, 2, 3, 3, 3, 4, 5]))
+        k = 3 if t in (4, 5) else int(rng.choice([1, 2, 3, 7, 31, 64, 65, 130, 256, 257, 900, 3000]))
+        if t != 3:
+            k = 3 if t in (4, 5) else int(rng.integers(1, 50))
+        types.append(t), dims.append(k)
+    v, d = random_cone_vector(rng, types, dims)
+    say("project", dual, seed, v.size)
+    ref = orc.proj_blocks(types, dims, v, d, dual=dual)
+    vd = dev(v)
+    pd.project(types, dims, vd, dev(d), dual=dual)
+    got = vd.cpu().numpy()
+    o = 0
+    for t, k in zip(types, dims):
+        sc = max(1.0, np.linalg.norm(v[o:o + k]))
+        err = np.abs(got[o:o + k] - ref[o:o + k]).max() / sc
+        assert err <= 1e-12, (t, k, err)
+        o += k
+
+
+def test_project_unscaled_extreme_exp(pd, orc):
+    rng = np.random.default_rng(5)
+    nb = 4000
+    v = rng.standard_normal(3 * nb) * 10 ** rng.uniform(-4, 4, 3 * nb)
+    d = 10 ** rng.uniform(-2.5, 2.5, 3 * nb)
+    for dual in (False, True):
+        ref = orc.proj_blocks([4] * nb, [3] * nb, v, d, dual=dual)
+        vd = dev(v)
+        pd.project([4] * nb, [3] * nb, vd, dev(d), dual=dual)
+        got = vd.cpu().numpy().reshape(nb, 3)
+        sc = np.maximum(1.0, np.linalg.norm(v.reshape(nb, 3), axis=1))
+        err = (np.abs(got - ref.reshape(nb, 3)).max(axis=1) / sc).max()
+        assert np.all(np.isfinite(got)) and err <= 1e-9, err
+
+
+# ---------------------------------------------------------------- products
+@pytest.mark.parametrize("maker", ["small", "lp_soc", "powerlaw"])
+def test_spmv_matches_oracle(pd, orc, maker):
+    rng = np.random.default_rng(3)
+    if maker == "small":
+        inst = I.small_mixed(1)
+    elif maker == "lp_soc":
+        inst = I.lp_soc_small(20250501)
+    else:   # power-law columns: long rows of G^T go down the chunked path
+        inst = I.large_mixed(4, n=200_000, m=100_000)
+    say("spmv", maker, inst.n, inst.m, inst.nnz)
+    prob = pd.Problem(inst)
+    x = rng.standard_normal(inst.n)
+    y = rng.standard_normal(inst.m)
+    gx = torch.empty(inst.m, dtype=torch.float64, device="cuda")
+    gty = torch.empty(inst.n, dtype=torch.float64, device="cuda")
+    prob.spmv(dev(x), gx)
+    prob.spmv(dev(y), gty, transpose=True)
+    torch.cuda.synchronize()
+    ref = orc.spmv(inst.row_ptr, inst.col, inst.val, x)
+    rows = np.repeat(np.arange(inst.m), np.diff(inst.row_ptr))
+    absrow = np.zeros(inst.m)
+    np.add.at(absrow, rows, np.abs(inst.val * x[inst.col]))
+    assert np.all(np.abs(gx.cpu().numpy() - ref) <= 1e-14 * absrow + 1e-300)
+    # G^T y against the oracle's product with the transposed matrix
+    order = np.lexsort((rows, inst.col))
+    trp = np.concatenate([[0], np.cumsum(np.bincount(inst.col, minlength=inst.n))])
+    tref = orc.spmv(trp, rows[order], inst.val[order], y)
+    abscol = np.zeros(inst.n)
+    np.add.at(abscol, inst.col, np.abs(inst.val * y[rows]))
+    assert np.all(np.abs(gty.cpu().numpy() - tref) <= 1e-14 * abscol + 1e-300)
+    prob.close()
+
+
+# ---------------------------------------------------------- scaling, KKT
+@pytest.mark.parametrize("ruiz,pc", [(10, 1), (0, 1), (3, 0)])
+def test_scaling_matches_oracle(pd, orc, ruiz, pc):
+    inst = I.large_mixed(6, n=20000, m=10000)
+    prob = pd.Problem(inst)
+    e, f = prob.scaling(pd.settings_default(ruiz_iters=ruiz, pock_chambolle=pc))
+    eo, fo = orc.scaling(inst, orc.default_settings(ruiz_iters=ruiz, pock_chambolle=pc))
+    assert np.allclose(e, eo, rtol=1e-13, atol=0) and np.allclose(f, fo, rtol=1e-13, atol=0)
+    if not pc:   # max-based passes form every product in the oracle's order: bit-exact
+        assert np.array_equal(e, eo) and np.array_equal(f, fo)
+    prob.close()
+
+
+@pytest.mark.parametrize("seed", [0, 2])
+def test_kkt_matches_oracle(pd, orc, seed):
+    inst = I.small_mixed(seed)
+    prob = pd.Problem(inst)
+    rng = np.random.default_rng(seed)
+    for x, y in ((inst.x_star, inst.y_star),
+                 (inst.x_star + 0.1 * rng.standard_normal(inst.n), inst.y_star),
+                 (rng.standard_normal(inst.n), rng.standard_normal(inst.m))):
+        g = prob.kkt(dev(x), dev(y))
+        o = orc.kkt(inst, x, y)
+        for k in ("err_p", "err_d", "err_gap", "pobj", "dobj"):
+            assert g[k] == pytest.approx(o[k], rel=1e-12, abs=1e-14), k
+    prob.close()
+
+
+# ------------------------------------------------------ iterate trajectory
+TRAJ = [("small_mixed_0", lambda: I.small_mixed(0)),
+        ("small_mixed_5", lambda: I.small_mixed(5)),
+        ("lp_soc_n1000", lambda: I.lp_soc_small(20250501)),
+        ("large_mixed_n20000", lambda: I.large_mixed(7, n=20000, m=10000))]
+
+
+@pytest.mark.parametrize("name,maker", TRAJ, ids=[t[0] for t in TRAJ])
+def test_trajectory_first_200_iterations(pd, orc, name, maker):
+    """Same decisions and iterates within 1e-10 relative at every one of the
+    first 200 iterations (restarts at the checks included)."""
+    inst = maker()
+    say("trajectory", name, inst.n, inst.m, inst.nnz)
+    iters = np.arange(1, 201)
+    s = pd.settings_default(max_iter=200)
+    so = orc.default_settings(max_iter=200)
+    prob = pd.Problem(inst)
+    g = prob.solve(s, log_cap=200, snap_iters=iters)
+    o = orc.solve(inst, so, log_cap=200, snap_iters=iters)
+    gl, ol = g["log"], o["log"]
+    assert np.array_equal(gl["attempts"], ol["attempts"])
+    assert np.array_equal(gl["check_code"], ol["check_code"])
+    for k in ("eta_used", "beta", "omega"):
+        assert np.allclose(gl[k], ol[k], rtol=1e-10, atol=0), k
+    worst = 0.0
+    for i in range(200):
+        zg = np.concatenate([gl["snap_x"][i], gl["snap_y"][i]])
+        zo = np.concatenate([ol["snap_x"][i], ol["snap_y"][i]])
+        err = np.linalg.norm(zg - zo) / max(1.0, np.linalg.norm(zo))
+        worst = max(worst, err)
+        assert err <= 1e-10, (i + 1, err)
+    say("  worst relative iterate difference", worst)
+    prob.close()
+
+
+# ------------------------------------------------------------ end to end
+E2E = [("small_mixed_1", lambda: I.small_mixed(1)),
+       ("small_mixed_4", lambda: I.small_mixed(4)),
+       ("lp_soc_n1000", lambda: I.lp_soc_small(20250501)),
+       ("ball_socp", lambda: I.ball_socp(2)),
+       ("tiny_lp", lambda: I.tiny_lp(3))]
+
+
+@pytest.mark.parametrize("name,maker", E2E, ids=[t[0] for t in E2E])
+def test_solve_to_tolerance_matches_oracle(pd, orc, name, maker):
+    inst = maker()
+    say("e2e", name)
+    prob = pd.Problem(inst)
+    g = prob.solve(pd.settings_default())
+    o = orc.solve(inst, orc.default_settings())
+    assert g["status"] == 0 and o["status"] == 0
+    assert max(g["err_p"], g["err_d"], g["err_gap"]) <= 1e-6
+    assert g["pobj"] == pytest.approx(o["pobj"], rel=1e-6, abs=1e-6)
+    # the oracle's own measures at the GPU's answer
+    k = orc.kkt(inst, g["x"], g["y"])
+    assert max(k["err_p"], k["err_d"], k["err_gap"]) <= 1.01e-6
+    assert k["pobj"] == pytest.approx(g["pobj"], rel=1e-12, abs=1e-12)
+    if inst.opt is not None:
+        assert g["pobj"] == pytest.approx(inst.opt, rel=1e-5, abs=1e-5)
+    prob.close()
+
+
+def test_solve_from_device_arrays_and_device_outputs(pd, orc):
+    inst = I.small_mixed(3)
+    a = pd.Problem(inst).solve(pd.settings_default(max_iter=300))
+    prob = pd.Problem(inst, from_device=True)
+    xo = torch.empty(inst.n, dtype=torch.float64, device="cuda")
+    yo = torch.empty(inst.m, dtype=torch.float64, device="cuda")
+    b = prob.solve(pd.settings_default(max_iter=300), x_out=xo, y_out=yo)
+    torch.cuda.synchronize()
+    assert np.array_equal(a["x"], xo.cpu().numpy()) and np.array_equal(a["y"], yo.cpu().numpy())
+    prob.close()
+
+
+def test_edge_cases(pd, orc):
+    inst = I.small_mixed(0)
+    prob = pd.Problem(inst)
+    # no iterations: the projected starting point is returned
+    r = prob.solve(pd.settings_default(max_iter=0))
+    assert r["status"] == 1 and r["iterations"] == 0
+    # warm start at the planted optimum: optimal before the first iteration
+    r = prob.solve(pd.settings_default(), x0=inst.x_star, y0=inst.y_star)
+    assert r["status"] == 0 and r["iterations"] == 0
+    # an iteration limit that is not a multiple of the check period
+    r = prob.solve(pd.settings_default(max_iter=100))
+    o = orc.solve(inst, orc.default_settings(max_iter=100))
+    assert r["status"] == 1 and r["iterations"] == 100
+    assert np.allclose(r["x"], o["x"], rtol=1e-9, atol=1e-9)
+    prob.close()
+    # malformed inputs are rejected with the documented status
+    bad = I.small_mixed(0)
+    bad.c = bad.c.copy()
+    bad.c[2] = np.nan
+    with pytest.raises(pd.PdcsError, match="non-finite"):
+        pd.Problem(bad)
+    bad = I.small_mixed(0)
+    bad.xcone_dim = bad.xcone_dim.copy()
+    bad.xcone_dim[0] += 1
+    with pytest.raises(pd.PdcsError, match="dimension"):
+        pd.Problem(bad)
+    bad = I.small_mixed(0)
+    bad.col = bad.col.copy()
+    bad.col[0] = inst.n + 5
+    with pytest.raises(pd.PdcsError, match="CSR"):
+        pd.Problem(bad)
+
+
+def test_empty_rows_and_columns(pd, orc):
+    """Rows and columns without entries (the ball SOCP's first row is empty)."""
+    inst = I.ball_socp(1, n=6)
+    prob = pd.Problem(inst)
+    g = prob.solve(pd.settings_default(max_iter=128), log_cap=128, snap_iters=[64, 128])
+    o = orc.solve(inst, orc.default_settings(max_iter=128), log_cap=128, snap_iters=[64, 128])
+    assert np.allclose(g["log"]["snap_x"], o["log"]["snap_x"], rtol=1e-10, atol=1e-12)
+    prob.close()
