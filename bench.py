@@ -173,7 +173,7 @@ def main():
 
     if not args.no_time_to_tol:
         t0 = time.perf_counter()
-        rt = prob.solve(pdcs.settings_default(time_limit=150.0))
+        rt = prob.solve(pdcs.settings_default(time_limit=100.0))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         out["time_to_tol"] = {

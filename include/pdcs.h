@@ -106,6 +106,9 @@ typedef struct {
     double restart_sufficient, restart_necessary, restart_artificial;
     int32_t max_attempts;       /* line-search attempts per iteration before NUMERICAL   */
     int32_t out_on_device;      /* 1: x_out / y_out of pdcs_solve are device pointers    */
+    int32_t step_mode;          /* 0: adaptive step of Algorithm 1; 1: fixed step        */
+    double step_fixed;          /* fixed step = step_fixed / ||G~||_2 (step_mode 1)      */
+    int32_t power_iters;        /* power iterations estimating ||G~||_2 (step_mode 1)    */
 } pdcs_settings;
 
 typedef struct {

@@ -59,7 +59,8 @@ class Settings(ctypes.Structure):
                 ("beta_const", _dbl), ("beta_grow", _dbl), ("beta_shrink", _dbl),
                 ("step_reduce_exp", _dbl), ("step_grow_exp", _dbl),
                 ("restart_sufficient", _dbl), ("restart_necessary", _dbl),
-                ("restart_artificial", _dbl), ("max_attempts", _i32)]
+                ("restart_artificial", _dbl), ("max_attempts", _i32), ("step_mode", _i32),
+                ("step_fixed", _dbl), ("power_iters", _i32)]
 
 
 class _Info(ctypes.Structure):

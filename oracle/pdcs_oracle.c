@@ -216,28 +216,43 @@ int orc_proj_exp(const double *v, const double *d, double *out) {
         return 3;
     }
     /* case 4: root of h on (l_rho, u_rho), eq. (lrho_urho); h(a3) > 0, h(a4) < 0.
-     * Reading for the unbounded ends: step away from the finite end by
-     * 1, 2, 4, ... until h changes sign. */
+     * Reading for the unbounded and the far ends: the bracket is kept inside
+     * |rho| <= 700.  An unbounded end is found by stepping away from the finite
+     * one by 1, 2, 4, ... until h changes sign.  In case (iii) with a4 > 700 the
+     * root lies beyond a4, where s_p ~ e^-rho t0 / dt, so the projection equals
+     * its limit (0, 0, t0^+) to double precision; in case (ii) with a3 < -700
+     * it equals (r0, s0, dt (s0/ds) e^a3). */
+    const double R = 700.0;
     exp_ctx c = {r0, s0, t0, dr, ds, dt, ds / dr};
     double xneg, xpos;
     if (r0 > 0.0 && s0 > 0.0) {
-        xpos = r0 * ds / (s0 * dr);
-        xneg = 1.0 - s0 * ds / (r0 * dr);
+        xpos = fmin(r0 * ds / (s0 * dr), R);
+        xneg = fmax(1.0 - s0 * ds / (r0 * dr), -R);
     } else if (s0 > 0.0) { /* r0 <= 0: (-inf, a3) */
-        xpos = r0 * ds / (s0 * dr);
+        double a3 = r0 * ds / (s0 * dr);
+        if (!(a3 >= -R)) {
+            out[0] = r0, out[1] = s0, out[2] = dt * (s0 / ds) * exp(a3);
+            return 4;
+        }
+        xpos = a3;
         double step = 1.0;
-        xneg = xpos - step;
-        for (int j = 0; j < 1100 && !(exp_hs(&c, xneg) < 0.0); ++j) {
+        xneg = fmax(xpos - step, -R);
+        while (!(exp_hs(&c, xneg) < 0.0) && xneg > -R) {
             step *= 2.0;
-            xneg = xpos - step;
+            xneg = fmax(xpos - step, -R);
         }
     } else { /* r0 > 0, s0 <= 0: (a4, inf) */
-        xneg = 1.0 - s0 * ds / (r0 * dr);
+        double a4 = 1.0 - s0 * ds / (r0 * dr);
+        if (!(a4 <= R)) {
+            out[0] = 0.0, out[1] = 0.0, out[2] = t0 > 0.0 ? t0 : 0.0;
+            return 4;
+        }
+        xneg = a4;
         double step = 1.0;
-        xpos = xneg + step;
-        for (int j = 0; j < 1100 && !(exp_hs(&c, xpos) > 0.0); ++j) {
+        xpos = fmin(xneg + step, R);
+        while (!(exp_hs(&c, xpos) > 0.0) && xpos < R) {
             step *= 2.0;
-            xpos = xneg + step;
+            xpos = fmin(xneg + step, R);
         }
     }
     double rho = exp_root(&c, xneg, xpos);
@@ -553,6 +568,9 @@ void orc_settings_default(orc_settings *s) {
     s->restart_necessary = 0.8;
     s->restart_artificial = 0.36;
     s->max_attempts = 64;
+    s->step_mode = 0;
+    s->step_fixed = 0.9;
+    s->power_iters = 100;
 }
 
 typedef struct {
@@ -604,6 +622,22 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
 
     /* --- initial step size and primal weight (readings) --- */
     double eta = gmax > 0.0 ? 1.0 / gmax : 1.0;
+    if (s->step_mode == 1) {
+        /* fixed step step_fixed / ||G~||_2, the norm by power iteration on
+         * G~^T G~ from the normalised all-ones vector */
+        double *pv = ALLOC(double, n), *pu = ALLOC(double, m), *pw = ALLOC(double, n);
+        for (int64_t j = 0; j < n; ++j) pv[j] = 1.0 / sqrt((double)n);
+        double lam = 0.0;
+        for (int it = 0; it < s->power_iters; ++it) {
+            spmv(m, p->row_ptr, p->col, gv, pv, pu);
+            spmv(n, trp, tci, tv, pu, pw);
+            lam = sqrt(nrm2sq(n, pw));
+            if (!(lam > 0.0)) break;
+            for (int64_t j = 0; j < n; ++j) pv[j] = pw[j] / lam;
+        }
+        eta = lam > 0.0 ? s->step_fixed / sqrt(lam) : 1.0;
+        free(pv), free(pu), free(pw);
+    }
     double omega;
     {
         double nc = sqrt(nrm2sq(n, cs)), nh = sqrt(nrm2sq(m, hs));
@@ -679,6 +713,10 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
             double e1 = (1.0 - pow(nn, -s->step_reduce_exp)) * ebar;
             double e2 = (1.0 + pow(nn, -s->step_grow_exp)) * eta;
             double enew = e1 < e2 ? e1 : e2;
+            if (s->step_mode == 1) { /* fixed step: every attempt is accepted */
+                eta_used = eta;
+                break;
+            }
             if (eta <= ebar) {
                 eta_used = eta;
                 eta = enew;

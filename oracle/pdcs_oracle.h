@@ -70,6 +70,9 @@ typedef struct {
     double restart_necessary;   /* ... or <= this * KKT(anchor) and KKT grew             */
     double restart_artificial;  /* ... or inner iterations >= this * total iterations     */
     int32_t max_attempts;       /* line-search attempts per iteration before NUMERICAL    */
+    int32_t step_mode;          /* 0: adaptive step (Algorithm 1), 1: fixed step          */
+    double step_fixed;          /* fixed step = step_fixed / ||G~||_2                      */
+    int32_t power_iters;        /* power iterations estimating ||G~||_2                    */
 } orc_settings;
 
 typedef struct {

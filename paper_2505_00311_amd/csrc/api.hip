@@ -370,6 +370,25 @@ static void ensure_scaling(pdcs_problem *P, int ruiz, int pc) {
     P->scaled_ruiz = ruiz, P->scaled_pc = pc;
 }
 
+// Fixed step step_fixed / ||G~||_2, the norm by power iteration on G~^T G~ from
+// the normalised all-ones vector (the plain-PDHG step of the ablation).
+static double fixed_step(pdcs_problem *P, const pdcs_settings *S) {
+    hipStream_t s = P->stream;
+    const int64_t n = P->n;
+    fill(P->tmp_n, n, 1.0 / std::sqrt((double)n), s);
+    for (int it = 0; it < S->power_iters; ++it) {
+        spmv(P->Gs, P->pG, P->tmp_n, P->tmp_m, nullptr, s);
+        spmv(P->Gts, P->pGt, P->tmp_m, P->atyh, nullptr, s);
+        reduce_sumsq(P->atyh, n, P->scal + 5, s);
+        scale_by_inv_sqrt(P->atyh, P->scal + 5, P->tmp_n, n, s);
+    }
+    double lam2 = 0.0;
+    d2h(&lam2, P->scal + 5, 1, s);
+    PDCS_HIP(hipStreamSynchronize(s));
+    const double lam = std::sqrt(lam2);
+    return (S->power_iters > 0 && lam > 0.0) ? S->step_fixed / std::sqrt(lam) : 1.0;
+}
+
 struct Kkt {
     double err_p, err_d, err_gap, pobj, dobj, dx2, dy2;
     double avg() const { return (err_p + err_d + err_gap) / 3.0; }
@@ -417,7 +436,8 @@ static void solve_impl(pdcs_problem *P, const pdcs_settings *S, const double *x0
                        double omega0, double *xo, double *yo, pdcs_info *info, pdcs_trace *tr) {
     using clk = std::chrono::steady_clock;
     if (!S || !xo || !yo) fail(PDCS_ERR_INVALID_ARG, "settings, x_out and y_out are required");
-    if (S->check_every < 1 || S->ruiz_iters < 0 || S->max_attempts < 1 || !(S->tol >= 0.0))
+    if (S->check_every < 1 || S->ruiz_iters < 0 || S->max_attempts < 1 || !(S->tol >= 0.0) ||
+        S->step_mode < 0 || S->step_mode > 1 || (S->step_mode == 1 && !(S->step_fixed > 0.0)))
         fail(PDCS_ERR_INVALID_ARG, "bad settings");
     if (tr && (tr->cap < 0 || tr->n_snap < 0 || (tr->n_snap > 0 && (!tr->snap_iter || !tr->snap_x || !tr->snap_y)) ||
                (tr->cap > 0 && (!tr->attempts || !tr->eta_used || !tr->beta || !tr->omega ||
@@ -465,12 +485,14 @@ static void solve_impl(pdcs_problem *P, const pdcs_settings *S, const double *x0
 
     DevState hs{};
     hs.eta = P->gmax > 0.0 ? 1.0 / P->gmax : 1.0;
+    if (S->step_mode == 1) hs.eta = fixed_step(P, S);
     hs.omega = (P->cs_norm > 1e-10 && P->hs_norm > 1e-10) ? P->cs_norm / P->hs_norm : 1.0;
     if (omega0 > 0.0) hs.omega = omega0;
     hs.tau = hs.eta / hs.omega, hs.sigma = hs.eta * hs.omega;
     hs.beta_prev = 1.0, hs.r_prev = INFINITY;
     hs.max_iter = S->max_iter, hs.check_every = S->check_every, hs.max_attempts = S->max_attempts;
     hs.beta_mode = S->beta_mode, hs.beta_const = S->beta_const, hs.beta_grow = S->beta_grow;
+    hs.step_mode = S->step_mode;
     hs.beta_shrink = S->beta_shrink, hs.step_reduce_exp = S->step_reduce_exp;
     hs.step_grow_exp = S->step_grow_exp;
     hs.log_cap = cap, hs.log_attempts = log_att, hs.log_eta = log_eta, hs.log_beta = log_beta,
@@ -669,6 +691,9 @@ pdcs_status pdcs_settings_default(pdcs_settings *s) {
     s->restart_artificial = 0.36;
     s->max_attempts = 64;
     s->out_on_device = 0;
+    s->step_mode = 0;
+    s->step_fixed = 0.9;
+    s->power_iters = 100;
     return PDCS_OK;
 }
 

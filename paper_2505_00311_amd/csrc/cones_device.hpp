@@ -113,26 +113,41 @@ __device__ void exp_project(double r0, double s0, double t0, double dr, double d
         pr = r0, ps = 0.0, pt = t0 > 0.0 ? t0 : 0.0;
         return;
     }
-    const ExpPt c{r0, s0, t0, dr, ds, dt, ds / dr};       // case 4
+    // case 4: the bracket stays inside |rho| <= 700; an unbounded end is found
+    // by doubling steps away from the finite one.  Beyond 700 the projection
+    // is its limit to double precision: (0, 0, t0+) when a4 > 700 in case (iii),
+    // (r0, s0, dt (s0/ds) e^a3) when a3 < -700 in case (ii).
+    constexpr double R = 700.0;
+    const ExpPt c{r0, s0, t0, dr, ds, dt, ds / dr};
     double xneg, xpos;
     if (r0 > 0.0 && s0 > 0.0) {
-        xpos = r0 * ds / (s0 * dr);
-        xneg = 1.0 - s0 * ds / (r0 * dr);
+        xpos = fmin(r0 * ds / (s0 * dr), R);
+        xneg = fmax(1.0 - s0 * ds / (r0 * dr), -R);
     } else if (s0 > 0.0) {
-        xpos = r0 * ds / (s0 * dr);
+        const double a3 = r0 * ds / (s0 * dr);
+        if (!(a3 >= -R)) {
+            pr = r0, ps = s0, pt = dt * (s0 / ds) * exp(a3);
+            return;
+        }
+        xpos = a3;
         double step = 1.0;
-        xneg = xpos - step;
-        for (int j = 0; j < 1100 && !(exp_hs_value(c, xneg) < 0.0); ++j) {
+        xneg = fmax(xpos - step, -R);
+        while (!(exp_hs_value(c, xneg) < 0.0) && xneg > -R) {
             step *= 2.0;
-            xneg = xpos - step;
+            xneg = fmax(xpos - step, -R);
         }
     } else {
-        xneg = 1.0 - s0 * ds / (r0 * dr);
+        const double a4 = 1.0 - s0 * ds / (r0 * dr);
+        if (!(a4 <= R)) {
+            pr = 0.0, ps = 0.0, pt = t0 > 0.0 ? t0 : 0.0;
+            return;
+        }
+        xneg = a4;
         double step = 1.0;
-        xpos = xneg + step;
-        for (int j = 0; j < 1100 && !(exp_hs_value(c, xpos) > 0.0); ++j) {
+        xpos = fmin(xneg + step, R);
+        while (!(exp_hs_value(c, xpos) > 0.0) && xpos < R) {
             step *= 2.0;
-            xpos = xneg + step;
+            xpos = fmin(xneg + step, R);
         }
     }
     const double rho = exp_root(c, xneg, xpos);

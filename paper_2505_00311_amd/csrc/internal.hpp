@@ -84,7 +84,7 @@ struct DevState {
     double nx2, ny2, ip;              // reductions of the last attempt
     long long n_iter, kin, attempts_total, max_iter;
     int attempts_cur, halt, skip_update, status;
-    int check_every, max_attempts, beta_mode, pad0;
+    int check_every, max_attempts, beta_mode, step_mode;
     double beta_const, beta_grow, beta_shrink, step_reduce_exp, step_grow_exp;
     long long log_cap;
     int *log_attempts;
@@ -138,6 +138,8 @@ void check_finite(const double *a, int64_t n, int *flag, hipStream_t s);
 void div_vec(const double *a, const double *b, double *out, int64_t n, hipStream_t s);
 void mul_vec(const double *a, const double *b, double *out, int64_t n, hipStream_t s);
 void copy_vec(const double *a, double *out, int64_t n, hipStream_t s);
+// v = w / sqrt(*sumsq) on the device (no host round trip)
+void scale_by_inv_sqrt(const double *w, const double *sumsq, double *v, int64_t n, hipStream_t s);
 
 // cone_pass.hip
 struct PrimalArgs {

@@ -50,8 +50,9 @@ __global__ __launch_bounds__(kBlock) void decide_kernel(DevState *__restrict__ s
     const double nn = (double)(st->attempts_total + st->attempts_cur + 1);
     const double e1 = (1.0 - pow(nn, -st->step_reduce_exp)) * ebar;
     const double e2 = (1.0 + pow(nn, -st->step_grow_exp)) * eta;
-    const double enew = e1 < e2 ? e1 : e2;
-    if (eta <= ebar) {
+    const bool fixed = st->step_mode == 1;   // fixed step: every attempt is accepted
+    const double enew = fixed ? eta : (e1 < e2 ? e1 : e2);
+    if (fixed || eta <= ebar) {
         const double r = sqrt(omega * nx2 + ny2 / omega);
         double beta;
         if (st->beta_mode == 1)

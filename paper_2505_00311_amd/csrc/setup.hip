@@ -282,4 +282,15 @@ void copy_vec(const double *a, double *out, int64_t n, hipStream_t s) {
     PDCS_HIP(hipGetLastError());
 }
 
+__global__ void scale_inv_sqrt_kernel(const double *w, const double *sumsq, double *v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double lam = sqrt(*sumsq);
+    if (i < n && lam > 0.0) v[i] = w[i] / lam;
+}
+void scale_by_inv_sqrt(const double *w, const double *sumsq, double *v, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(scale_inv_sqrt_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, w, sumsq, v, n);
+    PDCS_HIP(hipGetLastError());
+}
+
 }  // namespace pdcs

@@ -252,6 +252,24 @@ def test_exp_extreme_inputs_stay_finite(orc):
         assert np.linalg.norm(v - p) <= np.linalg.norm(v) * (1 + 1e-12)
 
 
+def test_exp_far_brackets_stay_finite(orc):
+    """Entries of very different magnitude put a3 or a4 of eq. (lrho_urho) far
+    beyond |rho| = 700 (the case met in the large workload's dual exp rows:
+    r = -1.7e-178, s = 12.4, t = -5.8e-189).  The projection must stay finite
+    and never be farther from v than the origin is."""
+    p, _ = orc.proj_exp_dual(np.array([-1.66653501e-178, 1.24179468e1, -5.81330326e-189]),
+                             np.array([3.01210793, 0.96024127, 0.39153593]))
+    assert np.all(np.isfinite(p))
+    rng = np.random.default_rng(18)
+    for _ in range(20000):
+        v = rng.standard_normal(3) * 10.0 ** rng.uniform(-300, 300, 3)
+        d = 10 ** rng.uniform(-3, 3, 3)
+        for fn in (orc.proj_exp, orc.proj_exp_dual):
+            q, _ = fn(v, d)
+            assert np.all(np.isfinite(q)), (v, d)
+            assert np.linalg.norm(v - q) <= np.linalg.norm(v) * (1 + 1e-12)
+
+
 def test_exp_idempotent(orc):
     rng = np.random.default_rng(16)
     for _ in range(500):

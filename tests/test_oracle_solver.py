@@ -210,3 +210,23 @@ def test_solve_decision_log_is_consistent(orc):
     assert (lg["check_code"][63] - 1) // 2 % 4 != 0
     # the snapshot at iteration 65 follows a restart, so it differs from 64's
     assert not np.allclose(lg["snap_x"][1], lg["snap_x"][2])
+
+
+def test_fixed_step_uses_the_spectral_norm(orc):
+    """step_mode 1: eta = step_fixed / ||E G F||_2, the norm from power
+    iteration; it can only underestimate the norm, and 100 iterations get
+    within a few percent on these matrices."""
+    for seed in (0, 3):
+        inst = I.small_mixed(seed)
+        e, f = orc.scaling(inst)
+        sig = np.linalg.norm(inst.dense() * e[:, None] * f[None, :], 2)
+        r = orc.solve(inst, orc.default_settings(step_mode=1, max_iter=64))
+        est = 0.9 / r["eta"]
+        assert est <= sig * (1 + 1e-12) and est >= 0.95 * sig, (est, sig)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_fixed_step_solves(orc, seed):
+    inst = I.small_mixed(seed)
+    r = orc.solve(inst, orc.default_settings(step_mode=1, max_iter=400000))
+    _check_solution(inst, r, 1e-6)
