@@ -256,25 +256,24 @@ int orc_proj_exp(const double *v, const double *d, double *out) {
         }
     }
     double rho = exp_root(&c, xneg, xpos);
-    double sp, rd;
-    exp_sp_rd(&c, rho, &sp, &rd);
-    /* eq. (vpvd_defn): v_p = s_p (dr rho, ds, dt e^rho).  For rho > 0 the factor
-     * e^rho would amplify the rounding error of s_p (which vanishes at a4), so
-     * there t_p = dt e^rho s_p is taken from the t equation (v_p + v_d)_t = t0
-     * that holds at the root, t_p = t0 + e^-rho r_d / dt, and s_p = e^-rho t_p / dt
-     * (reading; it keeps v_p on the boundary ray of D K_exp). */
-    double tp;
+    /* eq. (vpvd_defn): v_p = s_p w(rho), w = (dr rho, ds, dt e^rho).  At the root
+     * v_d = v0 - v_p is orthogonal to w (Step 1 of the proof of Theorem 3), so
+     * s_p = <v0, w> / ||w||^2: the projection of v0 onto the ray of w.  Evaluated
+     * this way (reading) v_p carries an absolute error of order eps ||v0||,
+     * where the closed form of eq. (sp_rd) cancels near a3 or a4; for rho > 0
+     * the ray is scaled by e^-rho so that nothing overflows. */
+    double w0, w1, w2;
     if (rho > 0.0) {
         double em = exp(-rho);
-        tp = t0 + em * rd / dt;
-        if (tp < 0.0) tp = 0.0;
-        sp = em * tp / dt;
+        w0 = dr * rho * em, w1 = ds * em, w2 = dt;
     } else {
-        tp = dt * exp(rho) * sp;
+        w0 = dr * rho, w1 = ds, w2 = dt * exp(rho);
     }
-    out[0] = dr * rho * sp;
-    out[1] = ds * sp;
-    out[2] = tp;
+    double cf = (r0 * w0 + s0 * w1 + t0 * w2) / (w0 * w0 + w1 * w1 + w2 * w2);
+    if (!(cf > 0.0)) cf = 0.0;
+    out[0] = cf * w0;
+    out[1] = cf * w1;
+    out[2] = cf * w2;
     return 4;
 }
 

@@ -45,7 +45,9 @@ struct DevMem {
         void *p = nullptr;
         const size_t bytes = sizeof(T) * (size_t)(n > 0 ? n : 1);
         hipError_t e = hipMalloc(&p, bytes);
-        if (e != hipSuccess) fail(PDCS_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        if (e != hipSuccess)
+            fail(e == hipErrorOutOfMemory ? PDCS_ERR_OOM : PDCS_ERR_HIP,
+                 "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
         ptrs.push_back(p);
         return (T *)p;
     }
@@ -90,7 +92,16 @@ static HostPlan build_plan(int64_t base, int64_t n_box, const std::vector<int32_
             elem.push_back(Tile{kind, (int32_t)std::min<int64_t>(kElemPerTile, len - o), start + o});
     };
     push_run(kTileBox, 0, n_box);
-    std::vector<std::pair<int64_t, int64_t>> small_soc, big_soc;
+    // SOC size classes: lanes per block 8, 16, 32, 64 (1 entry per lane), then
+    // one wavefront with 2 or 4 entries per lane, then a workgroup per block
+    constexpr int kClasses = 7;
+    const int class_kind[kClasses] = {kTileSoc8, kTileSoc16, kTileSoc32, kTileSoc64,
+                                      kTileSoc128, kTileSoc256, kTileSocBlock};
+    const int class_per_tile[kClasses] = {32, 16, 8, 4, 4, 4, 1};
+    auto soc_class = [](int64_t d) {
+        return d <= 8 ? 0 : d <= 16 ? 1 : d <= 32 ? 2 : d <= 64 ? 3 : d <= 128 ? 4 : d <= 256 ? 5 : 6;
+    };
+    std::vector<std::pair<int64_t, int64_t>> soc[kClasses];
     std::vector<int64_t> ep, ed;
     int run_kind = -1;
     int64_t run_start = 0, run_len = 0, off = base;
@@ -106,7 +117,7 @@ static HostPlan build_plan(int64_t base, int64_t n_box, const std::vector<int32_
                 run_kind = k, run_start = off, run_len = d;
             }
         } else if (t == kSoc) {
-            (d <= kSocWaveMax ? small_soc : big_soc).push_back({off, d});
+            soc[soc_class(d)].push_back({off, d});
         } else if (t == kExp) {
             ep.push_back(off);
         } else {
@@ -115,13 +126,15 @@ static HostPlan build_plan(int64_t base, int64_t n_box, const std::vector<int32_
         off += d;
     }
     if (run_len) push_run(run_kind, run_start, run_len);
-    for (auto &p : small_soc) P.soc_off.push_back(p.first), P.soc_dim.push_back((int32_t)p.second);
-    for (auto &p : big_soc) P.soc_off.push_back(p.first), P.soc_dim.push_back((int32_t)p.second);
-    const int64_t ns = (int64_t)small_soc.size();
-    for (int64_t i = 0; i < (int64_t)big_soc.size(); ++i) P.tiles.push_back(Tile{kTileSocBlock, 1, ns + i});
-    const int per = kBlock / kWave;
-    for (int64_t i = 0; i < ns; i += per)
-        P.tiles.push_back(Tile{kTileSocWave, (int32_t)std::min<int64_t>(per, ns - i), i});
+    // largest classes first: they run longest
+    for (int c = kClasses - 1; c >= 0; --c) {
+        const int64_t first = (int64_t)P.soc_off.size();
+        for (auto &p : soc[c]) P.soc_off.push_back(p.first), P.soc_dim.push_back((int32_t)p.second);
+        const int64_t cnt = (int64_t)soc[c].size();
+        for (int64_t i = 0; i < cnt; i += class_per_tile[c])
+            P.tiles.push_back(Tile{class_kind[c],
+                                   (int32_t)std::min<int64_t>(class_per_tile[c], cnt - i), first + i});
+    }
     for (auto o : ep) P.exp_off.push_back(o);
     for (auto o : ed) P.exp_off.push_back(o);
     for (int64_t i = 0; i < (int64_t)ep.size(); i += kExpPerTile)
@@ -152,8 +165,12 @@ static SpmvPlan build_spmv_plan(DevMem &mem, const std::vector<int64_t> &rp, hip
     SpmvPlan P;
     const int64_t rows = (int64_t)rp.size() - 1;
     const int64_t nnz = rp.back();
-    P.lanes = choose_lanes(rows > 0 ? (double)nnz / (double)rows : 1.0);
+    const double avg = rows > 0 ? (double)nnz / (double)rows : 0.0;
+    P.lanes = choose_lanes(rows > 0 ? avg : 1.0);
     P.long_thr = std::max<int64_t>(64, 32 * P.lanes);
+    P.stream = avg < 12.0 ? 1 : 0;
+    if (P.stream) P.long_thr = std::min<int64_t>(P.long_thr, kStreamNnz);
+    // rows longer than long_thr: chunks of kLongChunk entries
     std::vector<int32_t> lr, crow;
     std::vector<int64_t> cptr{0}, cbeg;
     for (int64_t i = 0; i < rows; ++i) {
@@ -164,17 +181,40 @@ static SpmvPlan build_spmv_plan(DevMem &mem, const std::vector<int64_t> &rp, hip
         for (int64_t b = rp[i]; b < rp[i + 1]; b += kLongChunk) crow.push_back(li), cbeg.push_back(b);
         cptr.push_back((int64_t)cbeg.size());
     }
+    // CSR-stream row ranges (start, end) of consecutive short rows whose entries
+    // fit in kStreamNnz; a long row closes the range
+    std::vector<int64_t> sb;
+    if (P.stream) {
+        int64_t start = 0, acc = 0;
+        for (int64_t i = 0; i < rows; ++i) {
+            const int64_t len = rp[i + 1] - rp[i];
+            if (len > P.long_thr) {
+                if (i > start) sb.push_back(start), sb.push_back(i);
+                start = i + 1, acc = 0;
+                continue;
+            }
+            if (acc + len > kStreamNnz) {
+                sb.push_back(start), sb.push_back(i);
+                start = i, acc = 0;
+            }
+            acc += len;
+        }
+        if (rows > start) sb.push_back(start), sb.push_back(rows);
+    }
     P.n_long = (int64_t)lr.size();
     P.n_chunks = (int64_t)cbeg.size();
+    P.n_sblocks = (int64_t)sb.size() / 2;
     P.long_rows = mem.alloc<int32_t>(P.n_long);
     P.long_chunk_ptr = mem.alloc<int64_t>(P.n_long + 1);
     P.chunk_row = mem.alloc<int32_t>(P.n_chunks);
     P.chunk_begin = mem.alloc<int64_t>(P.n_chunks);
     P.chunk_part = mem.alloc<double>(P.n_chunks);
+    P.sblock = mem.alloc<int64_t>((int64_t)sb.size());
     h2d(P.long_rows, lr.data(), P.n_long, s);
     h2d(P.long_chunk_ptr, cptr.data(), P.n_long + 1, s);
     h2d(P.chunk_row, crow.data(), P.n_chunks, s);
     h2d(P.chunk_begin, cbeg.data(), P.n_chunks, s);
+    h2d(P.sblock, sb.data(), (int64_t)sb.size(), s);
     PDCS_HIP(hipStreamSynchronize(s));
     return P;
 }

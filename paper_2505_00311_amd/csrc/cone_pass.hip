@@ -5,10 +5,11 @@
 // (PDCS_terminate_tolerance).
 //
 // Each workgroup reads one tile of the side's cone plan: a run of elementwise
-// entries (box / zero / free / nonnegative, thread per entry), up to four SOC
-// blocks of dim <= 256 (one wavefront each), one larger SOC block (whole
-// workgroup), or up to 256 exponential cones (one thread each) -- the
-// thread-, block- and grid-level strategies of Section 4 mapped to CDNA.
+// entries (box / zero / free / nonnegative, thread per entry), SOC blocks of
+// one size class (an aligned group of 8, 16, 32 or 64 lanes per block, up to
+// 256 entries), one larger SOC block (whole workgroup), or up to 64
+// exponential cones (one thread each) -- the thread-, block- and grid-level
+// strategies of Section 4 mapped to CDNA wavefronts.
 #include "cones_device.hpp"
 
 namespace pdcs {
@@ -240,6 +241,30 @@ __device__ void soc_block(Op &op, int64_t off, int dim, Acc &acc) {
     }
 }
 
+// --------------------------------------- lane-group-per-SOC block (dim <= 256)
+template <class Op, int LPB, int R>
+__device__ __forceinline__ void soc_tile(Op &op, const Tile &tl, const int64_t *__restrict__ soc_off,
+                                         const int32_t *__restrict__ soc_dim, Acc &acc) {
+    const int gi = threadIdx.x / LPB, g = threadIdx.x % LPB;
+    if (gi >= tl.count) return;
+    const int64_t b = tl.start + gi;
+    const int64_t off = soc_off[b];
+    const int dim = soc_dim[b];
+    double v[R], d[R], p[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = g + LPB * r;
+        v[r] = e < dim ? op.load(off + e) : 0.0;
+        d[r] = e < dim ? op.scale(off + e) : 1.0;
+    }
+    soc_project_group<LPB, R>(dim, v, d, p);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = g + LPB * r;
+        if (e < dim) op.store(off + e, v[r], p[r], acc);
+    }
+}
+
 // ------------------------------------------------------------------ kernel
 template <class Op, bool DUAL>
 __global__ __launch_bounds__(kBlock) void cone_pass_kernel(Op op, const Tile *__restrict__ tiles,
@@ -278,28 +303,12 @@ __global__ __launch_bounds__(kBlock) void cone_pass_kernel(Op op, const Tile *__
             op.store(j, v, v > 0.0 ? v : 0.0, acc);
         }
         break;
-    case kTileSocWave: {
-        const int w = tid / kWave, lane = tid % kWave;
-        if (w < tl.count) {
-            const int64_t b = tl.start + w;
-            const int64_t off = soc_off[b];
-            const int dim = soc_dim[b];
-            double v[kSocRegs], d[kSocRegs], p[kSocRegs];
-#pragma unroll
-            for (int r = 0; r < kSocRegs; ++r) {
-                const int e = lane + kWave * r;
-                v[r] = e < dim ? op.load(off + e) : 0.0;
-                d[r] = e < dim ? op.scale(off + e) : 1.0;
-            }
-            soc_project_wave(dim, v, d, p);
-#pragma unroll
-            for (int r = 0; r < kSocRegs; ++r) {
-                const int e = lane + kWave * r;
-                if (e < dim) op.store(off + e, v[r], p[r], acc);
-            }
-        }
-        break;
-    }
+    case kTileSoc8: soc_tile<Op, 8, 1>(op, tl, soc_off, soc_dim, acc); break;
+    case kTileSoc16: soc_tile<Op, 16, 1>(op, tl, soc_off, soc_dim, acc); break;
+    case kTileSoc32: soc_tile<Op, 32, 1>(op, tl, soc_off, soc_dim, acc); break;
+    case kTileSoc64: soc_tile<Op, 64, 1>(op, tl, soc_off, soc_dim, acc); break;
+    case kTileSoc128: soc_tile<Op, 64, 2>(op, tl, soc_off, soc_dim, acc); break;
+    case kTileSoc256: soc_tile<Op, 64, 4>(op, tl, soc_off, soc_dim, acc); break;
     case kTileSocBlock:
         soc_block(op, soc_off[tl.start], soc_dim[tl.start], acc);
         break;

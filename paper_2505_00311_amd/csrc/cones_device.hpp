@@ -3,8 +3,9 @@
 //   exponential cone  : Section 3 Theorem 2 / Appendix A.2 Theorem 3, one thread
 //                       per cone (the thread-wise strategy of Section 4, Table 3);
 //   dual exponential  : Appendix A.2 Remark, Proj_{DK*}(v) = v + Proj_{D^-1 K}(-v);
-//   second-order cone : Section 3 Theorem 1, one wavefront per block (dims up
-//                       to 256, values in VGPRs) or one workgroup per block.
+//   second-order cone : Section 3 Theorem 1, an aligned group of 8..64 lanes per
+//                       block for dims up to 256 (values in VGPRs, several
+//                       blocks per wavefront) or one workgroup per block.
 //
 // The fourth case of Theorem 1 is solved in s = t / (1 - 2 lambda) on the
 // bracket (max(t,0), ||(t,x)||], where g(s) = sum_i (x_i dh_i)^2 / (dh_i^2 + a)^2
@@ -151,22 +152,22 @@ __device__ void exp_project(double r0, double s0, double t0, double dr, double d
         }
     }
     const double rho = exp_root(c, xneg, xpos);
-    double sp, rd;
-    exp_sprd(c, rho, sp, rd);
-    // v_p = s_p (dr rho, ds, dt e^rho); for rho > 0 t_p and s_p come from the
-    // t equation at the root, where e^rho would amplify s_p's rounding.
-    double tp;
+    // v_p = s_p w(rho), w = (dr rho, ds, dt e^rho); at the root v0 - v_p is
+    // orthogonal to w, so s_p = <v0, w>/||w||^2 (projection of v0 onto the ray
+    // of w), which avoids the cancellation of eq. (sp_rd) near a3 and a4; the
+    // ray is scaled by e^-rho for rho > 0 so that nothing overflows.
+    double w0, w1, w2;
     if (rho > 0.0) {
         const double em = exp(-rho);
-        tp = t0 + em * rd / dt;
-        if (tp < 0.0) tp = 0.0;
-        sp = em * tp / dt;
+        w0 = dr * rho * em, w1 = ds * em, w2 = dt;
     } else {
-        tp = dt * exp(rho) * sp;
+        w0 = dr * rho, w1 = ds, w2 = dt * exp(rho);
     }
-    pr = dr * rho * sp;
-    ps = ds * sp;
-    pt = tp;
+    double cf = (r0 * w0 + s0 * w1 + t0 * w2) / (w0 * w0 + w1 * w1 + w2 * w2);
+    if (!(cf > 0.0)) cf = 0.0;
+    pr = cf * w0;
+    ps = cf * w1;
+    pt = cf * w2;
 }
 
 __device__ __forceinline__ void exp_dual_project(double r0, double s0, double t0, double dr,
@@ -178,18 +179,32 @@ __device__ __forceinline__ void exp_dual_project(double r0, double s0, double t0
 }
 
 // ------------------------------------------------------- second-order cone
-// One block per wavefront; lane l holds entries l + 64 r, r < kSocRegs; entry
-// 0 (t) is in lane 0.  Inactive slots carry v = 0, d = 1.
-__device__ void soc_project_wave(int dim, const double (&v)[kSocRegs],
-                                 const double (&d)[kSocRegs], double (&p)[kSocRegs]) {
+// Sum over an aligned group of LPB lanes (a power of two <= 64); every lane of
+// the group receives the same bits.
+template <int LPB>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int off = LPB / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// One block per aligned group of LPB lanes; lane g of the group holds entries
+// g + LPB r, r < R; entry 0 (t) is in the group's first lane.  Inactive slots
+// carry v = 0, d = 1.  Several blocks share a wavefront when LPB < 64, so small
+// cones need fewer exchange steps per reduction and keep more lanes busy.
+template <int LPB, int R>
+__device__ void soc_project_group(int dim, const double (&v)[R], const double (&d)[R],
+                                  double (&p)[R]) {
     const int lane = threadIdx.x % kWave;
-    const double t = __shfl(v[0], 0, kWave);
-    const double d0 = __shfl(d[0], 0, kWave);
-    double x[kSocRegs], dh[kSocRegs];
+    const int g = lane % LPB;
+    const int base = lane - g;
+    const double t = __shfl(v[0], base, kWave);
+    const double d0 = __shfl(d[0], base, kWave);
+    double x[R], dh[R];
     double snd = 0.0, sndi = 0.0, snx = 0.0;
 #pragma unroll
-    for (int r = 0; r < kSocRegs; ++r) {
-        const int e = lane + kWave * r;
+    for (int r = 0; r < R; ++r) {
+        const int e = g + LPB * r;
         const bool on = e >= 1 && e < dim;
         x[r] = on ? v[r] : 0.0;
         dh[r] = on ? d[r] / d0 : 1.0;
@@ -197,35 +212,35 @@ __device__ void soc_project_wave(int dim, const double (&v)[kSocRegs],
         sndi += (x[r] / dh[r]) * (x[r] / dh[r]);
         snx += x[r] * x[r];
     }
-    const double nd = sqrt(wave_sum(snd));
-    const double ndi = sqrt(wave_sum(sndi));
-    const double nx2 = wave_sum(snx);
+    const double nd = sqrt(group_sum<LPB>(snd));
+    const double ndi = sqrt(group_sum<LPB>(sndi));
+    const double nx2 = group_sum<LPB>(snx);
     if (t <= 0.0 && nd <= -t) {                           // case 1: polar -> 0
 #pragma unroll
-        for (int r = 0; r < kSocRegs; ++r) p[r] = 0.0;
+        for (int r = 0; r < R; ++r) p[r] = 0.0;
         return;
     }
     if (ndi <= t) {                                       // case 2: inside
 #pragma unroll
-        for (int r = 0; r < kSocRegs; ++r) p[r] = v[r];
+        for (int r = 0; r < R; ++r) p[r] = v[r];
         return;
     }
     if (t == 0.0) {                                       // case 3: lambda = 1/2
         double s2 = 0.0;
 #pragma unroll
-        for (int r = 0; r < kSocRegs; ++r) {
+        for (int r = 0; r < R; ++r) {
             const double q = x[r] / (dh[r] + 1.0 / dh[r]);
             s2 += q * q;
             p[r] = x[r] / (1.0 + 1.0 / (dh[r] * dh[r]));
         }
-        s2 = sqrt(wave_sum(s2));
-        if (lane == 0) p[0] = s2;
+        s2 = sqrt(group_sum<LPB>(s2));
+        if (g == 0) p[0] = s2;
         return;
     }
     // case 4: root of g(s) on (max(t,0), ||(t,x)||]
-    double w[kSocRegs], h2[kSocRegs];
+    double w[R], h2[R];
 #pragma unroll
-    for (int r = 0; r < kSocRegs; ++r) {
+    for (int r = 0; r < R; ++r) {
         w[r] = (x[r] * dh[r]) * (x[r] * dh[r]);
         h2[r] = dh[r] * dh[r];
     }
@@ -238,14 +253,14 @@ __device__ void soc_project_wave(int dim, const double (&v)[kSocRegs],
         const double a = 1.0 - t / ss;
         double g1 = 0.0, g2 = 0.0;
 #pragma unroll
-        for (int r = 0; r < kSocRegs; ++r) {
+        for (int r = 0; r < R; ++r) {
             const double iq = 1.0 / (h2[r] + a);
             const double u = w[r] * iq * iq;
             g1 += u;
             g2 += u * iq;
         }
-        g1 = wave_sum(g1);
-        g2 = wave_sum(g2);
+        g1 = group_sum<LPB>(g1);
+        g2 = group_sum<LPB>(g2);
         f = g1 - ss * ss;
         df = -2.0 * (t / (ss * ss)) * g2 - 2.0 * ss;
     };
@@ -273,8 +288,8 @@ __device__ void soc_project_wave(int dim, const double (&v)[kSocRegs],
     }
     const double a = 1.0 - t / s;
 #pragma unroll
-    for (int r = 0; r < kSocRegs; ++r) p[r] = x[r] / (1.0 + a / h2[r]);
-    if (lane == 0) p[0] = s;
+    for (int r = 0; r < R; ++r) p[r] = x[r] / (1.0 + a / h2[r]);
+    if (g == 0) p[0] = s;
 }
 
 }  // namespace pdcs

@@ -16,10 +16,9 @@ namespace pdcs {
 
 constexpr int kBlock = 256;          // threads per workgroup of every pass kernel
 constexpr int kWave = 64;            // CDNA wavefront
-constexpr int kSocWaveMax = 256;     // SOC blocks up to this dim: one wavefront each
-constexpr int kSocRegs = kSocWaveMax / kWave;
+constexpr int kSocWaveMax = 256;     // SOC blocks up to this dim: a lane group each
 constexpr int kElemPerTile = 2048;   // entries per elementwise tile
-constexpr int kExpPerTile = kBlock;  // exponential cones per tile (one thread each)
+constexpr int kExpPerTile = 64;      // exponential cones per tile (one thread each)
 constexpr int kPartials = 6;         // per-tile partial slots: 3 sums, 3 maxima
 
 // cone type codes of the C ABI
@@ -31,10 +30,15 @@ enum TileKind : int32_t {
     kTileZero = 1,
     kTileFree = 2,
     kTileNonneg = 3,
-    kTileSocWave = 4,
-    kTileSocBlock = 5,
+    kTileSocBlock = 5,   // one SOC block per workgroup (dim > 256)
     kTileExp = 6,
-    kTileExpDual = 7
+    kTileExpDual = 7,
+    kTileSoc8 = 8,       // SOC blocks of dim <= 8, 8 lanes each (32 per tile)
+    kTileSoc16 = 9,      // dim <= 16, 16 lanes each
+    kTileSoc32 = 10,     // dim <= 32
+    kTileSoc64 = 11,     // dim <= 64, one wavefront each
+    kTileSoc128 = 12,    // dim <= 128, one wavefront, 2 entries per lane
+    kTileSoc256 = 13     // dim <= 256, one wavefront, 4 entries per lane
 };
 
 struct Tile {
@@ -63,8 +67,12 @@ struct Csr {
 // longer than long_thr are cut into chunks of kLongChunk entries, one
 // workgroup per chunk, and summed per row in chunk order.
 constexpr int64_t kLongChunk = 4096;
+constexpr int kStreamNnz = 1024;   // entries per workgroup of the CSR-stream kernel
 struct SpmvPlan {
     int lanes = 8;
+    int stream = 0;                    // 1: CSR-stream kernel for the short rows
+    int64_t n_sblocks = 0;
+    int64_t *sblock = nullptr;         // [2 n_sblocks] row ranges [sblock[2b], sblock[2b+1])
     int64_t long_thr = 0;
     int64_t n_long = 0;
     int64_t n_chunks = 0;

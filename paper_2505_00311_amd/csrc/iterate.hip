@@ -1,12 +1,9 @@
 // iterate.hip -- the scalar and elementwise steps of Algorithm 1 that sit
 // between the projection passes and the sparse products:
-//   decide   : AdaptiveStepPDHG's accept/reject, the next step size and the
-//              AdaptiveReflectionParameter, taken by one workgroup on device
-//              so the host never waits inside an iteration;
 //   halpern  : ReflectedHalpern (and the same affine map applied to the kept
 //              products G~x and G~^T y) fused with the weighted average;
 //   reduce_kkt, restart_copy, unscale: pieces of the periodic check.
-#include "device_common.hpp"
+#include "decide_device.hpp"
 
 namespace pdcs {
 
@@ -15,83 +12,16 @@ static unsigned grid_for(int64_t n) {
     return (unsigned)(g < 1 ? 1 : g);
 }
 
-// Step-size rule (reading: PDLP's): eta_bar = ||dz||_omega^2 / (2 |<dy, G~ dx>|),
-// accept when eta <= eta_bar; eta' = min((1 - N^-a) eta_bar, (1 + N^-b) eta)
-// with N = 1 + attempts so far.  Reflection parameter (reading): grows by
-// beta_grow (capped at 1) while ||dz||_omega falls, else shrinks by beta_shrink.
-__global__ __launch_bounds__(kBlock) void decide_kernel(DevState *__restrict__ st,
-                                                        const double *__restrict__ px, int64_t ntx,
-                                                        const double *__restrict__ py,
-                                                        int64_t nty) {
+// The step decision, one workgroup after the dual pass (a kernel boundary
+// orders the passes' partials before it; a fenced last-workgroup hand-off
+// would write back an XCD's L2 once per workgroup).
+__global__ __launch_bounds__(kBlock) void decide_kernel(DevState *st, const double *px, int64_t ntx,
+                                                        const double *py, int64_t nty) {
     if (st->halt) {
         if (threadIdx.x == 0) st->skip_update = 1;
         return;
     }
-    double v[3] = {0.0, 0.0, 0.0};
-    for (int64_t t = threadIdx.x; t < ntx; t += kBlock) v[0] += px[t * kPartials + 0];
-    for (int64_t t = threadIdx.x; t < nty; t += kBlock) {
-        v[1] += py[t * kPartials + 0];
-        v[2] += py[t * kPartials + 1];
-    }
-    block_sum_all<3>(v);
-    if (threadIdx.x != 0) return;
-    const double nx2 = v[0], ny2 = v[1], ip = v[2];
-    st->nx2 = nx2, st->ny2 = ny2, st->ip = ip;
-    st->attempts_cur += 1;
-    const double omega = st->omega, eta = st->eta;
-    const double den = 2.0 * fabs(ip);
-    const double ebar = den > 0.0 ? (omega * nx2 + ny2 / omega) / den : INFINITY;
-    if (ebar != ebar) {
-        st->status = 3;
-        st->halt = 1;
-        st->skip_update = 1;
-        return;
-    }
-    const double nn = (double)(st->attempts_total + st->attempts_cur + 1);
-    const double e1 = (1.0 - pow(nn, -st->step_reduce_exp)) * ebar;
-    const double e2 = (1.0 + pow(nn, -st->step_grow_exp)) * eta;
-    const bool fixed = st->step_mode == 1;   // fixed step: every attempt is accepted
-    const double enew = fixed ? eta : (e1 < e2 ? e1 : e2);
-    if (fixed || eta <= ebar) {
-        const double r = sqrt(omega * nx2 + ny2 / omega);
-        double beta;
-        if (st->beta_mode == 1)
-            beta = st->beta_const;
-        else
-            beta = r <= st->r_prev ? fmin(1.0, st->beta_grow * st->beta_prev)
-                                   : st->beta_shrink * st->beta_prev;
-        st->r_prev = r;
-        st->beta_prev = beta;
-        st->beta = beta;
-        const long long k = st->kin;
-        st->ha = (double)(k + 1) / (double)(k + 2);
-        st->hb = 1.0 / (double)(k + 2);
-        st->eta_used = eta;
-        st->eta_sum += eta;
-        st->eta = enew;
-        const long long it = st->n_iter;
-        if (it < st->log_cap) {
-            st->log_attempts[it] = st->attempts_cur;
-            st->log_eta[it] = eta;
-            st->log_beta[it] = beta;
-            st->log_omega[it] = omega;
-        }
-        st->attempts_total += st->attempts_cur;
-        st->attempts_cur = 0;
-        st->n_iter = it + 1;
-        st->kin = k + 1;
-        st->skip_update = 0;
-        if ((k + 1) % st->check_every == 0 || it + 1 >= st->max_iter) st->halt = 1;
-    } else {
-        st->eta = enew;
-        st->skip_update = 1;
-        if (st->attempts_cur >= st->max_attempts) {
-            st->status = 3;
-            st->halt = 1;
-        }
-    }
-    st->tau = st->eta / st->omega;
-    st->sigma = st->eta * st->omega;
+    decide_body(st, px, ntx, py, nty);
 }
 
 void decide(DevState *st, const double *px, int64_t ntx, const double *py, int64_t nty,

@@ -323,3 +323,15 @@ def ball_socp(seed, n=4):
                     xcone_type=np.zeros(0, np.int32), xcone_dim=np.zeros(0, np.int64),
                     rcone_type=np.array([SOC], np.int32), rcone_dim=np.array([n + 1], np.int64),
                     name=f"ball_socp({seed})", meta={"W": W, "x0": x0, "r": r})
+
+
+def box_only(c=(1.0, -2.0, 0.5)):
+    """A problem without rows: min c^T x over the box [-1, 1]^n; x* = -sign(c)."""
+    c = np.asarray(c, dtype=np.float64)
+    n = c.size
+    x = -np.sign(c)
+    return Instance(n=n, m=0, n_box=n, row_ptr=np.zeros(1, np.int64), col=np.zeros(0, np.int32),
+                    val=np.zeros(0), c=c, h=np.zeros(0), l=-np.ones(n), u=np.ones(n),
+                    xcone_type=np.zeros(0, np.int32), xcone_dim=np.zeros(0, np.int64),
+                    rcone_type=np.zeros(0, np.int32), rcone_dim=np.zeros(0, np.int64),
+                    x_star=x, y_star=np.zeros(0), opt=float(c @ x), name="box_only")

@@ -72,6 +72,13 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise PdcsError(f"{LIB_PATH} is not built; run `python -m paper_2505_00311_amd.build`")
+    # torch's HIP runtime must be the process's one: torch asks for
+    # libamdhip64.so, which would not match an already loaded libamdhip64.so.7,
+    # and two runtimes cannot share the device
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     L.pdcs_settings_default.argtypes = [ctypes.POINTER(Settings)]
     L.pdcs_problem_create.argtypes = [ctypes.POINTER(ProblemDesc), _vp, ctypes.POINTER(_vp)]

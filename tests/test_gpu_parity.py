@@ -295,6 +295,17 @@ def test_edge_cases(pd, orc):
         pd.Problem(bad)
 
 
+def test_problem_without_rows(pd, orc):
+    """m = 0: no dual pass, the step decision runs on its own."""
+    inst = I.box_only()
+    prob = pd.Problem(inst)
+    g = prob.solve(pd.settings_default(tol=1e-9))
+    o = orc.solve(inst, orc.default_settings(tol=1e-9))
+    assert g["status"] == 0 and g["iterations"] == o["iterations"]
+    assert np.allclose(g["x"], inst.x_star, atol=1e-8)
+    prob.close()
+
+
 def test_empty_rows_and_columns(pd, orc):
     """Rows and columns without entries (the ball SOCP's first row is empty)."""
     inst = I.ball_socp(1, n=6)

@@ -230,3 +230,10 @@ def test_fixed_step_solves(orc, seed):
     inst = I.small_mixed(seed)
     r = orc.solve(inst, orc.default_settings(step_mode=1, max_iter=400000))
     _check_solution(inst, r, 1e-6)
+
+
+def test_solve_without_rows(orc):
+    inst = I.box_only()
+    r = orc.solve(inst, orc.default_settings(tol=1e-9))
+    assert r["status"] == 0 and r["iterations"] > 0
+    assert np.allclose(r["x"], inst.x_star, atol=1e-8)
