@@ -109,6 +109,7 @@ typedef struct {
     int32_t step_mode;          /* 0: adaptive step of Algorithm 1; 1: fixed step        */
     double step_fixed;          /* fixed step = step_fixed / ||G~||_2 (step_mode 1)      */
     int32_t power_iters;        /* power iterations estimating ||G~||_2 (step_mode 1)    */
+    int32_t use_graph;          /* 1: replay batches of 64 step attempts as a HIP graph  */
 } pdcs_settings;
 
 typedef struct {

@@ -245,7 +245,19 @@ struct pdcs_problem {
     double cinf = 0, hinf = 0;
     int scaled_ruiz = -1, scaled_pc = -1;
     double gmax = 0, cs_norm = 0, hs_norm = 0;
+    // a captured batch of step attempts, replayed on a library stream
+    hipStream_t gstream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    ~pdcs_problem() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (gstream) (void)hipStreamDestroy(gstream);
+    }
 };
+
+constexpr int kGraphBatch = 64;   // step attempts per captured graph
 
 static void validate_cones(int64_t nblk, const int32_t *t, const int64_t *d, int64_t expect,
                            const char *what, std::vector<int32_t> &ot, std::vector<int64_t> &od) {
@@ -472,6 +484,52 @@ static void fill_info(pdcs_info *info, int status, const DevState &hs, long long
     info->setup_s = setup_s, info->solve_s = solve_s;
 }
 
+// One step attempt of Algorithm 1 (see the file header), `batch` times.
+static void enqueue_attempts(pdcs_problem *P, long long batch, hipStream_t s) {
+    const PrimalArgs pa{P->x, P->aty, P->cs, P->ls, P->us, P->dx, P->xh, P->st};
+    const DualArgs da{P->y, P->gxh, P->gx, P->hs, P->dy, P->yh, P->st};
+    const HalpernArgs ha{P->x, P->aty, P->xsum, P->xh, P->atyh, P->xa, P->aty0,
+                         P->y, P->gx, P->ysum, P->yh, P->gxh, P->ya, P->gx0, P->n, P->m, P->st};
+    for (long long b = 0; b < batch; ++b) {
+        pass_primal(P->planX, pa, P->partX, s);
+        spmv(P->Gs, P->pG, P->xh, P->gxh, &P->st->halt, s);
+        pass_dual(P->planY, da, P->partY, s);
+        decide(P->st, P->partX, P->planX.ntiles, P->partY, P->planY.ntiles, s);
+        spmv(P->Gts, P->pGt, P->yh, P->atyh, &P->st->skip_update, s);
+        halpern(ha, s);
+    }
+}
+
+// Captures kGraphBatch attempts once per problem on a library-owned stream
+// (the caller's stream may be the null stream, which cannot be captured).
+static void ensure_graph(pdcs_problem *P) {
+    if (P->gexec) return;
+    if (!P->gstream) PDCS_HIP(hipStreamCreateWithFlags(&P->gstream, hipStreamNonBlocking));
+    if (!P->ev_in) PDCS_HIP(hipEventCreateWithFlags(&P->ev_in, hipEventDisableTiming));
+    if (!P->ev_out) PDCS_HIP(hipEventCreateWithFlags(&P->ev_out, hipEventDisableTiming));
+    hipGraph_t g = nullptr;
+    PDCS_HIP(hipStreamBeginCapture(P->gstream, hipStreamCaptureModeThreadLocal));
+    try {
+        enqueue_attempts(P, kGraphBatch, P->gstream);
+    } catch (...) {
+        (void)hipStreamEndCapture(P->gstream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    PDCS_HIP(hipStreamEndCapture(P->gstream, &g));
+    hipError_t e = hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    PDCS_HIP(e);
+}
+
+static void run_graph(pdcs_problem *P, hipStream_t s) {
+    PDCS_HIP(hipEventRecord(P->ev_in, s));
+    PDCS_HIP(hipStreamWaitEvent(P->gstream, P->ev_in, 0));
+    PDCS_HIP(hipGraphLaunch(P->gexec, P->gstream));
+    PDCS_HIP(hipEventRecord(P->ev_out, P->gstream));
+    PDCS_HIP(hipStreamWaitEvent(s, P->ev_out, 0));
+}
+
 static void solve_impl(pdcs_problem *P, const pdcs_settings *S, const double *x0, const double *y0,
                        double omega0, double *xo, double *yo, pdcs_info *info, pdcs_trace *tr) {
     using clk = std::chrono::steady_clock;
@@ -555,23 +613,18 @@ static void solve_impl(pdcs_problem *P, const pdcs_settings *S, const double *x0
     long long restarts = 0;
     int64_t snap = 0;
     const bool stepwise = tr && (tr->cap > 0 || tr->n_snap > 0);
-    PrimalArgs pa{P->x, P->aty, P->cs, P->ls, P->us, P->dx, P->xh, P->st};
-    DualArgs da{P->y, P->gxh, P->gx, P->hs, P->dy, P->yh, P->st};
-    HalpernArgs ha{P->x, P->aty, P->xsum, P->xh, P->atyh, P->xa, P->aty0,
-                   P->y, P->gx, P->ysum, P->yh, P->gxh, P->ya, P->gx0, n, m, P->st};
     long long prev_attempts = 0;
     while (status < 0) {
         // ---- step attempts until the device asks for a check ----
         while (!hs.halt) {
             const long long todo = S->check_every - hs.kin % S->check_every;
-            const long long batch = stepwise ? 1 : std::max<long long>(1, std::min<long long>(todo, 64));
-            for (long long b = 0; b < batch; ++b) {
-                pass_primal(P->planX, pa, P->partX, s);
-                spmv(P->Gs, P->pG, P->xh, P->gxh, &P->st->halt, s);
-                pass_dual(P->planY, da, P->partY, s);
-                decide(P->st, P->partX, P->planX.ntiles, P->partY, P->planY.ntiles, s);
-                spmv(P->Gts, P->pGt, P->yh, P->atyh, &P->st->skip_update, s);
-                halpern(ha, s);
+            const long long batch =
+                stepwise ? 1 : std::max<long long>(1, std::min<long long>(todo, kGraphBatch));
+            if (S->use_graph && batch == kGraphBatch) {
+                ensure_graph(P);
+                run_graph(P, s);
+            } else {
+                enqueue_attempts(P, batch, s);
             }
             const long long it_before = hs.n_iter;
             d2h(&hs, P->st, 1, s);
@@ -734,6 +787,7 @@ pdcs_status pdcs_settings_default(pdcs_settings *s) {
     s->step_mode = 0;
     s->step_fixed = 0.9;
     s->power_iters = 100;
+    s->use_graph = 1;
     return PDCS_OK;
 }
 

@@ -38,7 +38,8 @@ class Settings(ctypes.Structure):
                 ("beta_shrink", _dbl), ("step_reduce_exp", _dbl), ("step_grow_exp", _dbl),
                 ("restart_sufficient", _dbl), ("restart_necessary", _dbl),
                 ("restart_artificial", _dbl), ("max_attempts", _i32), ("out_on_device", _i32),
-                ("step_mode", _i32), ("step_fixed", _dbl), ("power_iters", _i32)]
+                ("step_mode", _i32), ("step_fixed", _dbl), ("power_iters", _i32),
+                ("use_graph", _i32)]
 
 
 class Info(ctypes.Structure):

@@ -295,6 +295,21 @@ def test_edge_cases(pd, orc):
         pd.Problem(bad)
 
 
+@pytest.mark.parametrize("maker", [lambda: I.small_mixed(2), lambda: I.large_mixed(7, n=20000, m=10000)])
+def test_graph_replay_matches_eager_launches(pd, maker):
+    """Batches of 64 step attempts replayed as a captured HIP graph (10 replays,
+    with the eager check work and a synchronisation between replays) give the
+    same bits as launching the same kernels one by one."""
+    inst = maker()
+    prob = pd.Problem(inst)
+    a = prob.solve(pd.settings_default(max_iter=640, use_graph=1))
+    b = prob.solve(pd.settings_default(max_iter=640, use_graph=0))
+    assert a["iterations"] == b["iterations"] == 640
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["y"], b["y"])
+    assert a["restarts"] == b["restarts"] and a["eta"] == b["eta"]
+    prob.close()
+
+
 def test_problem_without_rows(pd, orc):
     """m = 0: no dual pass, the step decision runs on its own."""
     inst = I.box_only()
