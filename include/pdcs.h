@@ -110,7 +110,21 @@ typedef struct {
     double step_fixed;          /* fixed step = step_fixed / ||G~||_2 (step_mode 1)      */
     int32_t power_iters;        /* power iterations estimating ||G~||_2 (step_mode 1)    */
     int32_t use_graph;          /* 1: replay batches of 64 step attempts as a HIP graph  */
+    int32_t time_kernels;       /* 1: time each step-attempt kernel with HIP events on
+                                 * the solve stream (launches eagerly, no graph); the
+                                 * sums land in pdcs_info.kernel_ms / kernel_launches */
 } pdcs_settings;
+
+/* Kernels of one step attempt, in launch order (indices of pdcs_info.kernel_ms). */
+enum {
+    PDCS_K_PRIMAL = 0,          /* primal update and projection of eq. (5)               */
+    PDCS_K_SPMV_G = 1,          /* G~ x^                                                 */
+    PDCS_K_DUAL = 2,            /* dual update and projection of eq. (5)                 */
+    PDCS_K_DECIDE = 3,          /* step acceptance, next step size, reflection parameter */
+    PDCS_K_SPMV_GT = 4,         /* G~^T y^                                               */
+    PDCS_K_HALPERN = 5,         /* reflected Halpern step and weighted average           */
+    PDCS_K_COUNT = 6
+};
 
 typedef struct {
     int32_t status;             /* PDCS_SOLVE_*                                          */
@@ -123,6 +137,14 @@ typedef struct {
     double omega, eta;          /* final primal weight and step size                     */
     double setup_s;             /* rescaling and initialisation, seconds                 */
     double solve_s;             /* iterations and checks, seconds                        */
+    /* With settings.time_kernels: summed event-to-event milliseconds of each
+     * step-attempt kernel (PDCS_K_*) over the attempts that did work, and the
+     * number of such launches.  Launches on attempts past a due check are
+     * excluded; SPMV_GT and HALPERN count accepted attempts only, but their
+     * sums include the early-exit launches of rejected attempts.  Zero
+     * otherwise. */
+    double kernel_ms[PDCS_K_COUNT];
+    int64_t kernel_launches[PDCS_K_COUNT];
 } pdcs_info;
 
 /* Optional decision log and iterate snapshots of pdcs_solve, host memory.

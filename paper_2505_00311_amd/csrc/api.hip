@@ -249,7 +249,10 @@ struct pdcs_problem {
     hipStream_t gstream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // timing events of settings.time_kernels: (PDCS_K_COUNT + 1) per attempt
+    std::vector<hipEvent_t> tev;
     ~pdcs_problem() {
+        for (hipEvent_t e : tev) (void)hipEventDestroy(e);
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_out) (void)hipEventDestroy(ev_out);
@@ -482,21 +485,36 @@ static void fill_info(pdcs_info *info, int status, const DevState &hs, long long
     info->err_p = k.err_p, info->err_d = k.err_d, info->err_gap = k.err_gap;
     info->omega = hs.omega, info->eta = hs.eta;
     info->setup_s = setup_s, info->solve_s = solve_s;
+    for (int j = 0; j < PDCS_K_COUNT; ++j) info->kernel_ms[j] = 0.0, info->kernel_launches[j] = 0;
 }
 
-// One step attempt of Algorithm 1 (see the file header), `batch` times.
-static void enqueue_attempts(pdcs_problem *P, long long batch, hipStream_t s) {
+// One step attempt of Algorithm 1 (see the file header), `batch` times.  With
+// `ev`, event ev[(PDCS_K_COUNT + 1) b + j] is recorded before kernel j of
+// attempt b and ev[(PDCS_K_COUNT + 1) b + PDCS_K_COUNT] after its last kernel.
+static void enqueue_attempts(pdcs_problem *P, long long batch, hipStream_t s,
+                             const hipEvent_t *ev = nullptr) {
     const PrimalArgs pa{P->x, P->aty, P->cs, P->ls, P->us, P->dx, P->xh, P->st};
     const DualArgs da{P->y, P->gxh, P->gx, P->hs, P->dy, P->yh, P->st};
     const HalpernArgs ha{P->x, P->aty, P->xsum, P->xh, P->atyh, P->xa, P->aty0,
                          P->y, P->gx, P->ysum, P->yh, P->gxh, P->ya, P->gx0, P->n, P->m, P->st};
+    constexpr int E = PDCS_K_COUNT + 1;
+    auto mark = [&](long long b, int j) {
+        if (ev) PDCS_HIP(hipEventRecord(ev[E * b + j], s));
+    };
     for (long long b = 0; b < batch; ++b) {
+        mark(b, PDCS_K_PRIMAL);
         pass_primal(P->planX, pa, P->partX, s);
+        mark(b, PDCS_K_SPMV_G);
         spmv(P->Gs, P->pG, P->xh, P->gxh, &P->st->halt, s);
+        mark(b, PDCS_K_DUAL);
         pass_dual(P->planY, da, P->partY, s);
+        mark(b, PDCS_K_DECIDE);
         decide(P->st, P->partX, P->planX.ntiles, P->partY, P->planY.ntiles, s);
+        mark(b, PDCS_K_SPMV_GT);
         spmv(P->Gts, P->pGt, P->yh, P->atyh, &P->st->skip_update, s);
+        mark(b, PDCS_K_HALPERN);
         halpern(ha, s);
+        mark(b, PDCS_K_COUNT);
     }
 }
 
@@ -614,21 +632,46 @@ static void solve_impl(pdcs_problem *P, const pdcs_settings *S, const double *x0
     int64_t snap = 0;
     const bool stepwise = tr && (tr->cap > 0 || tr->n_snap > 0);
     long long prev_attempts = 0;
+    constexpr int E = PDCS_K_COUNT + 1;
+    double kms[PDCS_K_COUNT] = {};
+    int64_t klaunch[PDCS_K_COUNT] = {};
+    if (S->time_kernels && P->tev.empty()) {
+        P->tev.resize(E * kGraphBatch, nullptr);
+        for (hipEvent_t &e : P->tev) PDCS_HIP(hipEventCreate(&e));
+    }
     while (status < 0) {
         // ---- step attempts until the device asks for a check ----
         while (!hs.halt) {
             const long long todo = S->check_every - hs.kin % S->check_every;
             const long long batch =
                 stepwise ? 1 : std::max<long long>(1, std::min<long long>(todo, kGraphBatch));
-            if (S->use_graph && batch == kGraphBatch) {
+            if (S->time_kernels) {
+                enqueue_attempts(P, batch, s, P->tev.data());
+            } else if (S->use_graph && batch == kGraphBatch) {
                 ensure_graph(P);
                 run_graph(P, s);
             } else {
                 enqueue_attempts(P, batch, s);
             }
             const long long it_before = hs.n_iter;
+            const long long att_before = hs.attempts_total + hs.attempts_cur;
             d2h(&hs, P->st, 1, s);
             PDCS_HIP(hipStreamSynchronize(s));
+            if (S->time_kernels) {
+                // attempts run in order and the device halts only at the end of a
+                // batch, so the first `worked` attempts are the ones that did work
+                const long long worked = hs.attempts_total + hs.attempts_cur - att_before;
+                for (long long b = 0; b < worked && b < batch; ++b)
+                    for (int j = 0; j < PDCS_K_COUNT; ++j) {
+                        float ms = 0.0f;
+                        PDCS_HIP(hipEventElapsedTime(&ms, P->tev[E * b + j], P->tev[E * b + j + 1]));
+                        kms[j] += ms;
+                    }
+                const long long acc = hs.n_iter - it_before;
+                klaunch[PDCS_K_PRIMAL] += worked, klaunch[PDCS_K_SPMV_G] += worked;
+                klaunch[PDCS_K_DUAL] += worked, klaunch[PDCS_K_DECIDE] += worked;
+                klaunch[PDCS_K_SPMV_GT] += acc, klaunch[PDCS_K_HALPERN] += acc;
+            }
             spmv_count += (hs.attempts_total + hs.attempts_cur - prev_attempts) + (hs.n_iter - it_before);
             prev_attempts = hs.attempts_total + hs.attempts_cur;
             if (tr && snap < tr->n_snap && hs.n_iter > it_before && tr->snap_iter[snap] == hs.n_iter) {
@@ -733,6 +776,8 @@ static void solve_impl(pdcs_problem *P, const pdcs_settings *S, const double *x0
     PDCS_HIP(hipStreamSynchronize(s));
     const double solve_s = std::chrono::duration<double>(clk::now() - t_iter).count();
     fill_info(info, status, hs, restarts, spmv_count, kout, setup_s, solve_s);
+    if (info)
+        for (int j = 0; j < PDCS_K_COUNT; ++j) info->kernel_ms[j] = kms[j], info->kernel_launches[j] = klaunch[j];
 }
 
 // --------------------------------------------------------------------- ABI
@@ -788,6 +833,7 @@ pdcs_status pdcs_settings_default(pdcs_settings *s) {
     s->step_fixed = 0.9;
     s->power_iters = 100;
     s->use_graph = 1;
+    s->time_kernels = 0;
     return PDCS_OK;
 }
 

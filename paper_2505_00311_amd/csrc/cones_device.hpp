@@ -180,11 +180,20 @@ __device__ __forceinline__ void exp_dual_project(double r0, double s0, double t0
 
 // ------------------------------------------------------- second-order cone
 // Sum over an aligned group of LPB lanes (a power of two <= 64); every lane of
-// the group receives the same bits.
+// the group receives the same bits, which keeps the lanes of a group on one
+// path through the root finder.  That needs each exchange to add two rounded
+// values: with contraction the compiler may fuse the caller's last product into
+// the first exchange, fma(a, a, round(b*b)) in one lane against
+// fma(b, b, round(a*a)) in its partner, and the two halves of the group then
+// follow different Newton paths.  Contraction is therefore off for these adds.
 template <int LPB>
 __device__ __forceinline__ double group_sum(double v) {
+#pragma clang fp contract(off)
 #pragma unroll
-    for (int off = LPB / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    for (int off = LPB / 2; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off, kWave);
+        v = v + o;
+    }
     return v;
 }
 

@@ -39,14 +39,16 @@ class Settings(ctypes.Structure):
                 ("restart_sufficient", _dbl), ("restart_necessary", _dbl),
                 ("restart_artificial", _dbl), ("max_attempts", _i32), ("out_on_device", _i32),
                 ("step_mode", _i32), ("step_fixed", _dbl), ("power_iters", _i32),
-                ("use_graph", _i32)]
+                ("use_graph", _i32), ("time_kernels", _i32)]
+
+KERNELS = ("primal", "spmv_g", "dual", "decide", "spmv_gt", "halpern")
 
 
 class Info(ctypes.Structure):
     _fields_ = [("status", _i32), ("iterations", _i64), ("attempts", _i64), ("restarts", _i64),
                 ("spmv", _i64), ("pobj", _dbl), ("dobj", _dbl), ("err_p", _dbl), ("err_d", _dbl),
                 ("err_gap", _dbl), ("omega", _dbl), ("eta", _dbl), ("setup_s", _dbl),
-                ("solve_s", _dbl)]
+                ("solve_s", _dbl), ("kernel_ms", _dbl * 6), ("kernel_launches", _i64 * 6)]
 
 
 class Trace(ctypes.Structure):
@@ -214,6 +216,8 @@ class Problem:
                             float(omega0), px, py, ctypes.byref(info),
                             ctypes.byref(tr) if tr is not None else None))
         out = {k: getattr(info, k) for k, _ in Info._fields_}
+        out["kernel_ms"] = dict(zip(KERNELS, info.kernel_ms))
+        out["kernel_launches"] = dict(zip(KERNELS, info.kernel_launches))
         out["x"], out["y"] = xo, yo
         if logs is not None:
             cnt = tr.count
