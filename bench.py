@@ -60,6 +60,27 @@ def kernel_timing(pdcs, prob, iters):
     return us, r
 
 
+def counter_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the summary is missing, covers another kernel, or
+    the kernel's source changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_large_mixed_n1e6.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"<!-- traffic: (\{.*?\}) -->", open(path).read())
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    src = os.path.join(ROOT, rec["source"])
+    if rec["kernel"] != kernel or not os.path.exists(src):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["sha256"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
 def cpu_baseline(inst, iters):
     """The oracle as it stands, single thread, on the first `iters` iterations."""
     import oracle
@@ -85,6 +106,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=64)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--m", type=int, default=500_000)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (the reference kernel "
+                         "for scaling HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -96,6 +120,15 @@ def main():
     from paper_2505_00311_amd import pdcs
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy > 0:
+        nb = args.calibrate_copy << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {nb} bytes 5 times")
+        return
     t = time.perf_counter()
     inst = instances.large_mixed(SEED_LARGE, n=args.n, m=args.m)
     log(f"generated n={inst.n} m={inst.m} nnz={inst.nnz} in {time.perf_counter() - t:.1f}s")
@@ -161,7 +194,7 @@ def main():
         "bytes_per_iteration_model": bytes_iter,
         "roofline": {"bound": "hbm", "kernel": dom_name,
                      "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": counter_traffic(dom),
                      "launch_us": round(kus[dom], 2), "bytes_per_launch": b_dom,
                      "kernel_us": {k: round(v, 2) for k, v in kus.items()},
                      "timing": "HIP events on the solve stream around each launch, "
