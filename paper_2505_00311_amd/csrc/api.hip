@@ -157,6 +157,8 @@ static ConePlan upload_plan(DevMem &mem, const HostPlan &H, hipStream_t s) {
     h2d(P.soc_off, H.soc_off.data(), (int64_t)H.soc_off.size(), s);
     h2d(P.soc_dim, H.soc_dim.data(), (int64_t)H.soc_dim.size(), s);
     h2d(P.exp_off, H.exp_off.data(), (int64_t)H.exp_off.size(), s);
+    P.n_soc = (int64_t)H.soc_off.size();
+    P.n_exp = (int64_t)H.exp_off.size();
     PDCS_HIP(hipStreamSynchronize(s));  // the host vectors die with the caller's frame
     return P;
 }
@@ -375,6 +377,10 @@ static pdcs_problem *create_impl(const pdcs_problem_desc *D, void *stream, bool 
     double **ys[] = {&P->y, &P->ya, &P->yh, &P->gx, &P->gx0, &P->gxh, &P->ysum, &P->tmp_m,
                      &P->yc[0], &P->yc[1], &P->gxc[0], &P->gxc[1]};
     for (double **v : ys) *v = M.alloc<double>(m);
+    for (ConePlan *pl : {&P->planX, &P->planY}) {
+        pl->soc_root = M.alloc<double>(pl->n_soc);
+        pl->exp_root = M.alloc<double>(pl->n_exp);
+    }
     P->partX = M.alloc<double>(P->planX.ntiles * kPartials);
     P->partY = M.alloc<double>(P->planY.ntiles * kPartials);
     P->scal = M.alloc<double>(8);
@@ -573,6 +579,12 @@ static void solve_impl(pdcs_problem *P, const pdcs_settings *S, const double *x0
     if (tr) {
         tr->count = 0;
         for (int64_t i = 0; i < cap; ++i) tr->check_code[i] = 0, tr->check_kkt[i] = 0.0;
+    }
+
+    // no root guesses yet: every solve starts from the same state
+    for (ConePlan *pl : {&P->planX, &P->planY}) {
+        fill(pl->soc_root, pl->n_soc, NAN, s);
+        fill(pl->exp_root, pl->n_exp, NAN, s);
     }
 
     // z^{0,0}: the mapped starting point projected onto X x Y (reading)

@@ -28,8 +28,12 @@ __device__ __forceinline__ int dual_kind(int k) {
 // An op supplies: skip(), load(j) -> value before projection, scale(j) ->
 // diagonal of D (1 when unscaled), box(j, v) -> projection of a box entry,
 // store(j, v, p, acc) / store_box(...), and scratch() for the workgroup SOC path.
+// kWarm: the op runs once per step attempt on slowly changing inputs, so the
+// roots of the SOC and exponential cases are kept per block between launches
+// and start the next root search.
 
 struct OpPrimal {  // x^ = Proj_X(x - tau (c~ - G~^T y)), acc.s0 += (x^ - x)^2
+    static constexpr bool kWarm = true;
     PrimalArgs a;
     double tau;
     __device__ bool skip() const { return a.st->halt != 0; }
@@ -47,6 +51,7 @@ struct OpPrimal {  // x^ = Proj_X(x - tau (c~ - G~^T y)), acc.s0 += (x^ - x)^2
 };
 
 struct OpDual {  // y^ = Proj_Y(y + sigma (h~ - 2 G~x^ + G~x)), acc: |dy|^2, <dy, G~dx>
+    static constexpr bool kWarm = true;
     DualArgs a;
     double sigma;
     __device__ bool skip() const { return a.st->halt != 0; }
@@ -67,6 +72,7 @@ struct OpDual {  // y^ = Proj_Y(y + sigma (h~ - 2 G~x^ + G~x)), acc: |dy|^2, <dy
 };
 
 struct OpCand {  // dst = Proj(src / div), div = 1 or the sum of step weights
+    static constexpr bool kWarm = false;
     CandArgs a;
     double div;
     __device__ bool skip() const { return false; }
@@ -81,6 +87,7 @@ struct OpCand {  // dst = Proj(src / div), div = 1 or the sum of step weights
 
 // rows of eq. (PDCS_terminate_tolerance): r = G x - h (unscaled), P(r) onto K_d^*
 struct OpKktRows {
+    static constexpr bool kWarm = false;
     KktRowsArgs a;
     __device__ bool skip() const { return false; }
     __device__ void begin() {}
@@ -102,6 +109,7 @@ struct OpKktRows {
 // columns: lambda = c - G^T y (unscaled); box entries measured against Lambda
 // of eq. (defn_Lambda1), cone entries against K_p^*
 struct OpKktCols {
+    static constexpr bool kWarm = false;
     KktColsArgs a;
     __device__ bool skip() const { return false; }
     __device__ void begin() {}
@@ -131,6 +139,7 @@ struct OpKktCols {
 };
 
 struct OpProject {
+    static constexpr bool kWarm = false;
     ProjArgs a;
     __device__ bool skip() const { return false; }
     __device__ void begin() {}
@@ -144,7 +153,7 @@ struct OpProject {
 
 // ------------------------------------------------- workgroup-per-SOC block
 template <class Op>
-__device__ void soc_block(Op &op, int64_t off, int dim, Acc &acc) {
+__device__ void soc_block(Op &op, int64_t off, int dim, Acc &acc, double *root) {
     double *buf = op.scratch();
     const int tid = threadIdx.x;
     for (int e = tid; e < dim; e += kBlock) buf[off + e] = op.load(off + e);
@@ -182,6 +191,10 @@ __device__ void soc_block(Op &op, int64_t off, int dim, Acc &acc) {
         double xpos = lo, xneg = hi;
         s = 0.5 * (t + sqrt(nx2));
         if (!(s > lo && s < hi)) s = 0.5 * (lo + hi);
+        if (root) {
+            const double g = *root;   // root of an earlier, nearby input
+            if (g > lo && g < hi) s = g;
+        }
         double dxold = hi - lo, dx = dxold;
         auto eval = [&](double ss, double &f, double &df) {
             const double a = 1.0 - t / ss;
@@ -221,7 +234,8 @@ __device__ void soc_block(Op &op, int64_t off, int dim, Acc &acc) {
             eval(s, f, df);
         }
     }
-    __syncthreads();  // every thread has read buf[off] (t) before it is overwritten
+    __syncthreads();  // every thread has read buf[off] (t) and *root before they change
+    if (root && cs == 4 && tid == 0) *root = s;
     const double a = 1.0 - t / s;
     for (int e = tid; e < dim; e += kBlock) {
         const int64_t j = off + e;
@@ -244,7 +258,8 @@ __device__ void soc_block(Op &op, int64_t off, int dim, Acc &acc) {
 // --------------------------------------- lane-group-per-SOC block (dim <= 256)
 template <class Op, int LPB, int R>
 __device__ __forceinline__ void soc_tile(Op &op, const Tile &tl, const int64_t *__restrict__ soc_off,
-                                         const int32_t *__restrict__ soc_dim, Acc &acc) {
+                                         const int32_t *__restrict__ soc_dim, double *soc_root,
+                                         Acc &acc) {
     const int gi = threadIdx.x / LPB, g = threadIdx.x % LPB;
     if (gi >= tl.count) return;
     const int64_t b = tl.start + gi;
@@ -257,7 +272,9 @@ __device__ __forceinline__ void soc_tile(Op &op, const Tile &tl, const int64_t *
         v[r] = e < dim ? op.load(off + e) : 0.0;
         d[r] = e < dim ? op.scale(off + e) : 1.0;
     }
-    soc_project_group<LPB, R>(dim, v, d, p);
+    double s_new;
+    soc_project_group<LPB, R>(dim, v, d, p, soc_root ? soc_root[b] : __builtin_nan(""), s_new);
+    if (soc_root && g == 0 && s_new == s_new) soc_root[b] = s_new;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int e = g + LPB * r;
@@ -271,7 +288,9 @@ __global__ __launch_bounds__(kBlock) void cone_pass_kernel(Op op, const Tile *__
                                                            const int64_t *__restrict__ soc_off,
                                                            const int32_t *__restrict__ soc_dim,
                                                            const int64_t *__restrict__ exp_off,
-                                                           double *__restrict__ partials) {
+                                                           double *__restrict__ partials,
+                                                           double *__restrict__ soc_root,
+                                                           double *__restrict__ exp_root) {
     if (op.skip()) return;
     op.begin();
     const Tile tl = tiles[blockIdx.x];
@@ -303,14 +322,15 @@ __global__ __launch_bounds__(kBlock) void cone_pass_kernel(Op op, const Tile *__
             op.store(j, v, v > 0.0 ? v : 0.0, acc);
         }
         break;
-    case kTileSoc8: soc_tile<Op, 8, 1>(op, tl, soc_off, soc_dim, acc); break;
-    case kTileSoc16: soc_tile<Op, 16, 1>(op, tl, soc_off, soc_dim, acc); break;
-    case kTileSoc32: soc_tile<Op, 32, 1>(op, tl, soc_off, soc_dim, acc); break;
-    case kTileSoc64: soc_tile<Op, 64, 1>(op, tl, soc_off, soc_dim, acc); break;
-    case kTileSoc128: soc_tile<Op, 64, 2>(op, tl, soc_off, soc_dim, acc); break;
-    case kTileSoc256: soc_tile<Op, 64, 4>(op, tl, soc_off, soc_dim, acc); break;
+    case kTileSoc8: soc_tile<Op, 8, 1>(op, tl, soc_off, soc_dim, soc_root, acc); break;
+    case kTileSoc16: soc_tile<Op, 16, 1>(op, tl, soc_off, soc_dim, soc_root, acc); break;
+    case kTileSoc32: soc_tile<Op, 32, 1>(op, tl, soc_off, soc_dim, soc_root, acc); break;
+    case kTileSoc64: soc_tile<Op, 64, 1>(op, tl, soc_off, soc_dim, soc_root, acc); break;
+    case kTileSoc128: soc_tile<Op, 64, 2>(op, tl, soc_off, soc_dim, soc_root, acc); break;
+    case kTileSoc256: soc_tile<Op, 64, 4>(op, tl, soc_off, soc_dim, soc_root, acc); break;
     case kTileSocBlock:
-        soc_block(op, soc_off[tl.start], soc_dim[tl.start], acc);
+        soc_block(op, soc_off[tl.start], soc_dim[tl.start], acc,
+                  soc_root ? soc_root + tl.start : nullptr);
         break;
     case kTileExp:
     case kTileExpDual:
@@ -318,11 +338,13 @@ __global__ __launch_bounds__(kBlock) void cone_pass_kernel(Op op, const Tile *__
             const int64_t off = exp_off[tl.start + tid];
             const double r0 = op.load(off), s0 = op.load(off + 1), t0 = op.load(off + 2);
             const double dr = op.scale(off), ds = op.scale(off + 1), dt = op.scale(off + 2);
-            double pr, ps, pt;
+            double pr, ps, pt, rho;
+            const double guess = exp_root ? exp_root[tl.start + tid] : __builtin_nan("");
             if (kind == kTileExp)
-                exp_project(r0, s0, t0, dr, ds, dt, pr, ps, pt);
+                exp_project(r0, s0, t0, dr, ds, dt, pr, ps, pt, guess, rho);
             else
-                exp_dual_project(r0, s0, t0, dr, ds, dt, pr, ps, pt);
+                exp_dual_project(r0, s0, t0, dr, ds, dt, pr, ps, pt, guess, rho);
+            if (exp_root && rho == rho) exp_root[tl.start + tid] = rho;
             op.store(off, r0, pr, acc);
             op.store(off + 1, s0, ps, acc);
             op.store(off + 2, t0, pt, acc);
@@ -336,7 +358,8 @@ template <class Op, bool DUAL>
 static void launch(const ConePlan &p, const Op &op, double *partials, hipStream_t s) {
     if (p.ntiles == 0) return;
     hipLaunchKernelGGL((cone_pass_kernel<Op, DUAL>), dim3((unsigned)p.ntiles), dim3(kBlock), 0, s,
-                       op, p.tiles, p.soc_off, p.soc_dim, p.exp_off, partials);
+                       op, p.tiles, p.soc_off, p.soc_dim, p.exp_off, partials,
+                       Op::kWarm ? p.soc_root : nullptr, Op::kWarm ? p.exp_root : nullptr);
     PDCS_HIP(hipGetLastError());
 }
 

@@ -99,9 +99,40 @@ __device__ double exp_root(const ExpPt &c, double xneg, double xpos) {
     return rho;
 }
 
-// Projection of (r0, s0, t0) onto diag(dr, ds, dt) K_exp.
+// Outward search from a guess g of the root inside [lo, hi], where h < 0 at lo
+// and h > 0 at hi: steps of 2^-10 max(1, |g|), doubling, until h changes sign or
+// an end is reached.  Leaves a sign bracket [xneg, xpos] around the root.
+__device__ __forceinline__ void exp_local_bracket(const ExpPt &c, double g, double lo, double hi,
+                                                  double &xneg, double &xpos) {
+    const double fg = exp_hs_value(c, g);
+    double step = 0x1p-10 * fmax(1.0, fabs(g));
+    if (fg < 0.0) {
+        xneg = g;
+        xpos = fmin(g + step, hi);
+        while (xpos < hi && !(exp_hs_value(c, xpos) > 0.0)) {
+            xneg = xpos;
+            step *= 2.0;
+            xpos = fmin(g + step, hi);
+        }
+    } else {
+        xpos = g;
+        xneg = fmax(g - step, lo);
+        while (xneg > lo && !(exp_hs_value(c, xneg) < 0.0)) {
+            xpos = xneg;
+            step *= 2.0;
+            xneg = fmax(g - step, lo);
+        }
+    }
+}
+
+// Projection of (r0, s0, t0) onto diag(dr, ds, dt) K_exp.  `guess` (NaN for
+// none) is a root of h from an earlier, nearby input: when it lies inside the
+// case-4 interval the sign bracket is searched outward from it instead of
+// from the interval's ends.  `rho_out` receives the root of a case-4
+// projection and NaN otherwise.
 __device__ void exp_project(double r0, double s0, double t0, double dr, double ds, double dt,
-                            double &pr, double &ps, double &pt) {
+                            double &pr, double &ps, double &pt, double guess, double &rho_out) {
+    rho_out = __builtin_nan("");
     if (in_kexp(r0 / dr, s0 / ds, t0 / dt)) {              // case 1
         pr = r0, ps = s0, pt = t0;
         return;
@@ -120,17 +151,33 @@ __device__ void exp_project(double r0, double s0, double t0, double dr, double d
     // (r0, s0, dt (s0/ds) e^a3) when a3 < -700 in case (ii).
     constexpr double R = 700.0;
     const ExpPt c{r0, s0, t0, dr, ds, dt, ds / dr};
-    double xneg, xpos;
+    double xneg, xpos, lo, hi;   // [lo, hi]: the case-4 interval kept inside |rho| <= R
+    int side;                    // 0: both ends finite, 1: (-inf, a3), 2: (a4, inf)
     if (r0 > 0.0 && s0 > 0.0) {
-        xpos = fmin(r0 * ds / (s0 * dr), R);
-        xneg = fmax(1.0 - s0 * ds / (r0 * dr), -R);
+        hi = fmin(r0 * ds / (s0 * dr), R);
+        lo = fmax(1.0 - s0 * ds / (r0 * dr), -R);
+        side = 0;
     } else if (s0 > 0.0) {
         const double a3 = r0 * ds / (s0 * dr);
         if (!(a3 >= -R)) {
             pr = r0, ps = s0, pt = dt * (s0 / ds) * exp(a3);
             return;
         }
-        xpos = a3;
+        lo = -R, hi = a3, side = 1;
+    } else {
+        const double a4 = 1.0 - s0 * ds / (r0 * dr);
+        if (!(a4 <= R)) {
+            pr = 0.0, ps = 0.0, pt = t0 > 0.0 ? t0 : 0.0;
+            return;
+        }
+        lo = a4, hi = R, side = 2;
+    }
+    if (guess > lo && guess < hi) {
+        exp_local_bracket(c, guess, lo, hi, xneg, xpos);
+    } else if (side == 0) {
+        xneg = lo, xpos = hi;
+    } else if (side == 1) {
+        xpos = hi;
         double step = 1.0;
         xneg = fmax(xpos - step, -R);
         while (!(exp_hs_value(c, xneg) < 0.0) && xneg > -R) {
@@ -138,12 +185,7 @@ __device__ void exp_project(double r0, double s0, double t0, double dr, double d
             xneg = fmax(xpos - step, -R);
         }
     } else {
-        const double a4 = 1.0 - s0 * ds / (r0 * dr);
-        if (!(a4 <= R)) {
-            pr = 0.0, ps = 0.0, pt = t0 > 0.0 ? t0 : 0.0;
-            return;
-        }
-        xneg = a4;
+        xneg = lo;
         double step = 1.0;
         xpos = fmin(xneg + step, R);
         while (!(exp_hs_value(c, xpos) > 0.0) && xpos < R) {
@@ -152,6 +194,7 @@ __device__ void exp_project(double r0, double s0, double t0, double dr, double d
         }
     }
     const double rho = exp_root(c, xneg, xpos);
+    rho_out = rho;
     // v_p = s_p w(rho), w = (dr rho, ds, dt e^rho); at the root v0 - v_p is
     // orthogonal to w, so s_p = <v0, w>/||w||^2 (projection of v0 onto the ray
     // of w), which avoids the cancellation of eq. (sp_rd) near a3 and a4; the
@@ -172,9 +215,9 @@ __device__ void exp_project(double r0, double s0, double t0, double dr, double d
 
 __device__ __forceinline__ void exp_dual_project(double r0, double s0, double t0, double dr,
                                                  double ds, double dt, double &pr, double &ps,
-                                                 double &pt) {
+                                                 double &pt, double guess, double &rho_out) {
     double qr, qs, qt;
-    exp_project(-r0, -s0, -t0, 1.0 / dr, 1.0 / ds, 1.0 / dt, qr, qs, qt);
+    exp_project(-r0, -s0, -t0, 1.0 / dr, 1.0 / ds, 1.0 / dt, qr, qs, qt, guess, rho_out);
     pr = r0 + qr, ps = s0 + qs, pt = t0 + qt;
 }
 
@@ -203,7 +246,8 @@ __device__ __forceinline__ double group_sum(double v) {
 // cones need fewer exchange steps per reduction and keep more lanes busy.
 template <int LPB, int R>
 __device__ void soc_project_group(int dim, const double (&v)[R], const double (&d)[R],
-                                  double (&p)[R]) {
+                                  double (&p)[R], double s_guess, double &s_out) {
+    s_out = __builtin_nan("");
     const int lane = threadIdx.x % kWave;
     const int g = lane % LPB;
     const int base = lane - g;
@@ -257,6 +301,7 @@ __device__ void soc_project_group(int dim, const double (&v)[R], const double (&
     double xpos = lo, xneg = hi;                          // g > 0 at lo, g <= 0 at hi
     double s = 0.5 * (t + sqrt(nx2));
     if (!(s > lo && s < hi)) s = 0.5 * (lo + hi);
+    if (s_guess > lo && s_guess < hi) s = s_guess;        // root of an earlier, nearby input
     double dxold = hi - lo, dx = dxold;
     auto eval = [&](double ss, double &f, double &df) {
         const double a = 1.0 - t / ss;
@@ -299,6 +344,7 @@ __device__ void soc_project_group(int dim, const double (&v)[R], const double (&
 #pragma unroll
     for (int r = 0; r < R; ++r) p[r] = x[r] / (1.0 + a / h2[r]);
     if (g == 0) p[0] = s;
+    s_out = s;
 }
 
 }  // namespace pdcs

@@ -54,6 +54,9 @@ struct ConePlan {
     int64_t *soc_off = nullptr;   // global entry offset of each SOC block
     int32_t *soc_dim = nullptr;
     int64_t *exp_off = nullptr;   // global entry offset of each exp block
+    int64_t n_soc = 0, n_exp = 0;
+    double *soc_root = nullptr;   // last case-4 root per SOC block (s), NaN = none
+    double *exp_root = nullptr;   // last case-4 root per exp block (rho), NaN = none
 };
 
 struct Csr {
