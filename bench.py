@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-1e-6 rel. KKT & PDHG iter/s (plain FP64 vs chosen form), HBM GB/s"
 SEED_LARGE = 20250502
+SEED_BATCH = 20250504
 HBM_PEAK_GBS = 8000.0
 CHECK = 64
 
@@ -51,11 +52,14 @@ def iteration_bytes(n, m, nnz):
     return spmv_bytes(m, n, nnz) + spmv_bytes(n, m, nnz) + primal + dual + halpern
 
 
-def kernel_timing(pdcs, prob, iters):
+FP32_ONLY = dict(precision=1, polish_tol=0.0, polish_stall=1 << 30)
+
+
+def kernel_timing(pdcs, prob, iters, **kw):
     """Per-kernel average durations inside a solve of `iters` iterations from a
     cold start (the timed work again), from HIP events that the library records
     on its solve stream around every step-attempt kernel."""
-    r = prob.solve(pdcs.settings_default(max_iter=iters, time_kernels=1))
+    r = prob.solve(pdcs.settings_default(max_iter=iters, time_kernels=1, **kw))
     us = {k: 1e3 * r["kernel_ms"][k] / max(1, r["kernel_launches"][k]) for k in pdcs.KERNELS}
     return us, r
 
@@ -79,6 +83,44 @@ def counter_traffic(kernel):
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["sha256"]:
         return None
     return rec["bytes_per_launch"]
+
+
+def batched_form(pdcs, instances, torch, count):
+    """Time to 1e-6 of `count` independent planted LP/SOCP instances (n uniform
+    in 1e3..2e4, m = n/2, 0.5% density, 20% of the variables in SOC blocks of
+    dims 3..50): one batched solve (autotuned products) against solving them one
+    after another with the plain single-problem solver."""
+    insts = instances.batch_lp_soc(SEED_BATCH, count, n_lo=1000, n_hi=20000)
+    nnz = sum(i.nnz for i in insts)
+    log(f"batched form: {count} instances, sum n {sum(i.n for i in insts)}, sum nnz {nnz}")
+    batch = pdcs.Batch(insts)
+    batch.solve(pdcs.settings_default(max_iter=64, autotune=1))   # tune and warm up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rb = batch.solve(pdcs.settings_default(time_limit=120.0, autotune=1))
+    torch.cuda.synchronize()
+    wall_b = time.perf_counter() - t0
+    batch.close()
+    seq = 0.0
+    worst = 0.0
+    for inst, r in zip(insts, rb):
+        prob = pdcs.Problem(inst)
+        prob.solve(pdcs.settings_default(max_iter=64))   # scaling and graph, as for the batch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = prob.solve(pdcs.settings_default(time_limit=120.0))
+        torch.cuda.synchronize()
+        seq += time.perf_counter() - t0
+        worst = max(worst, abs(r["pobj"] - rs["pobj"]) / max(1.0, abs(rs["pobj"])))
+        prob.close()
+    ok = sum(r["status"] == 0 for r in rb)
+    log(f"batched {wall_b:.2f}s vs one by one {seq:.2f}s ({ok}/{count} optimal)")
+    return {"workload": f"{count} planted LP/SOCP instances, n in 1e3..2e4, m = n/2, 0.5% density, "
+                        f"20% SOC dims 3..50, seed {SEED_BATCH}",
+            "sum_nnz": nnz, "optimal": ok, "batched_s": round(wall_b, 3),
+            "one_by_one_s": round(seq, 3), "speedup_time_to_tol": round(seq / wall_b, 3),
+            "max_objective_diff_vs_single_rel": worst,
+            "iterations_max": max(r["iterations"] for r in rb)}
 
 
 def cpu_baseline(inst, iters):
@@ -106,6 +148,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=64)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--m", type=int, default=500_000)
+    ap.add_argument("--batch-count", type=int, default=32,
+                    help="instances of the batched-form measurement (0: skip it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (the reference kernel "
                          "for scaling HBM byte counters) and exit")
@@ -201,20 +245,49 @@ def main():
                                f"{rk['kernel_launches'][dom]} launches of a {CHECK * K}-iteration solve"},
     }
 
+    # the mixed-precision form: FP32 products for the same K check periods
+    sm = pdcs.settings_default(max_iter=CHECK * K, **FP32_ONLY)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rm = prob.solve(sm)
+    torch.cuda.synchronize()
+    wall_m = time.perf_counter() - t0
+    ips_m = rm["iterations"] / rm["solve_s"]
+    kus_m, _ = kernel_timing(pdcs, prob, CHECK * K, **FP32_ONLY)
+    log(f"mixed form: {ips_m:.1f} iter/s; kernels (us): "
+        + ", ".join(f"{k} {v:.1f}" for k, v in kus_m.items()))
+    out["mixed"] = {"form": "FP32 products (values and gathered x^, y^), FP64 iterates, "
+                            "projections and checks, FP64 polish",
+                    "iter_per_s": round(ips_m, 2), "ms_per_step": round(wall_m / K * 1e3, 3),
+                    "speedup_iter_s": round(ips_m / ips, 3),
+                    "kernel_us": {k: round(v, 2) for k, v in kus_m.items()}}
+
     if not args.no_time_to_tol:
-        t0 = time.perf_counter()
-        rt = prob.solve(pdcs.settings_default(time_limit=100.0))
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        out["time_to_tol"] = {
-            "tol": 1e-6, "status": pdcs.SOLVE_STATUS[rt["status"]], "solve_s": round(rt["solve_s"], 3),
-            "setup_s": round(rt["setup_s"], 3), "wall_s": round(wall, 3),
-            "iterations": rt["iterations"], "restarts": rt["restarts"], "spmv": rt["spmv"],
-            "err_p": rt["err_p"], "err_d": rt["err_d"], "err_gap": rt["err_gap"],
-            "objective": rt["pobj"], "planted_objective": inst.opt,
-            "objective_rel_err": abs(rt["pobj"] - inst.opt) / max(1.0, abs(inst.opt))}
-        log(f"time to 1e-6: {rt['solve_s']:.2f}s, {rt['iterations']} iterations, status "
-            f"{pdcs.SOLVE_STATUS[rt['status']]}")
+        def to_tol(**kw):
+            t0 = time.perf_counter()
+            rt = prob.solve(pdcs.settings_default(time_limit=100.0, **kw))
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            rec = {"tol": 1e-6, "status": pdcs.SOLVE_STATUS[rt["status"]], "solve_s": round(rt["solve_s"], 3),
+                   "setup_s": round(rt["setup_s"], 3), "wall_s": round(wall, 3),
+                   "iterations": rt["iterations"], "restarts": rt["restarts"], "spmv": rt["spmv"],
+                   "err_p": rt["err_p"], "err_d": rt["err_d"], "err_gap": rt["err_gap"],
+                   "objective": rt["pobj"], "planted_objective": inst.opt,
+                   "objective_rel_err": abs(rt["pobj"] - inst.opt) / max(1.0, abs(inst.opt))}
+            log(f"time to 1e-6 {kw or ''}: {rt['solve_s']:.2f}s, {rt['iterations']} iterations, status "
+                f"{pdcs.SOLVE_STATUS[rt['status']]}")
+            return rt, rec
+        rp_, out["time_to_tol"] = to_tol()
+        rmx, rec = to_tol(precision=1)
+        rec["polish_iter"] = rmx["polish_iter"]
+        xs = np.abs(rp_["x"]).max()
+        rec["x_diff_vs_fp64_inf_rel"] = float(np.abs(rmx["x"] - rp_["x"]).max() / max(xs, 1e-300))
+        rec["objective_diff_vs_fp64_rel"] = abs(rmx["pobj"] - rp_["pobj"]) / max(1.0, abs(rp_["pobj"]))
+        out["mixed"]["time_to_tol"] = rec
+        out["mixed"]["speedup_time_to_tol"] = round(rp_["solve_s"] / rmx["solve_s"], 3)
+
+    if args.batch_count > 0:
+        out["batched"] = batched_form(pdcs, instances, torch, args.batch_count)
 
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample ...")

@@ -113,6 +113,22 @@ typedef struct {
     int32_t time_kernels;       /* 1: time each step-attempt kernel with HIP events on
                                  * the solve stream (launches eagerly, no graph); the
                                  * sums land in pdcs_info.kernel_ms / kernel_launches */
+    /* Mixed precision (not in the paper): precision 1 runs the two products of
+     * every step attempt with FP32 matrix values and FP32 copies of x^ and y^
+     * (products and sums in FP64); iterates, anchors, averages, projections,
+     * step decisions and every check stay FP64.  The solve switches to the
+     * FP64 products for good (the polish phase) once the chosen candidate's
+     * max(err_p, err_d, err_gap) <= polish_tol, or after polish_stall checks in
+     * a row without a new best; the kept products G~x, G~^T y and those of the
+     * anchor are then recomputed in FP64.  precision 0 is plain FP64. */
+    int32_t precision;
+    double polish_tol;
+    int32_t polish_stall;
+    /* 1: before the first solve of a problem or batch, time every launch
+     * configuration of the two products (CSR-stream; row-split with 2, 4, ...,
+     * 64 lanes per row) on its own matrices with HIP events and keep the
+     * fastest for that handle (not in the paper).  0: fixed rule. */
+    int32_t autotune;
 } pdcs_settings;
 
 /* Kernels of one step attempt, in launch order (indices of pdcs_info.kernel_ms). */
@@ -145,6 +161,8 @@ typedef struct {
      * otherwise. */
     double kernel_ms[PDCS_K_COUNT];
     int64_t kernel_launches[PDCS_K_COUNT];
+    int64_t polish_iter;        /* precision 1: accepted iterations before the switch to
+                                 * FP64 products (-1: never switched); 0 otherwise     */
 } pdcs_info;
 
 /* Optional decision log and iterate snapshots of pdcs_solve, host memory.
@@ -213,6 +231,13 @@ pdcs_status pdcs_scaling(pdcs_problem *p, const pdcs_settings *settings, double 
 pdcs_status pdcs_spmv(pdcs_problem *p, int transpose, const double *x_dev, double *y_dev,
                       void *hip_stream);
 
+/* The FP32 product of the mixed-precision form (not in the paper), on the
+ * unscaled G: the values and x_dev are rounded to FP32, products and sums are
+ * formed in FP64, y_dev is FP64.  Same shapes, memory and stream rules as
+ * pdcs_spmv; the first call allocates the FP32 copies of the values. */
+pdcs_status pdcs_spmv32(pdcs_problem *p, int transpose, const double *x_dev, double *y_dev,
+                        void *hip_stream);
+
 /* Termination measures of eq. (PDCS_terminate_tolerance) at the unscaled
  * point (x_dev [n], y_dev [m], device memory).  out[5] (host) receives
  * err_p, err_d, err_gap, primal objective, dual objective. */
@@ -226,6 +251,66 @@ pdcs_status pdcs_kkt(pdcs_problem *p, const double *x_dev, const double *y_dev, 
  * Errors: INVALID_ARG, DIMENSION, HIP. */
 pdcs_status pdcs_project(int64_t nblocks, const int32_t *types, const int64_t *dims, int dual,
                          const double *d_dev, double *v_dev, void *hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Batches (not in the paper): `count` independent problems solved together.
+ * Their data are laid out block-diagonally on the device and every kernel of a
+ * step attempt covers all instances at once (one launch per kernel, replayed
+ * from a captured HIP graph), each instance with its own step size, primal
+ * weight, reflection parameter, restarts and termination.  An instance that
+ * has converged stops taking work.  descs: host arrays of every instance,
+ * deep-copied (the totals of n, m and nnz must each stay below 2^31).  Same
+ * errors as pdcs_problem_create, plus NOT_SUPPORTED for device arrays. */
+typedef struct pdcs_batch pdcs_batch;
+pdcs_status pdcs_batch_create(const pdcs_problem_desc *descs, int64_t count, void *hip_stream,
+                              pdcs_batch **out);
+/* Cold-start solve of every instance: x_out[b] (n_b) and y_out[b] (m_b) as in
+ * pdcs_solve (host memory, or device memory with settings.out_on_device);
+ * infos: array of count results, the times are the batch's. */
+pdcs_status pdcs_batch_solve(pdcs_batch *b, const pdcs_settings *settings, double *const *x_out,
+                             double *const *y_out, pdcs_info *infos);
+int64_t pdcs_batch_size(const pdcs_batch *b);
+void pdcs_batch_destroy(pdcs_batch *b);
+
+/* ---------------------------------------------------------------------------
+ * Learned warm start (not in the paper).  A perceptron with two hidden ReLU
+ * layers maps the parameters theta of a parametric family to a starting point
+ * (x0, y0) and log omega0 of pdcs_solve.  GEMM operands are BF16 with FP32
+ * accumulation on the matrix cores; master parameters, biases, the loss and
+ * the Adam moments are FP32.
+ *
+ * Parameters: one flat FP32 array of pdcs_mlp_num_params entries laid out
+ * [W1 (hid x in), b1 (hid), W2 (hid x hid), b2 (hid), W3 (out x hid), b3 (out)],
+ * weights row-major by output unit.  Activations: row-major, one row per
+ * sample.  params (host) is copied at create; max_batch bounds every call's
+ * batch.  All data pointers named *_dev are device memory; work is enqueued on
+ * the stream given at create. */
+typedef struct pdcs_mlp pdcs_mlp;
+pdcs_status pdcs_mlp_create(int64_t in, int64_t hid, int64_t out, int64_t max_batch,
+                            const float *params, void *hip_stream, pdcs_mlp **mlp);
+int64_t pdcs_mlp_num_params(const pdcs_mlp *m);
+/* out_dev [batch x out] = network(theta_dev [batch x in]) */
+pdcs_status pdcs_mlp_forward(pdcs_mlp *m, const float *theta_dev, int64_t batch, float *out_dev);
+/* Gradient of L = sum (out - target)^2 / (2 batch out) with respect to the
+ * parameters (grad_host: the flat layout above, may be NULL) and L. */
+pdcs_status pdcs_mlp_gradient(pdcs_mlp *m, const float *theta_dev, const float *target_dev,
+                              int64_t batch, float *grad_host, double *loss);
+/* The gradient above followed by one Adam step (beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias-corrected) with step size lr. */
+pdcs_status pdcs_mlp_train_step(pdcs_mlp *m, const float *theta_dev, const float *target_dev,
+                                int64_t batch, float lr, double *loss);
+pdcs_status pdcs_mlp_get_params(const pdcs_mlp *m, float *params_host);
+void pdcs_mlp_destroy(pdcs_mlp *m);
+
+/* The network's GEMM on the matrix cores: C [M x N] = op(A) op(B) (+ bias[n])
+ * (then max(., 0) when relu), A and B BF16 (raw 16-bit patterns), FP32
+ * accumulation; C written as FP32 to c32 and/or rounded to BF16 (nearest even)
+ * to c16, row-major with leading dimension ldc.  op(A)(m, k) = a[m lda + k]
+ * (ta = 0) or a[k lda + m] (ta = 1); op(B)(k, n) = b[k ldb + n] (tb = 0) or
+ * b[n ldb + k] (tb = 1).  Device pointers; enqueued on hip_stream. */
+pdcs_status pdcs_gemm_bf16(int ta, int tb, int64_t M, int64_t N, int64_t K, const uint16_t *a,
+                           int64_t lda, const uint16_t *b, int64_t ldb, const float *bias, int relu,
+                           float *c32, uint16_t *c16, int64_t ldc, void *hip_stream);
 
 const char *pdcs_status_string(pdcs_status s);
 const char *pdcs_last_error(void);

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpdcs.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "cone_pass.hip", "iterate.hip", "setup.hip", "spmv.hip"]
+SOURCES = ["api.hip", "cone_pass.hip", "iterate.hip", "mlp.hip", "setup.hip", "spmv.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -74,24 +74,28 @@ struct HostPlan {
     std::vector<Tile> tiles;
     std::vector<int64_t> soc_off, exp_off;
     std::vector<int32_t> soc_dim;
+    std::vector<int64_t> inst_tiles{0};   // tiles of instance b: [inst_tiles[b], inst_tiles[b+1])
 };
 
 static int elem_kind(int32_t t) {
     return t == kZero ? kTileZero : t == kFree ? kTileFree : kTileNonneg;
 }
 
-// Tiles for entries [0, n_box) (box) and the cone blocks starting at `base`.
-// Heavy classes come first so that they start early: large SOC (workgroup),
-// small SOC (wavefront), exponential (thread), then elementwise runs.
-static HostPlan build_plan(int64_t base, int64_t n_box, const std::vector<int32_t> &types,
-                           const std::vector<int64_t> &dims) {
-    HostPlan P;
+// Appends the tiles of one instance: box entries [box0, box0 + n_box) and the
+// cone blocks laid out from `base`.  Within an instance heavy classes come
+// first so that they start early: large SOC (workgroup), small SOC
+// (wavefront), exponential (thread), then elementwise runs.
+static void append_plan(HostPlan &P, int32_t inst, int64_t box0, int64_t n_box, int64_t base,
+                        const int32_t *types, const int64_t *dims, int64_t nblk) {
     std::vector<Tile> elem;
+    auto tile = [&](int kind, int64_t count, int64_t start) {
+        return Tile{kind, (int32_t)count, start, inst, 0};
+    };
     auto push_run = [&](int kind, int64_t start, int64_t len) {
         for (int64_t o = 0; o < len; o += kElemPerTile)
-            elem.push_back(Tile{kind, (int32_t)std::min<int64_t>(kElemPerTile, len - o), start + o});
+            elem.push_back(tile(kind, std::min<int64_t>(kElemPerTile, len - o), start + o));
     };
-    push_run(kTileBox, 0, n_box);
+    push_run(kTileBox, box0, n_box);
     // SOC size classes: lanes per block 8, 16, 32, 64 (1 entry per lane), then
     // one wavefront with 2 or 4 entries per lane, then a workgroup per block
     constexpr int kClasses = 7;
@@ -105,7 +109,7 @@ static HostPlan build_plan(int64_t base, int64_t n_box, const std::vector<int32_
     std::vector<int64_t> ep, ed;
     int run_kind = -1;
     int64_t run_start = 0, run_len = 0, off = base;
-    for (size_t b = 0; b < types.size(); ++b) {
+    for (int64_t b = 0; b < nblk; ++b) {
         const int32_t t = types[b];
         const int64_t d = dims[b];
         if (t == kZero || t == kFree || t == kNonneg) {
@@ -132,17 +136,24 @@ static HostPlan build_plan(int64_t base, int64_t n_box, const std::vector<int32_
         for (auto &p : soc[c]) P.soc_off.push_back(p.first), P.soc_dim.push_back((int32_t)p.second);
         const int64_t cnt = (int64_t)soc[c].size();
         for (int64_t i = 0; i < cnt; i += class_per_tile[c])
-            P.tiles.push_back(Tile{class_kind[c],
-                                   (int32_t)std::min<int64_t>(class_per_tile[c], cnt - i), first + i});
+            P.tiles.push_back(tile(class_kind[c], std::min<int64_t>(class_per_tile[c], cnt - i), first + i));
     }
+    const int64_t e0 = (int64_t)P.exp_off.size();
     for (auto o : ep) P.exp_off.push_back(o);
     for (auto o : ed) P.exp_off.push_back(o);
     for (int64_t i = 0; i < (int64_t)ep.size(); i += kExpPerTile)
-        P.tiles.push_back(Tile{kTileExp, (int32_t)std::min<int64_t>(kExpPerTile, ep.size() - i), i});
+        P.tiles.push_back(tile(kTileExp, std::min<int64_t>(kExpPerTile, ep.size() - i), e0 + i));
     for (int64_t i = 0; i < (int64_t)ed.size(); i += kExpPerTile)
-        P.tiles.push_back(Tile{kTileExpDual, (int32_t)std::min<int64_t>(kExpPerTile, ed.size() - i),
-                               (int64_t)ep.size() + i});
+        P.tiles.push_back(tile(kTileExpDual, std::min<int64_t>(kExpPerTile, ed.size() - i),
+                               e0 + (int64_t)ep.size() + i));
     for (auto &t : elem) P.tiles.push_back(t);
+    P.inst_tiles.push_back((int64_t)P.tiles.size());
+}
+
+static HostPlan build_plan(int64_t base, int64_t n_box, const std::vector<int32_t> &types,
+                           const std::vector<int64_t> &dims) {
+    HostPlan P;
+    append_plan(P, 0, 0, n_box, base, types.data(), dims.data(), (int64_t)types.size());
     return P;
 }
 
@@ -159,18 +170,26 @@ static ConePlan upload_plan(DevMem &mem, const HostPlan &H, hipStream_t s) {
     h2d(P.exp_off, H.exp_off.data(), (int64_t)H.exp_off.size(), s);
     P.n_soc = (int64_t)H.soc_off.size();
     P.n_exp = (int64_t)H.exp_off.size();
+    if (H.inst_tiles.size() > 2) {   // a batch: per-instance tile ranges
+        P.inst_tiles = mem.alloc<int64_t>((int64_t)H.inst_tiles.size());
+        h2d(P.inst_tiles, H.inst_tiles.data(), (int64_t)H.inst_tiles.size(), s);
+    }
     PDCS_HIP(hipStreamSynchronize(s));  // the host vectors die with the caller's frame
     return P;
 }
 
-static SpmvPlan build_spmv_plan(DevMem &mem, const std::vector<int64_t> &rp, hipStream_t s) {
+// Launch plan of one product.  Default: CSR-stream when rows average fewer
+// than 12 entries, else `choose_lanes` lanes per row.  `force` (from the
+// autotuner): 0 = default, -1 = CSR-stream, L > 0 = row-split with L lanes.
+static SpmvPlan build_spmv_plan(DevMem &mem, const std::vector<int64_t> &rp, hipStream_t s,
+                                int force = 0) {
     SpmvPlan P;
     const int64_t rows = (int64_t)rp.size() - 1;
     const int64_t nnz = rp.back();
     const double avg = rows > 0 ? (double)nnz / (double)rows : 0.0;
-    P.lanes = choose_lanes(rows > 0 ? avg : 1.0);
+    P.lanes = force > 0 ? force : choose_lanes(rows > 0 ? avg : 1.0);
     P.long_thr = std::max<int64_t>(64, 32 * P.lanes);
-    P.stream = avg < 12.0 ? 1 : 0;
+    P.stream = force == -1 ? 1 : force > 0 ? 0 : (avg < 12.0 ? 1 : 0);
     if (P.stream) P.long_thr = std::min<int64_t>(P.long_thr, kStreamNnz);
     // rows longer than long_thr: chunks of kLongChunk entries
     std::vector<int32_t> lr, crow;
@@ -226,40 +245,80 @@ static SpmvPlan build_spmv_plan(DevMem &mem, const std::vector<int64_t> &rp, hip
 using namespace pdcs;
 
 // ------------------------------------------------------------------ problem
+// Sizes and offsets of one instance inside the (block-diagonal) layout.
+struct InstDims {
+    int64_t x0 = 0, n = 0, y0 = 0, m = 0, nb = 0, k0 = 0, nnz = 0;
+};
+
 struct pdcs_problem {
-    int64_t n = 0, m = 0, nnz = 0, n_box = 0;
+    int64_t n = 0, m = 0, nnz = 0;     // totals over the instances
+    int64_t B = 1;                     // instances (1: a single problem)
+    std::vector<InstDims> inst;
     hipStream_t stream = nullptr;
     DevMem mem;
-    std::vector<int32_t> xt, rt;
+    std::vector<int32_t> xt, rt;       // cone lists of all instances, in order
     std::vector<int64_t> xd, rd;
-    Csr G, Gt;                     // unscaled
-    Csr Gs, Gts;                   // scaled values, shared structure
+    std::vector<int64_t> xblk, rblk;   // [B+1]: cone blocks of instance b
+    Csr G, Gt;                         // unscaled
+    Csr Gs, Gts;                       // scaled values, shared structure
     SpmvPlan pG, pGt;
+    int tuned = 0;                     // 1 once the autotuner has chosen the product plans
+    int forceG = 0, forceGt = 0;       // the chosen configurations (0: default)
     ConePlan planX, planY;
+    // l, u: length n, -inf/+inf outside the box entries of each instance
     double *c, *h, *l, *u, *ones_n, *ones_m;
     double *e, *f, *cs, *hs, *ls, *us, *dx, *dy;
     double *x, *y, *xa, *ya, *xh, *yh, *aty, *gx, *aty0, *gx0, *atyh, *gxh, *xsum, *ysum;
     double *xc[2], *yc[2], *gxc[2], *atyc[2], *tmp_n, *tmp_m;
     double *partX, *partY, *scal;
-    KktRaw *kraw;
-    DevState *st;
+    KktRaw *kraw;                      // [3 B]: slot k of instance b at k B + b
+    DevState *st;                      // [B]
     int *flag;
-    double cinf = 0, hinf = 0;
+    // batch maps (null for a single problem)
+    int32_t *x_inst = nullptr, *y_inst = nullptr;
+    int64_t *x_off = nullptr, *y_off = nullptr, *k_off = nullptr;   // [B+1]
+    int32_t *rcode = nullptr;          // [B] restart codes of a check
+    double *seg = nullptr;             // [5 B] per-instance reductions
+    std::vector<double> cinf, hinf, gmax, cs_norm, hs_norm;
     int scaled_ruiz = -1, scaled_pc = -1;
-    double gmax = 0, cs_norm = 0, hs_norm = 0;
     // a captured batch of step attempts, replayed on a library stream
     hipStream_t gstream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};   // [mixed]
     // timing events of settings.time_kernels: (PDCS_K_COUNT + 1) per attempt
     std::vector<hipEvent_t> tev;
+    // mixed-precision form: FP32 copies of the scaled values (Gs.v32, Gts.v32)
+    // and of the products' inputs x^, y^, allocated on first use
+    float *xh32 = nullptr, *yh32 = nullptr;
+    float *x32 = nullptr;   // input of pdcs_spmv32
     ~pdcs_problem() {
         for (hipEvent_t e : tev) (void)hipEventDestroy(e);
-        if (gexec) (void)hipGraphExecDestroy(gexec);
+        for (hipGraphExec_t g : gexec)
+            if (g) (void)hipGraphExecDestroy(g);
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_out) (void)hipEventDestroy(ev_out);
         if (gstream) (void)hipStreamDestroy(gstream);
     }
+};
+
+struct pdcs_batch {
+    pdcs_problem *p;
+};
+
+// The warm-start network: FP32 master parameters in one flat array laid out
+// [W1 (hid x in), b1, W2 (hid x hid), b2, W3 (out x hid), b3] (weights row-major
+// by output), their gradient and Adam moments, a BF16 copy for the GEMMs, and
+// the activations of one batch.
+struct pdcs_mlp {
+    int64_t in = 0, hid = 0, out = 0, cap = 0, np = 0, step = 0;
+    int64_t off[6] = {};
+    hipStream_t stream = nullptr;
+    DevMem mem;
+    float *p, *g, *m1, *m2;
+    uint16_t *p16;
+    uint16_t *xb, *h1b, *h2b, *d16;
+    float *h1, *h2, *o, *d32, *dh;
+    double *part;
 };
 
 constexpr int kGraphBatch = 64;   // step attempts per captured graph
@@ -298,49 +357,123 @@ __global__ void validate_bounds_kernel(const double *l, const double *u, int64_t
         atomicOr(flag, 4);
 }
 
-static pdcs_problem *create_impl(const pdcs_problem_desc *D, void *stream, bool on_device) {
+static void check_desc(const pdcs_problem_desc *D) {
     if (!D) fail(PDCS_ERR_INVALID_ARG, "desc is NULL");
     if (D->n < 1 || D->m < 0 || D->nnz < 0 || D->n_box < 0 || D->n_box > D->n)
         fail(PDCS_ERR_INVALID_ARG, "bad sizes");
-    if (D->nnz >= ((int64_t)1 << 31)) fail(PDCS_ERR_NOT_SUPPORTED, "nnz must be below 2^31");
-    if (D->n >= ((int64_t)1 << 31) || D->m >= ((int64_t)1 << 31))
-        fail(PDCS_ERR_NOT_SUPPORTED, "n and m must be below 2^31");
     if (!D->row_ptr || (D->nnz > 0 && (!D->col || !D->val)) || !D->c || (D->m > 0 && !D->h) ||
         (D->n_box > 0 && (!D->l || !D->u)))
         fail(PDCS_ERR_INVALID_ARG, "NULL array");
+}
+
+// A problem, or a batch of `count` independent problems laid out block-
+// diagonally: instance b owns entries [x0, x0 + n) of x, rows [y0, y0 + m) and
+// nonzeros [k0, k0 + nnz); its columns are shifted by x0.  A batch needs host
+// arrays; one problem may also come from device arrays.
+static pdcs_problem *create_impl(const pdcs_problem_desc *Ds, int64_t count, void *stream,
+                                 bool on_device) {
+    if (!Ds) fail(PDCS_ERR_INVALID_ARG, "desc is NULL");
+    if (count < 1) fail(PDCS_ERR_INVALID_ARG, "no problem in the batch");
+    if (on_device && count != 1) fail(PDCS_ERR_NOT_SUPPORTED, "a batch takes host arrays");
     auto P = std::make_unique<pdcs_problem>();
-    P->n = D->n, P->m = D->m, P->nnz = D->nnz, P->n_box = D->n_box;
+    P->B = count;
     P->stream = (hipStream_t)stream;
-    validate_cones(D->n_xcones, D->xcone_type, D->xcone_dim, D->n - D->n_box, "x cones", P->xt, P->xd);
-    validate_cones(D->n_rcones, D->rcone_type, D->rcone_dim, D->m, "row cones", P->rt, P->rd);
-    const int64_t n = P->n, m = P->m, nnz = P->nnz, nb = P->n_box;
+    P->xblk.push_back(0), P->rblk.push_back(0);
+    int64_t n = 0, m = 0, nnz = 0;
+    for (int64_t b = 0; b < count; ++b) {
+        const pdcs_problem_desc *D = Ds + b;
+        check_desc(D);
+        InstDims I;
+        I.x0 = n, I.n = D->n, I.y0 = m, I.m = D->m, I.nb = D->n_box, I.k0 = nnz, I.nnz = D->nnz;
+        validate_cones(D->n_xcones, D->xcone_type, D->xcone_dim, D->n - D->n_box, "x cones", P->xt, P->xd);
+        validate_cones(D->n_rcones, D->rcone_type, D->rcone_dim, D->m, "row cones", P->rt, P->rd);
+        P->xblk.push_back((int64_t)P->xt.size()), P->rblk.push_back((int64_t)P->rt.size());
+        n += D->n, m += D->m, nnz += D->nnz;
+        P->inst.push_back(I);
+    }
+    if (nnz >= ((int64_t)1 << 31)) fail(PDCS_ERR_NOT_SUPPORTED, "nnz must be below 2^31");
+    if (n >= ((int64_t)1 << 31) || m >= ((int64_t)1 << 31))
+        fail(PDCS_ERR_NOT_SUPPORTED, "n and m must be below 2^31");
+    P->n = n, P->m = m, P->nnz = nnz;
+    const int64_t B = count;
     hipStream_t s = P->stream;
     DevMem &M = P->mem;
     P->G = Csr{m, n, nnz, M.alloc<int64_t>(m + 1), M.alloc<int32_t>(nnz), M.alloc<double>(nnz)};
     P->Gt = Csr{n, m, nnz, M.alloc<int64_t>(n + 1), M.alloc<int32_t>(nnz), M.alloc<double>(nnz)};
     P->c = M.alloc<double>(n);
     P->h = M.alloc<double>(m);
-    P->l = M.alloc<double>(nb);
-    P->u = M.alloc<double>(nb);
-    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    auto cp = [&](void *dst, const void *src, size_t bytes) {
-        if (bytes) PDCS_HIP(hipMemcpyAsync(dst, src, bytes, kind, s));
-    };
-    cp(P->G.rp, D->row_ptr, sizeof(int64_t) * (m + 1));
-    cp(P->G.ci, D->col, sizeof(int32_t) * nnz);
-    cp(P->G.v, D->val, sizeof(double) * nnz);
-    cp(P->c, D->c, sizeof(double) * n);
-    cp(P->h, D->h, sizeof(double) * m);
-    cp(P->l, D->l, sizeof(double) * nb);
-    cp(P->u, D->u, sizeof(double) * nb);
+    P->l = M.alloc<double>(n);
+    P->u = M.alloc<double>(n);
+    fill(P->l, n, -INFINITY, s);
+    fill(P->u, n, INFINITY, s);
+    if (B == 1) {
+        const pdcs_problem_desc *D = Ds;
+        const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        auto cp = [&](void *dst, const void *src, size_t bytes) {
+            if (bytes) PDCS_HIP(hipMemcpyAsync(dst, src, bytes, kind, s));
+        };
+        cp(P->G.rp, D->row_ptr, sizeof(int64_t) * (m + 1));
+        cp(P->G.ci, D->col, sizeof(int32_t) * nnz);
+        cp(P->G.v, D->val, sizeof(double) * nnz);
+        cp(P->c, D->c, sizeof(double) * n);
+        cp(P->h, D->h, sizeof(double) * m);
+        cp(P->l, D->l, sizeof(double) * D->n_box);
+        cp(P->u, D->u, sizeof(double) * D->n_box);
+    } else {
+        std::vector<int64_t> rp(m + 1);
+        std::vector<int32_t> ci(nnz), xi(n), yi(m);
+        std::vector<double> val(nnz), c(n), h(m), l(n, -INFINITY), u(n, INFINITY);
+        std::vector<int64_t> xo(B + 1), yo(B + 1), ko(B + 1);
+        rp[0] = 0;
+        for (int64_t b = 0; b < B; ++b) {
+            const pdcs_problem_desc *D = Ds + b;
+            const InstDims &I = P->inst[b];
+            if (D->row_ptr[0] != 0 || D->row_ptr[D->m] != D->nnz)
+                fail(PDCS_ERR_INVALID_ARG, "malformed CSR (row_ptr or column index)");
+            for (int64_t r = 0; r < D->m; ++r) {
+                if (D->row_ptr[r] > D->row_ptr[r + 1])
+                    fail(PDCS_ERR_INVALID_ARG, "malformed CSR (row_ptr or column index)");
+                rp[I.y0 + r + 1] = I.k0 + D->row_ptr[r + 1];
+            }
+            for (int64_t k = 0; k < D->nnz; ++k) {
+                if (D->col[k] < 0 || D->col[k] >= D->n)
+                    fail(PDCS_ERR_INVALID_ARG, "malformed CSR (row_ptr or column index)");
+                ci[I.k0 + k] = (int32_t)(I.x0 + D->col[k]);
+                val[I.k0 + k] = D->val[k];
+            }
+            std::copy(D->c, D->c + D->n, c.begin() + I.x0);
+            if (D->m) std::copy(D->h, D->h + D->m, h.begin() + I.y0);
+            std::copy(D->l, D->l + D->n_box, l.begin() + I.x0);
+            std::copy(D->u, D->u + D->n_box, u.begin() + I.x0);
+            std::fill(xi.begin() + I.x0, xi.begin() + I.x0 + I.n, (int32_t)b);
+            std::fill(yi.begin() + I.y0, yi.begin() + I.y0 + I.m, (int32_t)b);
+            xo[b] = I.x0, yo[b] = I.y0, ko[b] = I.k0;
+        }
+        xo[B] = n, yo[B] = m, ko[B] = nnz;
+        h2d(P->G.rp, rp.data(), m + 1, s);
+        h2d(P->G.ci, ci.data(), nnz, s);
+        h2d(P->G.v, val.data(), nnz, s);
+        h2d(P->c, c.data(), n, s);
+        h2d(P->h, h.data(), m, s);
+        h2d(P->l, l.data(), n, s);
+        h2d(P->u, u.data(), n, s);
+        P->x_inst = M.alloc<int32_t>(n), P->y_inst = M.alloc<int32_t>(m);
+        P->x_off = M.alloc<int64_t>(B + 1), P->y_off = M.alloc<int64_t>(B + 1);
+        P->k_off = M.alloc<int64_t>(B + 1);
+        h2d(P->x_inst, xi.data(), n, s);
+        h2d(P->y_inst, yi.data(), m, s);
+        h2d(P->x_off, xo.data(), B + 1, s);
+        h2d(P->y_off, yo.data(), B + 1, s);
+        h2d(P->k_off, ko.data(), B + 1, s);
+        PDCS_HIP(hipStreamSynchronize(s));   // the host vectors die at the end of this block
+    }
     P->flag = M.alloc<int>(4);
     PDCS_HIP(hipMemsetAsync(P->flag, 0, sizeof(int) * 4, s));
     const int64_t vk = std::max(m + 1, nnz);
     hipLaunchKernelGGL(validate_csr_kernel, dim3((unsigned)((vk + 255) / 256)), dim3(256), 0, s,
                        P->G.rp, m, P->G.ci, nnz, n, P->flag);
-    if (nb > 0)
-        hipLaunchKernelGGL(validate_bounds_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0,
-                           s, P->l, P->u, nb, P->flag);
+    hipLaunchKernelGGL(validate_bounds_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       P->l, P->u, n, P->flag);
     check_finite(P->G.v, nnz, P->flag, s);
     check_finite(P->c, n, P->flag, s);
     check_finite(P->h, m, P->flag, s);
@@ -358,8 +491,16 @@ static pdcs_problem *create_impl(const pdcs_problem_desc *D, void *stream, bool 
     PDCS_HIP(hipStreamSynchronize(s));
     P->pG = build_spmv_plan(M, hrp, s);
     P->pGt = build_spmv_plan(M, hrpt, s);
-    P->planX = upload_plan(M, build_plan(nb, nb, P->xt, P->xd), s);
-    P->planY = upload_plan(M, build_plan(0, 0, P->rt, P->rd), s);
+    HostPlan hx, hy;
+    for (int64_t b = 0; b < B; ++b) {
+        const InstDims &I = P->inst[b];
+        append_plan(hx, (int32_t)b, I.x0, I.nb, I.x0 + I.nb, P->xt.data() + P->xblk[b], P->xd.data() + P->xblk[b],
+                    P->xblk[b + 1] - P->xblk[b]);
+        append_plan(hy, (int32_t)b, I.y0, 0, I.y0, P->rt.data() + P->rblk[b], P->rd.data() + P->rblk[b],
+                    P->rblk[b + 1] - P->rblk[b]);
+    }
+    P->planX = upload_plan(M, hx, s);
+    P->planY = upload_plan(M, hy, s);
 
     P->Gs = Csr{m, n, nnz, P->G.rp, P->G.ci, M.alloc<double>(nnz)};
     P->Gts = Csr{n, m, nnz, P->Gt.rp, P->Gt.ci, M.alloc<double>(nnz)};
@@ -369,7 +510,7 @@ static pdcs_problem *create_impl(const pdcs_problem_desc *D, void *stream, bool 
     fill(P->ones_m, m, 1.0, s);
     P->e = M.alloc<double>(m), P->f = M.alloc<double>(n);
     P->cs = M.alloc<double>(n), P->hs = M.alloc<double>(m);
-    P->ls = M.alloc<double>(nb), P->us = M.alloc<double>(nb);
+    P->ls = M.alloc<double>(n), P->us = M.alloc<double>(n);
     P->dx = M.alloc<double>(n), P->dy = M.alloc<double>(m);
     double **xs[] = {&P->x, &P->xa, &P->xh, &P->aty, &P->aty0, &P->atyh, &P->xsum, &P->tmp_n,
                      &P->xc[0], &P->xc[1], &P->atyc[0], &P->atyc[1]};
@@ -384,23 +525,35 @@ static pdcs_problem *create_impl(const pdcs_problem_desc *D, void *stream, bool 
     P->partX = M.alloc<double>(P->planX.ntiles * kPartials);
     P->partY = M.alloc<double>(P->planY.ntiles * kPartials);
     P->scal = M.alloc<double>(8);
-    P->kraw = M.alloc<KktRaw>(3);
-    P->st = M.alloc<DevState>(1);
-    reduce_absmax(P->c, n, P->scal + 0, s);
-    reduce_absmax(P->h, m, P->scal + 1, s);
-    double nrm[2] = {0, 0};
-    d2h(nrm, P->scal, 2, s);
+    P->seg = M.alloc<double>(5 * B);
+    P->rcode = M.alloc<int32_t>(B);
+    P->kraw = M.alloc<KktRaw>(3 * B);
+    P->st = M.alloc<DevState>(B);
+    std::vector<double> r(2 * B, 0.0);
+    if (B == 1) {
+        reduce_absmax(P->c, n, P->seg + 0, s);
+        reduce_absmax(P->h, m, P->seg + 1, s);
+    } else {
+        reduce_segments(1, P->c, P->x_off, B, P->seg, s);
+        reduce_segments(1, P->h, P->y_off, B, P->seg + B, s);
+    }
+    d2h(r.data(), P->seg, 2 * B, s);
     PDCS_HIP(hipStreamSynchronize(s));
-    P->cinf = nrm[0], P->hinf = m > 0 ? nrm[1] : 0.0;
+    P->cinf.assign(r.begin(), r.begin() + B);
+    P->hinf.assign(r.begin() + B, r.end());
+    for (int64_t b = 0; b < B; ++b)
+        if (P->inst[b].m == 0) P->hinf[b] = 0.0;
     return P.release();
 }
 
 // Rescaling of Section 3 (reading: Ruiz passes + one Pock-Chambolle pass),
-// cached for the parameters it was computed with.
+// cached for the parameters it was computed with.  The row and column passes
+// of a block-diagonal batch touch one instance each, so a batch is rescaled
+// instance by instance.
 static void ensure_scaling(pdcs_problem *P, int ruiz, int pc) {
     if (P->scaled_ruiz == ruiz && P->scaled_pc == pc) return;
     hipStream_t s = P->stream;
-    const int64_t n = P->n, m = P->m;
+    const int64_t n = P->n, m = P->m, B = P->B;
     fill(P->e, m, 1.0, s);
     fill(P->f, n, 1.0, s);
     for (int it = 0; it < ruiz + (pc ? 1 : 0); ++it) {
@@ -417,37 +570,121 @@ static void ensure_scaling(pdcs_problem *P, int ruiz, int pc) {
     }
     scale_values(P->G, P->e, P->f, true, P->Gs.v, s);
     scale_values(P->Gt, P->f, P->e, false, P->Gts.v, s);
-    scale_problem_vectors(n, m, P->n_box, P->c, P->h, P->l, P->u, P->e, P->f, P->cs, P->hs, P->ls,
+    if (P->Gs.v32) {   // keep the FP32 copies in step with the scaling
+        to_float(P->Gs.v, P->Gs.v32, P->nnz, s);
+        to_float(P->Gts.v, P->Gts.v32, P->nnz, s);
+    }
+    scale_problem_vectors(n, m, n, P->c, P->h, P->l, P->u, P->e, P->f, P->cs, P->hs, P->ls,
                           P->us, P->dx, P->dy, s);
-    reduce_absmax(P->Gs.v, P->nnz, P->scal + 2, s);
-    reduce_sumsq(P->cs, n, P->scal + 3, s);
-    reduce_sumsq(P->hs, m, P->scal + 4, s);
-    double r[3] = {0, 0, 0};
-    d2h(r, P->scal + 2, 3, s);
+    std::vector<double> r(3 * B, 0.0);
+    if (B == 1) {
+        reduce_absmax(P->Gs.v, P->nnz, P->seg + 0, s);
+        reduce_sumsq(P->cs, n, P->seg + 1, s);
+        reduce_sumsq(P->hs, m, P->seg + 2, s);
+    } else {
+        reduce_segments(1, P->Gs.v, P->k_off, B, P->seg, s);
+        reduce_segments(0, P->cs, P->x_off, B, P->seg + B, s);
+        reduce_segments(0, P->hs, P->y_off, B, P->seg + 2 * B, s);
+    }
+    d2h(r.data(), P->seg, 3 * B, s);
     PDCS_HIP(hipStreamSynchronize(s));
-    P->gmax = P->nnz > 0 ? r[0] : 0.0;
-    P->cs_norm = std::sqrt(r[1]);
-    P->hs_norm = m > 0 ? std::sqrt(r[2]) : 0.0;
+    P->gmax.resize(B), P->cs_norm.resize(B), P->hs_norm.resize(B);
+    for (int64_t b = 0; b < B; ++b) {
+        P->gmax[b] = P->inst[b].nnz > 0 ? r[b] : 0.0;
+        P->cs_norm[b] = std::sqrt(r[B + b]);
+        P->hs_norm[b] = P->inst[b].m > 0 ? std::sqrt(r[2 * B + b]) : 0.0;
+    }
     P->scaled_ruiz = ruiz, P->scaled_pc = pc;
 }
 
-// Fixed step step_fixed / ||G~||_2, the norm by power iteration on G~^T G~ from
-// the normalised all-ones vector (the plain-PDHG step of the ablation).
-static double fixed_step(pdcs_problem *P, const pdcs_settings *S) {
+// FP32 copies for the mixed-precision form, made once per problem (and kept in
+// step with the scaling by ensure_scaling).
+static void ensure_fp32(pdcs_problem *P) {
+    if (P->Gs.v32) return;
     hipStream_t s = P->stream;
-    const int64_t n = P->n;
-    fill(P->tmp_n, n, 1.0 / std::sqrt((double)n), s);
-    for (int it = 0; it < S->power_iters; ++it) {
-        spmv(P->Gs, P->pG, P->tmp_n, P->tmp_m, nullptr, s);
-        spmv(P->Gts, P->pGt, P->tmp_m, P->atyh, nullptr, s);
-        reduce_sumsq(P->atyh, n, P->scal + 5, s);
-        scale_by_inv_sqrt(P->atyh, P->scal + 5, P->tmp_n, n, s);
-    }
-    double lam2 = 0.0;
-    d2h(&lam2, P->scal + 5, 1, s);
+    P->xh32 = P->mem.alloc<float>(P->n);
+    P->yh32 = P->mem.alloc<float>(P->m);
+    float *g32 = P->mem.alloc<float>(P->nnz), *gt32 = P->mem.alloc<float>(P->nnz);
+    to_float(P->Gs.v, g32, P->nnz, s);
+    to_float(P->Gts.v, gt32, P->nnz, s);
+    P->Gs.v32 = g32, P->Gts.v32 = gt32;
+}
+
+// Autotuner of the product plans: times each candidate configuration (CSR-
+// stream, row-split with 2..64 lanes per row) of G~ and G~^T on the problem's
+// own matrices with HIP events and keeps the fastest.  Runs once per problem,
+// before the first graph capture.
+static void autotune_spmv(pdcs_problem *P) {
+    if (P->tuned) return;
+    hipStream_t s = P->stream;
+    std::vector<int64_t> hrp(P->m + 1), hrpt(P->n + 1);
+    d2h(hrp.data(), P->G.rp, P->m + 1, s);
+    d2h(hrpt.data(), P->Gt.rp, P->n + 1, s);
     PDCS_HIP(hipStreamSynchronize(s));
-    const double lam = std::sqrt(lam2);
-    return (S->power_iters > 0 && lam > 0.0) ? S->step_fixed / std::sqrt(lam) : 1.0;
+    hipEvent_t a, b;
+    PDCS_HIP(hipEventCreate(&a));
+    PDCS_HIP(hipEventCreate(&b));
+    const int cands[] = {-1, 2, 4, 8, 16, 32, 64};
+    for (int side = 0; side < 2; ++side) {
+        const Csr &A = side == 0 ? P->Gs : P->Gts;
+        const std::vector<int64_t> &rp = side == 0 ? hrp : hrpt;
+        double *in = side == 0 ? P->ones_n : P->ones_m;
+        double *out = side == 0 ? P->tmp_m : P->tmp_n;
+        float best = INFINITY;
+        int best_c = 0;
+        for (int c : cands) {
+            DevMem tmp;
+            const SpmvPlan plan = build_spmv_plan(tmp, rp, s, c);
+            spmv(A, plan, in, out, SpmvSkip{}, s);   // warm
+            PDCS_HIP(hipEventRecord(a, s));
+            for (int r = 0; r < 5; ++r) spmv(A, plan, in, out, SpmvSkip{}, s);
+            PDCS_HIP(hipEventRecord(b, s));
+            PDCS_HIP(hipEventSynchronize(b));
+            float ms = 0.0f;
+            PDCS_HIP(hipEventElapsedTime(&ms, a, b));
+            if (ms < best) best = ms, best_c = c;
+        }
+        if (side == 0) {
+            P->forceG = best_c;
+            P->pG = build_spmv_plan(P->mem, rp, s, best_c);
+        } else {
+            P->forceGt = best_c;
+            P->pGt = build_spmv_plan(P->mem, rp, s, best_c);
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    P->tuned = 1;
+}
+
+// Fixed step step_fixed / ||G~_b||_2 per instance, the norm by power iteration
+// on G~^T G~ from the normalised all-ones vector (the plain-PDHG step of the
+// ablation); the blocks of a batch are iterated together, each normalised on
+// its own.
+static std::vector<double> fixed_step(pdcs_problem *P, const pdcs_settings *S) {
+    hipStream_t s = P->stream;
+    const int64_t n = P->n, B = P->B;
+    std::vector<double> v(B);
+    for (int64_t b = 0; b < B; ++b) v[b] = 1.0 / std::sqrt((double)P->inst[b].n);
+    h2d(P->seg, v.data(), B, s);
+    fill_by_inst(P->tmp_n, P->x_inst, P->seg, n, s);
+    double *sums = P->seg + B;
+    for (int it = 0; it < S->power_iters; ++it) {
+        spmv(P->Gs, P->pG, P->tmp_n, P->tmp_m, SpmvSkip{}, s);
+        spmv(P->Gts, P->pGt, P->tmp_m, P->atyh, SpmvSkip{}, s);
+        if (B == 1)
+            reduce_sumsq(P->atyh, n, sums, s);
+        else
+            reduce_segments(0, P->atyh, P->x_off, B, sums, s);
+        scale_by_inv_sqrt(P->atyh, sums, P->x_inst, P->tmp_n, n, s);
+    }
+    d2h(v.data(), sums, B, s);
+    PDCS_HIP(hipStreamSynchronize(s));
+    for (int64_t b = 0; b < B; ++b) {
+        const double lam = std::sqrt(v[b]);
+        v[b] = (S->power_iters > 0 && lam > 0.0) ? S->step_fixed / std::sqrt(lam) : 1.0;
+    }
+    return v;
 }
 
 struct Kkt {
@@ -456,10 +693,10 @@ struct Kkt {
     double mx() const { return std::max(err_p, std::max(err_d, err_gap)); }
 };
 
-static Kkt kkt_from_raw(const pdcs_problem *P, const KktRaw &r) {
+static Kkt kkt_from_raw(const pdcs_problem *P, int64_t b, const KktRaw &r) {
     Kkt k;
-    k.err_p = r.rows_max[0] / (1.0 + std::max(P->hinf, std::max(r.rows_max[1], r.rows_max[2])));
-    k.err_d = r.cols_max[0] / (1.0 + std::max(P->cinf, r.cols_max[1]));
+    k.err_p = r.rows_max[0] / (1.0 + std::max(P->hinf[b], std::max(r.rows_max[1], r.rows_max[2])));
+    k.err_d = r.cols_max[0] / (1.0 + std::max(P->cinf[b], r.cols_max[1]));
     k.pobj = r.cols_sum[0];
     k.dobj = r.rows_sum[0] + r.cols_sum[1];
     k.err_gap = std::fabs(k.pobj - k.dobj) / (1.0 + std::max(std::fabs(k.pobj), std::fabs(k.dobj)));
@@ -468,15 +705,17 @@ static Kkt kkt_from_raw(const pdcs_problem *P, const KktRaw &r) {
     return k;
 }
 
-// Enqueue the termination measures of the scaled point (xc, yc) with products
-// gxc = G~xc and atyc = G~^T yc into kraw[slot]; distances are to (xa, ya).
+// Enqueue the termination measures of the scaled points (xc, yc) of every
+// instance with products gxc = G~xc and atyc = G~^T yc into kraw[slot B + b];
+// distances are to (xa, ya).
 static void enqueue_kkt(pdcs_problem *P, const double *xc, const double *yc, const double *gxc,
                         const double *atyc, const double *xa, const double *ya, const double *e,
                         const double *f, int slot) {
     hipStream_t s = P->stream;
     pass_kkt_rows(P->planY, KktRowsArgs{gxc, P->h, e, yc, ya, P->tmp_m}, P->partY, s);
     pass_kkt_cols(P->planX, KktColsArgs{atyc, P->c, f, P->l, P->u, xc, xa, P->tmp_n}, P->partX, s);
-    reduce_kkt(P->partY, P->planY.ntiles, P->partX, P->planX.ntiles, P->kraw + slot, s);
+    reduce_kkt(P->B, P->partY, P->planY.inst_tiles, P->planY.ntiles, P->partX, P->planX.inst_tiles,
+               P->planX.ntiles, P->kraw + slot * P->B, s);
 }
 
 static void fill_info(pdcs_info *info, int status, const DevState &hs, long long restarts,
@@ -492,17 +731,23 @@ static void fill_info(pdcs_info *info, int status, const DevState &hs, long long
     info->omega = hs.omega, info->eta = hs.eta;
     info->setup_s = setup_s, info->solve_s = solve_s;
     for (int j = 0; j < PDCS_K_COUNT; ++j) info->kernel_ms[j] = 0.0, info->kernel_launches[j] = 0;
+    info->polish_iter = 0;
 }
 
-// One step attempt of Algorithm 1 (see the file header), `batch` times.  With
-// `ev`, event ev[(PDCS_K_COUNT + 1) b + j] is recorded before kernel j of
-// attempt b and ev[(PDCS_K_COUNT + 1) b + PDCS_K_COUNT] after its last kernel.
-static void enqueue_attempts(pdcs_problem *P, long long batch, hipStream_t s,
+// One step attempt of Algorithm 1 (see the file header) for every instance,
+// `batch` times.  With `ev`, event ev[(PDCS_K_COUNT + 1) b + j] is recorded
+// before kernel j of attempt b and ev[(PDCS_K_COUNT + 1) b + PDCS_K_COUNT]
+// after its last kernel.
+static void enqueue_attempts(pdcs_problem *P, long long batch, bool mixed, hipStream_t s,
                              const hipEvent_t *ev = nullptr) {
-    const PrimalArgs pa{P->x, P->aty, P->cs, P->ls, P->us, P->dx, P->xh, P->st};
-    const DualArgs da{P->y, P->gxh, P->gx, P->hs, P->dy, P->yh, P->st};
-    const HalpernArgs ha{P->x, P->aty, P->xsum, P->xh, P->atyh, P->xa, P->aty0,
-                         P->y, P->gx, P->ysum, P->yh, P->gxh, P->ya, P->gx0, P->n, P->m, P->st};
+    const PrimalArgs pa{P->x, P->aty, P->cs, P->ls, P->us, P->dx, P->xh, P->st,
+                        mixed ? P->xh32 : nullptr};
+    const DualArgs da{P->y, P->gxh, P->gx, P->hs, P->dy, P->yh, P->st, mixed ? P->yh32 : nullptr};
+    const HalpernArgs ha{P->x,  P->aty, P->xsum, P->xh, P->atyh, P->xa, P->aty0, P->y, P->gx,
+                         P->ysum, P->yh, P->gxh, P->ya, P->gx0,  P->n,    P->m,  P->st,
+                         P->x_inst, P->y_inst};
+    const SpmvSkip on_halt{P->st, P->y_inst, SkipHalt};       // rows of G~: y entries
+    const SpmvSkip on_reject{P->st, P->x_inst, SkipUpdate};   // rows of G~^T: x entries
     constexpr int E = PDCS_K_COUNT + 1;
     auto mark = [&](long long b, int j) {
         if (ev) PDCS_HIP(hipEventRecord(ev[E * b + j], s));
@@ -511,13 +756,20 @@ static void enqueue_attempts(pdcs_problem *P, long long batch, hipStream_t s,
         mark(b, PDCS_K_PRIMAL);
         pass_primal(P->planX, pa, P->partX, s);
         mark(b, PDCS_K_SPMV_G);
-        spmv(P->Gs, P->pG, P->xh, P->gxh, &P->st->halt, s);
+        if (mixed)
+            spmv32(P->Gs, P->pG, P->xh32, P->gxh, on_halt, s);
+        else
+            spmv(P->Gs, P->pG, P->xh, P->gxh, on_halt, s);
         mark(b, PDCS_K_DUAL);
         pass_dual(P->planY, da, P->partY, s);
         mark(b, PDCS_K_DECIDE);
-        decide(P->st, P->partX, P->planX.ntiles, P->partY, P->planY.ntiles, s);
+        decide(P->st, P->B, P->partX, P->planX.inst_tiles, P->planX.ntiles, P->partY,
+               P->planY.inst_tiles, P->planY.ntiles, s);
         mark(b, PDCS_K_SPMV_GT);
-        spmv(P->Gts, P->pGt, P->yh, P->atyh, &P->st->skip_update, s);
+        if (mixed)
+            spmv32(P->Gts, P->pGt, P->yh32, P->atyh, on_reject, s);
+        else
+            spmv(P->Gts, P->pGt, P->yh, P->atyh, on_reject, s);
         mark(b, PDCS_K_HALPERN);
         halpern(ha, s);
         mark(b, PDCS_K_COUNT);
@@ -526,41 +778,50 @@ static void enqueue_attempts(pdcs_problem *P, long long batch, hipStream_t s,
 
 // Captures kGraphBatch attempts once per problem on a library-owned stream
 // (the caller's stream may be the null stream, which cannot be captured).
-static void ensure_graph(pdcs_problem *P) {
-    if (P->gexec) return;
+static void ensure_graph(pdcs_problem *P, bool mixed) {
+    if (P->gexec[mixed]) return;
     if (!P->gstream) PDCS_HIP(hipStreamCreateWithFlags(&P->gstream, hipStreamNonBlocking));
     if (!P->ev_in) PDCS_HIP(hipEventCreateWithFlags(&P->ev_in, hipEventDisableTiming));
     if (!P->ev_out) PDCS_HIP(hipEventCreateWithFlags(&P->ev_out, hipEventDisableTiming));
     hipGraph_t g = nullptr;
     PDCS_HIP(hipStreamBeginCapture(P->gstream, hipStreamCaptureModeThreadLocal));
     try {
-        enqueue_attempts(P, kGraphBatch, P->gstream);
+        enqueue_attempts(P, kGraphBatch, mixed, P->gstream);
     } catch (...) {
         (void)hipStreamEndCapture(P->gstream, &g);
         if (g) (void)hipGraphDestroy(g);
         throw;
     }
     PDCS_HIP(hipStreamEndCapture(P->gstream, &g));
-    hipError_t e = hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0);
+    hipError_t e = hipGraphInstantiate(&P->gexec[mixed], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     PDCS_HIP(e);
 }
 
-static void run_graph(pdcs_problem *P, hipStream_t s) {
+static void run_graph(pdcs_problem *P, bool mixed, hipStream_t s) {
     PDCS_HIP(hipEventRecord(P->ev_in, s));
     PDCS_HIP(hipStreamWaitEvent(P->gstream, P->ev_in, 0));
-    PDCS_HIP(hipGraphLaunch(P->gexec, P->gstream));
+    PDCS_HIP(hipGraphLaunch(P->gexec[mixed], P->gstream));
     PDCS_HIP(hipEventRecord(P->ev_out, P->gstream));
     PDCS_HIP(hipStreamWaitEvent(s, P->ev_out, 0));
 }
 
-static void solve_impl(pdcs_problem *P, const pdcs_settings *S, const double *x0, const double *y0,
-                       double omega0, double *xo, double *yo, pdcs_info *info, pdcs_trace *tr) {
+// Algorithm 1 on every instance of P at once.  x0/y0/omega0/xo/yo/infos are
+// per instance (x0[b], y0[b] nullable: cold start; omega0 <= 0: default);
+// a trace is only for a single problem.
+static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *const *x0,
+                        const double *const *y0, const double *omega0, double *const *xo,
+                        double *const *yo, pdcs_info *infos, pdcs_trace *tr) {
     using clk = std::chrono::steady_clock;
+    const int64_t B = P->B;
     if (!S || !xo || !yo) fail(PDCS_ERR_INVALID_ARG, "settings, x_out and y_out are required");
+    for (int64_t b = 0; b < B; ++b)
+        if (!xo[b] || !yo[b]) fail(PDCS_ERR_INVALID_ARG, "settings, x_out and y_out are required");
     if (S->check_every < 1 || S->ruiz_iters < 0 || S->max_attempts < 1 || !(S->tol >= 0.0) ||
-        S->step_mode < 0 || S->step_mode > 1 || (S->step_mode == 1 && !(S->step_fixed > 0.0)))
+        S->step_mode < 0 || S->step_mode > 1 || (S->step_mode == 1 && !(S->step_fixed > 0.0)) ||
+        S->precision < 0 || S->precision > 1 || !(S->polish_tol >= 0.0) || S->polish_stall < 1)
         fail(PDCS_ERR_INVALID_ARG, "bad settings");
+    if (tr && B != 1) fail(PDCS_ERR_INVALID_ARG, "a trace is for a single problem");
     if (tr && (tr->cap < 0 || tr->n_snap < 0 || (tr->n_snap > 0 && (!tr->snap_iter || !tr->snap_x || !tr->snap_y)) ||
                (tr->cap > 0 && (!tr->attempts || !tr->eta_used || !tr->beta || !tr->omega ||
                                 !tr->check_code || !tr->check_kkt))))
@@ -569,6 +830,16 @@ static void solve_impl(pdcs_problem *P, const pdcs_settings *S, const double *x0
     hipStream_t s = P->stream;
     const int64_t n = P->n, m = P->m;
     ensure_scaling(P, S->ruiz_iters, S->pock_chambolle ? 1 : 0);
+    if (S->autotune && !P->tuned) {
+        autotune_spmv(P);
+        for (hipGraphExec_t &g : P->gexec)   // captured with the old plans
+            if (g) (void)hipGraphExecDestroy(g), g = nullptr;
+    }
+    bool mixed = S->precision == 1;
+    if (mixed) ensure_fp32(P);
+    int64_t polish_iter = mixed ? -1 : 0;
+    std::vector<double> best_mixed(B, INFINITY);
+    std::vector<int> stall(B, 0);
 
     // trace buffers
     const int64_t cap = tr ? tr->cap : 0;
@@ -588,62 +859,92 @@ static void solve_impl(pdcs_problem *P, const pdcs_settings *S, const double *x0
     }
 
     // z^{0,0}: the mapped starting point projected onto X x Y (reading)
-    if (x0) {
-        h2d(P->tmp_n, x0, n, s);
-        scale_in(P->tmp_n, P->f, P->x, n, s);
-    } else {
-        fill(P->x, n, 0.0, s);
+    fill(P->tmp_n, n, 0.0, s);
+    fill(P->tmp_m, m, 0.0, s);
+    for (int64_t b = 0; b < B; ++b) {
+        const InstDims &I = P->inst[b];
+        if (x0 && x0[b]) h2d(P->tmp_n + I.x0, x0[b], I.n, s);
+        if (y0 && y0[b]) h2d(P->tmp_m + I.y0, y0[b], I.m, s);
     }
-    if (y0) {
-        h2d(P->tmp_m, y0, m, s);
-        scale_in(P->tmp_m, P->e, P->y, m, s);
-    } else {
-        fill(P->y, m, 0.0, s);
-    }
+    scale_in(P->tmp_n, P->f, P->x, n, s);
+    scale_in(P->tmp_m, P->e, P->y, m, s);
     pass_candidate(P->planX, false, CandArgs{P->x, P->ls, P->us, P->dx, P->st, 0, P->xa}, P->partX, s);
     pass_candidate(P->planY, true, CandArgs{P->y, P->ls, P->us, P->dy, P->st, 0, P->ya}, P->partY, s);
-    spmv(P->Gs, P->pG, P->xa, P->gx0, nullptr, s);
-    spmv(P->Gts, P->pGt, P->ya, P->aty0, nullptr, s);
-    restart_copy(n, m, P->xa, P->ya, P->gx0, P->aty0, P->x, P->y, P->xa, P->ya, P->gx, P->aty,
-                 P->gx0, P->aty0, P->xsum, P->ysum, s);
-    long long spmv_count = 2;
+    spmv(P->Gs, P->pG, P->xa, P->gx0, SpmvSkip{}, s);
+    spmv(P->Gts, P->pGt, P->ya, P->aty0, SpmvSkip{}, s);
+    RestartArgs ra{n, m, {P->xa, P->xc[1]}, {P->ya, P->yc[1]}, {P->gx0, P->gxc[1]},
+                   {P->aty0, P->atyc[1]}, nullptr, P->x_inst, P->y_inst,
+                   P->x, P->y, P->xa, P->ya, P->gx, P->aty, P->gx0, P->aty0, P->xsum, P->ysum};
+    restart_copy(ra, s);
     enqueue_kkt(P, P->xa, P->ya, P->gx0, P->aty0, P->xa, P->ya, P->e, P->f, 2);
-    KktRaw raw[3];
-    d2h(raw + 2, P->kraw + 2, 1, s);
+    std::vector<KktRaw> raw(3 * B);
+    d2h(raw.data() + 2 * B, P->kraw + 2 * B, B, s);
 
-    DevState hs{};
-    hs.eta = P->gmax > 0.0 ? 1.0 / P->gmax : 1.0;
-    if (S->step_mode == 1) hs.eta = fixed_step(P, S);
-    hs.omega = (P->cs_norm > 1e-10 && P->hs_norm > 1e-10) ? P->cs_norm / P->hs_norm : 1.0;
-    if (omega0 > 0.0) hs.omega = omega0;
-    hs.tau = hs.eta / hs.omega, hs.sigma = hs.eta * hs.omega;
-    hs.beta_prev = 1.0, hs.r_prev = INFINITY;
-    hs.max_iter = S->max_iter, hs.check_every = S->check_every, hs.max_attempts = S->max_attempts;
-    hs.beta_mode = S->beta_mode, hs.beta_const = S->beta_const, hs.beta_grow = S->beta_grow;
-    hs.step_mode = S->step_mode;
-    hs.beta_shrink = S->beta_shrink, hs.step_reduce_exp = S->step_reduce_exp;
-    hs.step_grow_exp = S->step_grow_exp;
-    hs.log_cap = cap, hs.log_attempts = log_att, hs.log_eta = log_eta, hs.log_beta = log_beta,
-    hs.log_omega = log_om;
-    hs.skip_update = 1, hs.status = -1;
+    std::vector<double> eta0(B);
+    if (S->step_mode == 1) eta0 = fixed_step(P, S);
+    std::vector<DevState> hs(B);
+    std::vector<Kkt> k_anchor(B), kout(B);
+    std::vector<int> status(B, -1), out_src(B, -2);   // -2: not written yet
+    // writes instance b's unscaled output from the anchor (src -1) or a
+    // candidate (0, 1); enqueued on s before any later pass reuses the buffers
+    auto emit = [&](int64_t b, int src) {
+        const InstDims &I = P->inst[b];
+        const double *sx = src < 0 ? P->xa : P->xc[src];
+        const double *sy = src < 0 ? P->ya : P->yc[src];
+        if (S->out_on_device) {
+            unscale(sx + I.x0, P->f + I.x0, xo[b], I.n, s);
+            unscale(sy + I.y0, P->e + I.y0, yo[b], I.m, s);
+        } else {
+            unscale(sx + I.x0, P->f + I.x0, P->tmp_n + I.x0, I.n, s);
+            unscale(sy + I.y0, P->e + I.y0, P->tmp_m + I.y0, I.m, s);
+            d2h(xo[b], P->tmp_n + I.x0, I.n, s);
+            d2h(yo[b], P->tmp_m + I.y0, I.m, s);
+        }
+        out_src[b] = src;
+    };
+    std::vector<double> kprev_avg(B, INFINITY);
+    std::vector<long long> restarts(B, 0), checks(B, 0);
     PDCS_HIP(hipStreamSynchronize(s));
-    Kkt k_anchor = kkt_from_raw(P, raw[2]);
-    int status = -1;
-    Kkt kout = k_anchor;
-    const double *outx = P->xa, *outy = P->ya;
-    if (k_anchor.mx() <= S->tol) status = PDCS_SOLVE_OPTIMAL;
-    if (!(k_anchor.mx() == k_anchor.mx())) status = PDCS_SOLVE_NUMERICAL;
-    if (status < 0 && S->max_iter <= 0) status = PDCS_SOLVE_ITER_LIMIT;
-    hs.halt = status >= 0 ? 1 : 0;
-    h2d(P->st, &hs, 1, s);
+    for (int64_t b = 0; b < B; ++b) {
+        DevState &h = hs[b];
+        h = DevState{};
+        h.eta = S->step_mode == 1 ? eta0[b] : (P->gmax[b] > 0.0 ? 1.0 / P->gmax[b] : 1.0);
+        h.omega = (P->cs_norm[b] > 1e-10 && P->hs_norm[b] > 1e-10) ? P->cs_norm[b] / P->hs_norm[b] : 1.0;
+        if (omega0 && omega0[b] > 0.0) h.omega = omega0[b];
+        h.tau = h.eta / h.omega, h.sigma = h.eta * h.omega;
+        h.beta_prev = 1.0, h.r_prev = INFINITY;
+        h.max_iter = S->max_iter, h.check_every = S->check_every, h.max_attempts = S->max_attempts;
+        h.beta_mode = S->beta_mode, h.beta_const = S->beta_const, h.beta_grow = S->beta_grow;
+        h.step_mode = S->step_mode;
+        h.beta_shrink = S->beta_shrink, h.step_reduce_exp = S->step_reduce_exp;
+        h.step_grow_exp = S->step_grow_exp;
+        h.log_cap = cap, h.log_attempts = log_att, h.log_eta = log_eta, h.log_beta = log_beta,
+        h.log_omega = log_om;
+        h.skip_update = 1, h.status = -1;
+        k_anchor[b] = kout[b] = kkt_from_raw(P, b, raw[2 * B + b]);
+        if (k_anchor[b].mx() <= S->tol) status[b] = PDCS_SOLVE_OPTIMAL;
+        if (!(k_anchor[b].mx() == k_anchor[b].mx())) status[b] = PDCS_SOLVE_NUMERICAL;
+        if (status[b] < 0 && S->max_iter <= 0) status[b] = PDCS_SOLVE_ITER_LIMIT;
+        h.halt = status[b] >= 0 ? 1 : 0;
+    }
+    h2d(P->st, hs.data(), B, s);
     const auto t_iter = clk::now();
     const double setup_s = std::chrono::duration<double>(t_iter - t_start).count();
 
-    double kprev_avg = INFINITY;
-    long long restarts = 0;
+    auto active = [&](int64_t b) { return status[b] < 0; };
+    auto any_running = [&]() {
+        for (int64_t b = 0; b < B; ++b)
+            if (active(b) && !hs[b].halt) return true;
+        return false;
+    };
+    auto any_active = [&]() {
+        for (int64_t b = 0; b < B; ++b)
+            if (active(b)) return true;
+        return false;
+    };
     int64_t snap = 0;
     const bool stepwise = tr && (tr->cap > 0 || tr->n_snap > 0);
-    long long prev_attempts = 0;
+    std::vector<long long> prev_att(B, 0);
     constexpr int E = PDCS_K_COUNT + 1;
     double kms[PDCS_K_COUNT] = {};
     int64_t klaunch[PDCS_K_COUNT] = {};
@@ -651,42 +952,48 @@ static void solve_impl(pdcs_problem *P, const pdcs_settings *S, const double *x0
         P->tev.resize(E * kGraphBatch, nullptr);
         for (hipEvent_t &e : P->tev) PDCS_HIP(hipEventCreate(&e));
     }
-    while (status < 0) {
-        // ---- step attempts until the device asks for a check ----
-        while (!hs.halt) {
-            const long long todo = S->check_every - hs.kin % S->check_every;
-            const long long batch =
-                stepwise ? 1 : std::max<long long>(1, std::min<long long>(todo, kGraphBatch));
+    std::vector<int32_t> code(B, 0);
+    while (any_active()) {
+        // ---- step attempts until every running instance asks for a check ----
+        while (any_running()) {
+            long long todo = kGraphBatch;
+            for (int64_t b = 0; b < B; ++b)
+                if (active(b) && !hs[b].halt)
+                    todo = std::min<long long>(todo, S->check_every - hs[b].kin % S->check_every);
+            const long long batch = stepwise ? 1 : std::max<long long>(1, todo);
             if (S->time_kernels) {
-                enqueue_attempts(P, batch, s, P->tev.data());
+                enqueue_attempts(P, batch, mixed, s, P->tev.data());
             } else if (S->use_graph && batch == kGraphBatch) {
-                ensure_graph(P);
-                run_graph(P, s);
+                ensure_graph(P, mixed);
+                run_graph(P, mixed, s);
             } else {
-                enqueue_attempts(P, batch, s);
+                enqueue_attempts(P, batch, mixed, s);
             }
-            const long long it_before = hs.n_iter;
-            const long long att_before = hs.attempts_total + hs.attempts_cur;
-            d2h(&hs, P->st, 1, s);
+            const long long it_before = hs[0].n_iter;
+            std::vector<long long> att_before(B), acc_before(B);
+            for (int64_t b = 0; b < B; ++b)
+                att_before[b] = hs[b].attempts_total + hs[b].attempts_cur, acc_before[b] = hs[b].n_iter;
+            d2h(hs.data(), P->st, B, s);
             PDCS_HIP(hipStreamSynchronize(s));
             if (S->time_kernels) {
-                // attempts run in order and the device halts only at the end of a
-                // batch, so the first `worked` attempts are the ones that did work
-                const long long worked = hs.attempts_total + hs.attempts_cur - att_before;
-                for (long long b = 0; b < worked && b < batch; ++b)
+                // attempts run in order and an instance halts only at the end of
+                // a batch, so the first `worked` attempts did work somewhere
+                long long worked = 0, acc = 0;
+                for (int64_t b = 0; b < B; ++b) {
+                    worked = std::max(worked, hs[b].attempts_total + hs[b].attempts_cur - att_before[b]);
+                    acc = std::max(acc, hs[b].n_iter - acc_before[b]);
+                }
+                for (long long a = 0; a < worked && a < batch; ++a)
                     for (int j = 0; j < PDCS_K_COUNT; ++j) {
                         float ms = 0.0f;
-                        PDCS_HIP(hipEventElapsedTime(&ms, P->tev[E * b + j], P->tev[E * b + j + 1]));
+                        PDCS_HIP(hipEventElapsedTime(&ms, P->tev[E * a + j], P->tev[E * a + j + 1]));
                         kms[j] += ms;
                     }
-                const long long acc = hs.n_iter - it_before;
                 klaunch[PDCS_K_PRIMAL] += worked, klaunch[PDCS_K_SPMV_G] += worked;
                 klaunch[PDCS_K_DUAL] += worked, klaunch[PDCS_K_DECIDE] += worked;
                 klaunch[PDCS_K_SPMV_GT] += acc, klaunch[PDCS_K_HALPERN] += acc;
             }
-            spmv_count += (hs.attempts_total + hs.attempts_cur - prev_attempts) + (hs.n_iter - it_before);
-            prev_attempts = hs.attempts_total + hs.attempts_cur;
-            if (tr && snap < tr->n_snap && hs.n_iter > it_before && tr->snap_iter[snap] == hs.n_iter) {
+            if (tr && snap < tr->n_snap && hs[0].n_iter > it_before && tr->snap_iter[snap] == hs[0].n_iter) {
                 unscale(P->x, P->f, P->tmp_n, n, s);
                 unscale(P->y, P->e, P->tmp_m, m, s);
                 d2h(tr->snap_x + snap * n, P->tmp_n, n, s);
@@ -695,90 +1002,115 @@ static void solve_impl(pdcs_problem *P, const pdcs_settings *S, const double *x0
                 ++snap;
             }
         }
-        if (hs.status == PDCS_SOLVE_NUMERICAL) {
-            status = PDCS_SOLVE_NUMERICAL;
-            break;
-        }
-        // ---- check: candidates P(z^{t,k}) and P(z_bar^{t,k}) ----
+        for (int64_t b = 0; b < B; ++b)
+            if (active(b) && hs[b].status == PDCS_SOLVE_NUMERICAL) status[b] = PDCS_SOLVE_NUMERICAL;
+        if (!any_active()) break;
+        // ---- check: candidates P(z^{t,k}) and P(z_bar^{t,k}) of every instance ----
         pass_candidate(P->planX, false, CandArgs{P->x, P->ls, P->us, P->dx, P->st, 0, P->xc[0]}, P->partX, s);
         pass_candidate(P->planY, true, CandArgs{P->y, P->ls, P->us, P->dy, P->st, 0, P->yc[0]}, P->partY, s);
         pass_candidate(P->planX, false, CandArgs{P->xsum, P->ls, P->us, P->dx, P->st, 1, P->xc[1]}, P->partX, s);
         pass_candidate(P->planY, true, CandArgs{P->ysum, P->ls, P->us, P->dy, P->st, 1, P->yc[1]}, P->partY, s);
         for (int cnd = 0; cnd < 2; ++cnd) {
-            spmv(P->Gs, P->pG, P->xc[cnd], P->gxc[cnd], nullptr, s);
-            spmv(P->Gts, P->pGt, P->yc[cnd], P->atyc[cnd], nullptr, s);
+            spmv(P->Gs, P->pG, P->xc[cnd], P->gxc[cnd], SpmvSkip{}, s);
+            spmv(P->Gts, P->pGt, P->yc[cnd], P->atyc[cnd], SpmvSkip{}, s);
             enqueue_kkt(P, P->xc[cnd], P->yc[cnd], P->gxc[cnd], P->atyc[cnd], P->xa, P->ya, P->e, P->f, cnd);
         }
-        spmv_count += 4;
-        d2h(raw, P->kraw, 2, s);
+        d2h(raw.data(), P->kraw, 2 * B, s);
         PDCS_HIP(hipStreamSynchronize(s));
-        const Kkt k1 = kkt_from_raw(P, raw[0]), k2 = kkt_from_raw(P, raw[1]);
-        const int chosen = k2.avg() < k1.avg() ? 1 : 0;
-        const Kkt kc = chosen ? k2 : k1;
-        const double kcv = kc.avg(), kav = k_anchor.avg();
-        int reason = 0, stop = 0;
         const double elapsed = std::chrono::duration<double>(clk::now() - t_iter).count();
-        if (!(kcv == kcv)) {
-            status = PDCS_SOLVE_NUMERICAL, stop = 1;
-        } else if (kc.mx() <= S->tol) {
-            status = PDCS_SOLVE_OPTIMAL, stop = 1;
-        } else if (hs.n_iter >= S->max_iter) {
-            status = PDCS_SOLVE_ITER_LIMIT, stop = 1;
-        } else if (S->time_limit > 0.0 && elapsed >= S->time_limit) {
-            status = PDCS_SOLVE_TIME_LIMIT, stop = 1;
+        bool any_restart = false, switch_ok = mixed;
+        for (int64_t b = 0; b < B; ++b) {
+            code[b] = 0;
+            if (!active(b)) continue;
+            DevState &h = hs[b];
+            ++checks[b];
+            const Kkt k1 = kkt_from_raw(P, b, raw[b]), k2 = kkt_from_raw(P, b, raw[B + b]);
+            const int chosen = k2.avg() < k1.avg() ? 1 : 0;
+            const Kkt kc = chosen ? k2 : k1;
+            const double kcv = kc.avg(), kav = k_anchor[b].avg();
+            int reason = 0, stop = 0;
+            if (!(kcv == kcv)) {
+                status[b] = PDCS_SOLVE_NUMERICAL, stop = 1;
+            } else if (kc.mx() <= S->tol) {
+                status[b] = PDCS_SOLVE_OPTIMAL, stop = 1;
+            } else if (h.n_iter >= S->max_iter) {
+                status[b] = PDCS_SOLVE_ITER_LIMIT, stop = 1;
+            } else if (S->time_limit > 0.0 && elapsed >= S->time_limit) {
+                status[b] = PDCS_SOLVE_TIME_LIMIT, stop = 1;
+            }
+            if (!stop) {
+                if (kcv <= S->restart_sufficient * kav)
+                    reason = 1;
+                else if (kcv <= S->restart_necessary * kav && kcv > kprev_avg[b])
+                    reason = 2;
+                else if ((double)h.kin >= S->restart_artificial * (double)h.n_iter)
+                    reason = 3;
+            }
+            const int64_t rec = h.n_iter - 1;
+            if (tr && rec >= 0 && rec < cap) {
+                tr->check_code[rec] = 1 + chosen + 2 * reason + 8 * stop;
+                tr->check_kkt[rec] = kcv;
+            }
+            if (stop) {
+                kout[b] = kc;
+                h.halt = 1;   // finished: its tiles and rows stay idle
+                emit(b, chosen);
+                continue;
+            }
+            if (reason) {
+                // PrimalWeightUpdate (reading: PDLP's smoothed log-ratio rule)
+                const double ddx = std::sqrt(kc.dx2), ddy = std::sqrt(kc.dy2);
+                if (ddx > 1e-10 && ddy > 1e-10)
+                    h.omega = std::exp(0.5 * std::log(ddy / ddx) + 0.5 * std::log(h.omega));
+                code[b] = 1 + chosen;
+                any_restart = true;
+                k_anchor[b] = kc;
+                kprev_avg[b] = INFINITY;
+                h.kin = 0;
+                h.eta_sum = 0.0;
+                h.beta_prev = 1.0;
+                h.r_prev = INFINITY;
+                h.tau = h.eta / h.omega, h.sigma = h.eta * h.omega;
+                ++restarts[b];
+            } else {
+                kprev_avg[b] = kcv;
+            }
+            if (mixed) {
+                if (kc.mx() < best_mixed[b]) best_mixed[b] = kc.mx(), stall[b] = 0;
+                else ++stall[b];
+                if (!(kc.mx() <= S->polish_tol || stall[b] >= S->polish_stall)) switch_ok = false;
+            }
         }
-        if (!stop) {
-            if (kcv <= S->restart_sufficient * kav)
-                reason = 1;
-            else if (kcv <= S->restart_necessary * kav && kcv > kprev_avg)
-                reason = 2;
-            else if ((double)hs.kin >= S->restart_artificial * (double)hs.n_iter)
-                reason = 3;
+        if (any_restart) {
+            h2d(P->rcode, code.data(), B, s);
+            RestartArgs rc{n, m, {P->xc[0], P->xc[1]}, {P->yc[0], P->yc[1]}, {P->gxc[0], P->gxc[1]},
+                           {P->atyc[0], P->atyc[1]}, P->rcode, P->x_inst, P->y_inst,
+                           P->x, P->y, P->xa, P->ya, P->gx, P->aty, P->gx0, P->aty0, P->xsum, P->ysum};
+            restart_copy(rc, s);
         }
-        const int64_t rec = hs.n_iter - 1;
-        if (tr && rec >= 0 && rec < cap) {
-            tr->check_code[rec] = 1 + chosen + 2 * reason + 8 * stop;
-            tr->check_kkt[rec] = kcv;
+        if (mixed && switch_ok && any_active()) {
+            // polish phase: FP64 products from here on (reading: the switch rule);
+            // the kept products are recomputed in FP64 (a restart brought them
+            // with its candidate already; recomputing gives the same bits)
+            mixed = false;
+            for (int64_t b = 0; b < B; ++b)
+                if (active(b)) { polish_iter = hs[b].n_iter; break; }
+            spmv(P->Gs, P->pG, P->x, P->gx, SpmvSkip{}, s);
+            spmv(P->Gts, P->pGt, P->y, P->aty, SpmvSkip{}, s);
+            spmv(P->Gs, P->pG, P->xa, P->gx0, SpmvSkip{}, s);
+            spmv(P->Gts, P->pGt, P->ya, P->aty0, SpmvSkip{}, s);
+            for (int64_t b = 0; b < B; ++b) checks[b] += 1;   // four more products each
         }
-        if (stop) {
-            outx = P->xc[chosen], outy = P->yc[chosen];
-            kout = kc;
-            break;
-        }
-        if (reason) {
-            // PrimalWeightUpdate (reading: PDLP's smoothed log-ratio rule)
-            const double ddx = std::sqrt(kc.dx2), ddy = std::sqrt(kc.dy2);
-            if (ddx > 1e-10 && ddy > 1e-10)
-                hs.omega = std::exp(0.5 * std::log(ddy / ddx) + 0.5 * std::log(hs.omega));
-            restart_copy(n, m, P->xc[chosen], P->yc[chosen], P->gxc[chosen], P->atyc[chosen], P->x,
-                         P->y, P->xa, P->ya, P->gx, P->aty, P->gx0, P->aty0, P->xsum, P->ysum, s);
-            k_anchor = kc;
-            kprev_avg = INFINITY;
-            hs.kin = 0;
-            hs.eta_sum = 0.0;
-            hs.beta_prev = 1.0;
-            hs.r_prev = INFINITY;
-            hs.tau = hs.eta / hs.omega, hs.sigma = hs.eta * hs.omega;
-            ++restarts;
-        } else {
-            kprev_avg = kcv;
-        }
-        hs.halt = 0;
-        h2d(P->st, &hs, 1, s);
+        for (int64_t b = 0; b < B; ++b)
+            if (active(b)) hs[b].halt = 0;
+        h2d(P->st, hs.data(), B, s);
     }
 
-    // ---- outputs (unscaled) ----
-    if (S->out_on_device) {
-        unscale(outx, P->f, xo, n, s);
-        unscale(outy, P->e, yo, m, s);
-    } else {
-        unscale(outx, P->f, P->tmp_n, n, s);
-        unscale(outy, P->e, P->tmp_m, m, s);
-        d2h(xo, P->tmp_n, n, s);
-        d2h(yo, P->tmp_m, m, s);
-    }
+    // ---- outputs of the instances that ended without a final check: the anchor ----
+    for (int64_t b = 0; b < B; ++b)
+        if (out_src[b] == -2) emit(b, -1);
     if (tr && cap > 0) {
-        const int64_t cnt = std::min<int64_t>(cap, hs.n_iter);
+        const int64_t cnt = std::min<int64_t>(cap, hs[0].n_iter);
         d2h(tr->attempts, log_att, cnt, s);
         d2h(tr->eta_used, log_eta, cnt, s);
         d2h(tr->beta, log_beta, cnt, s);
@@ -787,9 +1119,16 @@ static void solve_impl(pdcs_problem *P, const pdcs_settings *S, const double *x0
     }
     PDCS_HIP(hipStreamSynchronize(s));
     const double solve_s = std::chrono::duration<double>(clk::now() - t_iter).count();
-    fill_info(info, status, hs, restarts, spmv_count, kout, setup_s, solve_s);
-    if (info)
-        for (int j = 0; j < PDCS_K_COUNT; ++j) info->kernel_ms[j] = kms[j], info->kernel_launches[j] = klaunch[j];
+    for (int64_t b = 0; b < B; ++b) {
+        if (!infos) break;
+        // products: one with G~ per attempt, one with G~^T per accepted
+        // iteration, two at the start and four per check
+        const long long spmv_count = hs[b].attempts_total + hs[b].attempts_cur + hs[b].n_iter + 2 + 4 * checks[b];
+        fill_info(infos + b, status[b], hs[b], restarts[b], spmv_count, kout[b], setup_s, solve_s);
+        for (int j = 0; j < PDCS_K_COUNT; ++j)
+            infos[b].kernel_ms[j] = kms[j], infos[b].kernel_launches[j] = klaunch[j];
+        infos[b].polish_iter = polish_iter;
+    }
 }
 
 // --------------------------------------------------------------------- ABI
@@ -846,6 +1185,10 @@ pdcs_status pdcs_settings_default(pdcs_settings *s) {
     s->power_iters = 100;
     s->use_graph = 1;
     s->time_kernels = 0;
+    s->precision = 0;
+    s->polish_tol = 1e-5;
+    s->polish_stall = 8;
+    s->autotune = 0;
     return PDCS_OK;
 }
 
@@ -855,7 +1198,7 @@ pdcs_status pdcs_problem_create(const pdcs_problem_desc *desc, void *hip_stream,
         return PDCS_ERR_INVALID_ARG;
     }
     *out = nullptr;
-    return guarded([&] { *out = create_impl(desc, hip_stream, false); });
+    return guarded([&] { *out = create_impl(desc, 1, hip_stream, false); });
 }
 
 pdcs_status pdcs_problem_create_device(const pdcs_problem_desc *desc, void *hip_stream,
@@ -865,7 +1208,7 @@ pdcs_status pdcs_problem_create_device(const pdcs_problem_desc *desc, void *hip_
         return PDCS_ERR_INVALID_ARG;
     }
     *out = nullptr;
-    return guarded([&] { *out = create_impl(desc, hip_stream, true); });
+    return guarded([&] { *out = create_impl(desc, 1, hip_stream, true); });
 }
 
 void pdcs_problem_destroy(pdcs_problem *p) {
@@ -879,7 +1222,7 @@ pdcs_status pdcs_solve(pdcs_problem *p, const pdcs_settings *settings, const dou
                        pdcs_info *info, pdcs_trace *trace) {
     return guarded([&] {
         if (!p) fail(PDCS_ERR_INVALID_ARG, "problem is NULL");
-        solve_impl(p, settings, x0, y0, omega0, x_out, y_out, info, trace);
+        solve_batch(p, settings, &x0, &y0, &omega0, &x_out, &y_out, info, trace);
     });
 }
 
@@ -900,9 +1243,27 @@ pdcs_status pdcs_spmv(pdcs_problem *p, int transpose, const double *x_dev, doubl
         if (!p || !x_dev || !y_dev) fail(PDCS_ERR_INVALID_ARG, "NULL argument");
         hipStream_t s = hip_stream ? (hipStream_t)hip_stream : p->stream;
         if (transpose)
-            spmv(p->Gt, p->pGt, x_dev, y_dev, nullptr, s);
+            spmv(p->Gt, p->pGt, x_dev, y_dev, SpmvSkip{}, s);
         else
-            spmv(p->G, p->pG, x_dev, y_dev, nullptr, s);
+            spmv(p->G, p->pG, x_dev, y_dev, SpmvSkip{}, s);
+    });
+}
+
+pdcs_status pdcs_spmv32(pdcs_problem *p, int transpose, const double *x_dev, double *y_dev,
+                        void *hip_stream) {
+    return guarded([&] {
+        if (!p || !x_dev || !y_dev) fail(PDCS_ERR_INVALID_ARG, "NULL argument");
+        hipStream_t s = hip_stream ? (hipStream_t)hip_stream : p->stream;
+        if (!p->G.v32) {   // FP32 copies of the unscaled values, made on first use
+            float *g32 = p->mem.alloc<float>(p->nnz), *gt32 = p->mem.alloc<float>(p->nnz);
+            to_float(p->G.v, g32, p->nnz, s);
+            to_float(p->Gt.v, gt32, p->nnz, s);
+            p->x32 = p->mem.alloc<float>(std::max(p->n, p->m));
+            p->G.v32 = g32, p->Gt.v32 = gt32;
+        }
+        const Csr &A = transpose ? p->Gt : p->G;
+        to_float(x_dev, p->x32, A.cols, s);
+        spmv32(A, transpose ? p->pGt : p->pG, p->x32, y_dev, SpmvSkip{}, s);
     });
 }
 
@@ -910,13 +1271,13 @@ pdcs_status pdcs_kkt(pdcs_problem *p, const double *x_dev, const double *y_dev, 
     return guarded([&] {
         if (!p || !x_dev || !y_dev || !out) fail(PDCS_ERR_INVALID_ARG, "NULL argument");
         hipStream_t s = p->stream;
-        spmv(p->G, p->pG, x_dev, p->gxc[0], nullptr, s);
-        spmv(p->Gt, p->pGt, y_dev, p->atyc[0], nullptr, s);
+        spmv(p->G, p->pG, x_dev, p->gxc[0], SpmvSkip{}, s);
+        spmv(p->Gt, p->pGt, y_dev, p->atyc[0], SpmvSkip{}, s);
         enqueue_kkt(p, x_dev, y_dev, p->gxc[0], p->atyc[0], x_dev, y_dev, p->ones_m, p->ones_n, 0);
         KktRaw r;
         d2h(&r, p->kraw, 1, s);
         PDCS_HIP(hipStreamSynchronize(s));
-        const Kkt k = kkt_from_raw(p, r);
+        const Kkt k = kkt_from_raw(p, 0, r);
         out[0] = k.err_p, out[1] = k.err_d, out[2] = k.err_gap, out[3] = k.pobj, out[4] = k.dobj;
     });
 }
@@ -938,6 +1299,179 @@ pdcs_status pdcs_project(int64_t nblocks, const int32_t *types, const int64_t *d
         pass_project(plan, dual != 0, ProjArgs{v_dev, d_dev}, part, s);
         PDCS_HIP(hipStreamSynchronize(s));
     });
+}
+
+pdcs_status pdcs_batch_create(const pdcs_problem_desc *descs, int64_t count, void *hip_stream,
+                              pdcs_batch **out) {
+    if (!out) {
+        g_last_error = "out is NULL";
+        return PDCS_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    return guarded([&] {
+        std::unique_ptr<pdcs_problem> p(create_impl(descs, count, hip_stream, false));
+        *out = new pdcs_batch{p.release()};
+    });
+}
+
+pdcs_status pdcs_batch_solve(pdcs_batch *b, const pdcs_settings *settings, double *const *x_out,
+                             double *const *y_out, pdcs_info *infos) {
+    return guarded([&] {
+        if (!b || !b->p) fail(PDCS_ERR_INVALID_ARG, "batch is NULL");
+        solve_batch(b->p, settings, nullptr, nullptr, nullptr, x_out, y_out, infos, nullptr);
+    });
+}
+
+int64_t pdcs_batch_size(const pdcs_batch *b) { return b && b->p ? b->p->B : 0; }
+
+void pdcs_batch_destroy(pdcs_batch *b) {
+    if (!b) return;
+    if (b->p) {
+        (void)hipStreamSynchronize(b->p->stream);
+        delete b->p;
+    }
+    delete b;
+}
+
+pdcs_status pdcs_gemm_bf16(int ta, int tb, int64_t M, int64_t N, int64_t K, const uint16_t *a,
+                           int64_t lda, const uint16_t *b, int64_t ldb, const float *bias, int relu,
+                           float *c32, uint16_t *c16, int64_t ldc, void *hip_stream) {
+    return guarded([&] {
+        if (M < 0 || N < 0 || K < 0 || (M && N && K && (!a || !b)) || (!c32 && !c16))
+            fail(PDCS_ERR_INVALID_ARG, "bad GEMM arguments");
+        if (lda < (ta ? M : K) || ldb < (tb ? K : N) || ldc < N)
+            fail(PDCS_ERR_INVALID_ARG, "leading dimension too small");
+        gemm_bf16(ta, tb, M, N, K, a, lda, b, ldb, bias, relu, c32, c16, ldc, (hipStream_t)hip_stream);
+    });
+}
+
+pdcs_status pdcs_mlp_create(int64_t in, int64_t hid, int64_t out, int64_t max_batch,
+                            const float *params, void *hip_stream, pdcs_mlp **mlp) {
+    if (!mlp) {
+        g_last_error = "out is NULL";
+        return PDCS_ERR_INVALID_ARG;
+    }
+    *mlp = nullptr;
+    return guarded([&] {
+        if (in < 1 || hid < 1 || out < 1 || max_batch < 1 || !params) fail(PDCS_ERR_INVALID_ARG, "bad sizes");
+        auto M = std::make_unique<pdcs_mlp>();
+        M->in = in, M->hid = hid, M->out = out, M->cap = max_batch;
+        M->stream = (hipStream_t)hip_stream;
+        M->off[0] = 0;
+        M->off[1] = M->off[0] + hid * in;
+        M->off[2] = M->off[1] + hid;
+        M->off[3] = M->off[2] + hid * hid;
+        M->off[4] = M->off[3] + hid;
+        M->off[5] = M->off[4] + out * hid;
+        M->np = M->off[5] + out;
+        DevMem &D = M->mem;
+        hipStream_t s = M->stream;
+        M->p = D.alloc<float>(M->np), M->g = D.alloc<float>(M->np);
+        M->m1 = D.alloc<float>(M->np), M->m2 = D.alloc<float>(M->np);
+        M->p16 = D.alloc<uint16_t>(M->np);
+        h2d(M->p, params, M->np, s);
+        to_bf16(M->p, M->p16, M->np, s);
+        PDCS_HIP(hipMemsetAsync(M->m1, 0, sizeof(float) * M->np, s));
+        PDCS_HIP(hipMemsetAsync(M->m2, 0, sizeof(float) * M->np, s));
+        const int64_t B = max_batch;
+        M->xb = D.alloc<uint16_t>(B * in);
+        M->h1 = D.alloc<float>(B * hid), M->h1b = D.alloc<uint16_t>(B * hid);
+        M->h2 = D.alloc<float>(B * hid), M->h2b = D.alloc<uint16_t>(B * hid);
+        M->o = D.alloc<float>(B * out);
+        M->d32 = D.alloc<float>(B * std::max(out, hid)), M->d16 = D.alloc<uint16_t>(B * std::max(out, hid));
+        M->dh = D.alloc<float>(B * hid);
+        M->part = D.alloc<double>((B * std::max(out, hid) + 255) / 256);
+        PDCS_HIP(hipStreamSynchronize(s));
+        *mlp = M.release();
+    });
+}
+
+int64_t pdcs_mlp_num_params(const pdcs_mlp *m) { return m ? m->np : 0; }
+
+static void mlp_forward(pdcs_mlp *M, const float *theta, int64_t B, float *out) {
+    hipStream_t s = M->stream;
+    const int64_t in = M->in, hid = M->hid, O = M->out;
+    to_bf16(theta, M->xb, B * in, s);
+    gemm_bf16(0, 1, B, hid, in, M->xb, in, M->p16 + M->off[0], in, M->p + M->off[1], 1, M->h1, M->h1b, hid, s);
+    gemm_bf16(0, 1, B, hid, hid, M->h1b, hid, M->p16 + M->off[2], hid, M->p + M->off[3], 1, M->h2, M->h2b, hid, s);
+    gemm_bf16(0, 1, B, O, hid, M->h2b, hid, M->p16 + M->off[4], hid, M->p + M->off[5], 0, out, nullptr, O, s);
+}
+
+// Gradient of L = (1 / (2 B out)) sum (o - target)^2 into M->g; returns L.
+static double mlp_gradient(pdcs_mlp *M, const float *theta, const float *target, int64_t B) {
+    hipStream_t s = M->stream;
+    const int64_t in = M->in, hid = M->hid, O = M->out;
+    mlp_forward(M, theta, B, M->o);
+    const int64_t n = B * O, nblk = (n + 255) / 256;
+    mse_grad(M->o, target, n, (float)(1.0 / (double)n), M->d32, M->d16, M->part, s);
+    float *g = M->g;
+    // layer 3: dW3 = dO^T H2, db3 = colsum(dO), dH2 = dO W3
+    gemm_bf16(1, 0, O, hid, B, M->d16, O, M->h2b, hid, nullptr, 0, g + M->off[4], nullptr, hid, s);
+    colsum(M->d32, B, O, g + M->off[5], s);
+    gemm_bf16(0, 0, B, hid, O, M->d16, O, M->p16 + M->off[4], hid, nullptr, 0, M->dh, nullptr, hid, s);
+    // layer 2
+    relu_back(M->dh, M->h2, B * hid, M->d32, M->d16, s);
+    gemm_bf16(1, 0, hid, hid, B, M->d16, hid, M->h1b, hid, nullptr, 0, g + M->off[2], nullptr, hid, s);
+    colsum(M->d32, B, hid, g + M->off[3], s);
+    gemm_bf16(0, 0, B, hid, hid, M->d16, hid, M->p16 + M->off[2], hid, nullptr, 0, M->dh, nullptr, hid, s);
+    // layer 1
+    relu_back(M->dh, M->h1, B * hid, M->d32, M->d16, s);
+    gemm_bf16(1, 0, hid, in, B, M->d16, hid, M->xb, in, nullptr, 0, g + M->off[0], nullptr, in, s);
+    colsum(M->d32, B, hid, g + M->off[1], s);
+    std::vector<double> part(nblk);
+    d2h(part.data(), M->part, nblk, s);
+    PDCS_HIP(hipStreamSynchronize(s));
+    double loss = 0.0;
+    for (double v : part) loss += v;
+    return loss / (2.0 * (double)n);
+}
+
+pdcs_status pdcs_mlp_forward(pdcs_mlp *m, const float *theta_dev, int64_t batch, float *out_dev) {
+    return guarded([&] {
+        if (!m || !theta_dev || !out_dev || batch < 1 || batch > m->cap) fail(PDCS_ERR_INVALID_ARG, "bad arguments");
+        mlp_forward(m, theta_dev, batch, out_dev);
+    });
+}
+
+pdcs_status pdcs_mlp_gradient(pdcs_mlp *m, const float *theta_dev, const float *target_dev,
+                              int64_t batch, float *grad_host, double *loss) {
+    return guarded([&] {
+        if (!m || !theta_dev || !target_dev || batch < 1 || batch > m->cap) fail(PDCS_ERR_INVALID_ARG, "bad arguments");
+        const double l = mlp_gradient(m, theta_dev, target_dev, batch);
+        if (loss) *loss = l;
+        if (grad_host) {
+            d2h(grad_host, m->g, m->np, m->stream);
+            PDCS_HIP(hipStreamSynchronize(m->stream));
+        }
+    });
+}
+
+pdcs_status pdcs_mlp_train_step(pdcs_mlp *m, const float *theta_dev, const float *target_dev,
+                                int64_t batch, float lr, double *loss) {
+    return guarded([&] {
+        if (!m || !theta_dev || !target_dev || batch < 1 || batch > m->cap || !(lr > 0.0f))
+            fail(PDCS_ERR_INVALID_ARG, "bad arguments");
+        const double l = mlp_gradient(m, theta_dev, target_dev, batch);
+        if (loss) *loss = l;
+        m->step += 1;
+        const float b1 = 0.9f, b2 = 0.999f;
+        const float c1 = 1.0f - std::pow(b1, (float)m->step), c2 = 1.0f - std::pow(b2, (float)m->step);
+        adam(m->p, m->g, m->m1, m->m2, m->np, lr, b1, b2, 1e-8f, c1, c2, m->p16, m->stream);
+    });
+}
+
+pdcs_status pdcs_mlp_get_params(const pdcs_mlp *m, float *params_host) {
+    return guarded([&] {
+        if (!m || !params_host) fail(PDCS_ERR_INVALID_ARG, "NULL argument");
+        d2h(params_host, m->p, m->np, m->stream);
+        PDCS_HIP(hipStreamSynchronize(m->stream));
+    });
+}
+
+void pdcs_mlp_destroy(pdcs_mlp *m) {
+    if (!m) return;
+    (void)hipStreamSynchronize(m->stream);
+    delete m;
 }
 
 const char *pdcs_status_string(pdcs_status s) {

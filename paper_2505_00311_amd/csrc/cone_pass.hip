@@ -36,13 +36,18 @@ struct OpPrimal {  // x^ = Proj_X(x - tau (c~ - G~^T y)), acc.s0 += (x^ - x)^2
     static constexpr bool kWarm = true;
     PrimalArgs a;
     double tau;
-    __device__ bool skip() const { return a.st->halt != 0; }
-    __device__ void begin() { tau = a.st->tau; }
+    const DevState *st;
+    __device__ void begin(int inst) {
+        st = a.st + inst;
+        tau = st->tau;
+    }
+    __device__ bool skip() const { return st->halt != 0; }
     __device__ double load(int64_t j) const { return a.x[j] - tau * (a.cs[j] - a.aty[j]); }
     __device__ double scale(int64_t j) const { return a.dx[j]; }
     __device__ double box(int64_t j, double v) const { return fmin(fmax(v, a.ls[j]), a.us[j]); }
     __device__ void store(int64_t j, double, double p, Acc &acc) const {
         a.xh[j] = p;
+        if (a.xh32) a.xh32[j] = (float)p;
         const double d = p - a.x[j];
         acc.s[0] += d * d;
     }
@@ -54,8 +59,12 @@ struct OpDual {  // y^ = Proj_Y(y + sigma (h~ - 2 G~x^ + G~x)), acc: |dy|^2, <dy
     static constexpr bool kWarm = true;
     DualArgs a;
     double sigma;
-    __device__ bool skip() const { return a.st->halt != 0; }
-    __device__ void begin() { sigma = a.st->sigma; }
+    const DevState *st;
+    __device__ void begin(int inst) {
+        st = a.st + inst;
+        sigma = st->sigma;
+    }
+    __device__ bool skip() const { return st->halt != 0; }
     __device__ double load(int64_t i) const {
         return a.y[i] + sigma * (a.hs[i] - 2.0 * a.gxh[i] + a.gx[i]);
     }
@@ -63,6 +72,7 @@ struct OpDual {  // y^ = Proj_Y(y + sigma (h~ - 2 G~x^ + G~x)), acc: |dy|^2, <dy
     __device__ double box(int64_t, double v) const { return v; }
     __device__ void store(int64_t i, double, double p, Acc &acc) const {
         a.yh[i] = p;
+        if (a.yh32) a.yh32[i] = (float)p;
         const double d = p - a.y[i];
         acc.s[0] += d * d;
         acc.s[1] += d * (a.gxh[i] - a.gx[i]);
@@ -75,8 +85,8 @@ struct OpCand {  // dst = Proj(src / div), div = 1 or the sum of step weights
     static constexpr bool kWarm = false;
     CandArgs a;
     double div;
+    __device__ void begin(int inst) { div = a.use_avg ? a.st[inst].eta_sum : 1.0; }
     __device__ bool skip() const { return false; }
-    __device__ void begin() { div = a.use_avg ? a.st->eta_sum : 1.0; }
     __device__ double load(int64_t j) const { return a.use_avg ? a.src[j] / div : a.src[j]; }
     __device__ double scale(int64_t j) const { return a.d[j]; }
     __device__ double box(int64_t j, double v) const { return fmin(fmax(v, a.ls[j]), a.us[j]); }
@@ -89,8 +99,8 @@ struct OpCand {  // dst = Proj(src / div), div = 1 or the sum of step weights
 struct OpKktRows {
     static constexpr bool kWarm = false;
     KktRowsArgs a;
+    __device__ void begin(int) {}
     __device__ bool skip() const { return false; }
-    __device__ void begin() {}
     __device__ double load(int64_t i) const { return a.gxc[i] / a.e[i] - a.h[i]; }
     __device__ double scale(int64_t) const { return 1.0; }
     __device__ double box(int64_t, double v) const { return v; }
@@ -111,8 +121,8 @@ struct OpKktRows {
 struct OpKktCols {
     static constexpr bool kWarm = false;
     KktColsArgs a;
+    __device__ void begin(int) {}
     __device__ bool skip() const { return false; }
-    __device__ void begin() {}
     __device__ double load(int64_t j) const { return a.c[j] - a.atyc[j] / a.f[j]; }
     __device__ double scale(int64_t) const { return 1.0; }
     __device__ double box(int64_t j, double lam) const {
@@ -141,8 +151,8 @@ struct OpKktCols {
 struct OpProject {
     static constexpr bool kWarm = false;
     ProjArgs a;
+    __device__ void begin(int) {}
     __device__ bool skip() const { return false; }
-    __device__ void begin() {}
     __device__ double load(int64_t j) const { return a.v[j]; }
     __device__ double scale(int64_t j) const { return a.d ? a.d[j] : 1.0; }
     __device__ double box(int64_t, double v) const { return v; }
@@ -291,9 +301,9 @@ __global__ __launch_bounds__(kBlock) void cone_pass_kernel(Op op, const Tile *__
                                                            double *__restrict__ partials,
                                                            double *__restrict__ soc_root,
                                                            double *__restrict__ exp_root) {
-    if (op.skip()) return;
-    op.begin();
     const Tile tl = tiles[blockIdx.x];
+    op.begin(tl.inst);
+    if (op.skip()) return;
     const int kind = DUAL ? dual_kind(tl.kind) : tl.kind;
     const int tid = threadIdx.x;
     Acc acc;

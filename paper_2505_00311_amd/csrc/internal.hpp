@@ -45,6 +45,8 @@ struct Tile {
     int32_t kind;
     int32_t count;   // entries (elementwise), blocks (SOC wave, exp) or 1 (SOC block)
     int64_t start;   // first entry (elementwise) or first block index
+    int32_t inst;    // instance of a batch the tile belongs to (0 for a single problem)
+    int32_t pad;
 };
 
 // Device view of a cone plan for one side (x or y).
@@ -57,13 +59,18 @@ struct ConePlan {
     int64_t n_soc = 0, n_exp = 0;
     double *soc_root = nullptr;   // last case-4 root per SOC block (s), NaN = none
     double *exp_root = nullptr;   // last case-4 root per exp block (rho), NaN = none
+    int64_t *inst_tiles = nullptr;  // [B+1]: tiles of instance b are [inst_tiles[b], inst_tiles[b+1])
 };
+
+// Instance of each entry of a batch (null for a single problem: instance 0).
+__host__ __device__ inline int inst_of(const int32_t *map, int64_t i) { return map ? map[i] : 0; }
 
 struct Csr {
     int64_t rows = 0, cols = 0, nnz = 0;
     int64_t *rp = nullptr;
     int32_t *ci = nullptr;
     double *v = nullptr;
+    float *v32 = nullptr;   // FP32 copy of v (mixed-precision form), or null
 };
 
 // Launch plan of one sparse product: short rows take `lanes` lanes each; rows
@@ -124,8 +131,21 @@ struct HipError {
 
 // ------------------------------------------------------------ launch wrappers
 // spmv.hip
-void spmv(const Csr &A, const SpmvPlan &plan, const double *x, double *y, const int *skip,
+// Rows whose instance's flag is set are skipped: `skip` names the flag in the
+// per-instance states (SkipNone, SkipHalt: st[b].halt, SkipUpdate:
+// st[b].skip_update), `row_inst` the instance of each row (null: instance 0).
+enum SkipFlag { SkipNone = 0, SkipHalt = 1, SkipUpdate = 2 };
+struct SpmvSkip {
+    const DevState *st = nullptr;
+    const int32_t *row_inst = nullptr;
+    int flag = SkipNone;
+};
+void spmv(const Csr &A, const SpmvPlan &plan, const double *x, double *y, const SpmvSkip &skip,
           hipStream_t s);
+// FP32 values (A.v32) and FP32 x, FP64 products and sums
+void spmv32(const Csr &A, const SpmvPlan &plan, const float *x, double *y, const SpmvSkip &skip,
+            hipStream_t s);
+void to_float(const double *in, float *out, int64_t n, hipStream_t s);
 int choose_lanes(double avg_row_nnz);
 
 // setup.hip
@@ -150,18 +170,25 @@ void div_vec(const double *a, const double *b, double *out, int64_t n, hipStream
 void mul_vec(const double *a, const double *b, double *out, int64_t n, hipStream_t s);
 void copy_vec(const double *a, double *out, int64_t n, hipStream_t s);
 // v = w / sqrt(*sumsq) on the device (no host round trip)
-void scale_by_inv_sqrt(const double *w, const double *sumsq, double *v, int64_t n, hipStream_t s);
+void scale_by_inv_sqrt(const double *w, const double *sumsq, const int32_t *map, double *v,
+                       int64_t n, hipStream_t s);
+void fill_by_inst(double *out, const int32_t *map, const double *vals, int64_t n, hipStream_t s);
+void reduce_segments(int mode, const double *a, const int64_t *off, int64_t B, double *out,
+                     hipStream_t s);
 
 // cone_pass.hip
+// `st` points at the batch's array of per-instance states (one for a single problem).
 struct PrimalArgs {
     const double *x, *aty, *cs, *ls, *us, *dx;
     double *xh;
     const DevState *st;
+    float *xh32 = nullptr;   // FP32 copy of x^ for the FP32 product (mixed form)
 };
 struct DualArgs {
     const double *y, *gxh, *gx, *hs, *dy;
     double *yh;
     const DevState *st;
+    float *yh32 = nullptr;   // FP32 copy of y^ for the FP32 product (mixed form)
 };
 struct CandArgs {  // projection of src / div onto the scaled set, into dst
     const double *src, *ls, *us, *d;
@@ -191,8 +218,10 @@ void pass_project(const ConePlan &p, bool dual, const ProjArgs &a, double *parti
                   hipStream_t s);
 
 // iterate.hip
-void decide(DevState *st, const double *px, int64_t ntx, const double *py, int64_t nty,
-            hipStream_t s);
+// One workgroup per instance b reduces the partials of its tiles ([tx[b],
+// tx[b+1]) and [ty[b], ty[b+1]); null ranges: all tiles, B = 1) and decides.
+void decide(DevState *st, int64_t B, const double *px, const int64_t *tx, int64_t ntx,
+            const double *py, const int64_t *ty, int64_t nty, hipStream_t s);
 struct HalpernArgs {
     double *x, *aty, *xsum;
     const double *xh, *atyh, *xa, *aty0;
@@ -200,15 +229,33 @@ struct HalpernArgs {
     const double *yh, *gxh, *ya, *gx0;
     int64_t n, m;
     const DevState *st;
+    const int32_t *x_inst = nullptr, *y_inst = nullptr;   // batch: instance per entry
 };
 void halpern(const HalpernArgs &a, hipStream_t s);
-void reduce_kkt(const double *prow, int64_t ntr, const double *pcol, int64_t ntc, KktRaw *out,
-                hipStream_t s);
-void restart_copy(int64_t n, int64_t m, const double *xc, const double *yc, const double *gxc,
-                  const double *atyc, double *x, double *y, double *xa, double *ya, double *gx,
-                  double *aty, double *gx0, double *aty0, double *xsum, double *ysum,
-                  hipStream_t s);
+void reduce_kkt(int64_t B, const double *prow, const int64_t *ty, int64_t ntr, const double *pcol,
+                const int64_t *tx, int64_t ntc, KktRaw *out, hipStream_t s);
+// Restart of each instance b with code[b] = 1 (from candidate set 0) or 2 (set
+// 1), 0 = untouched; code null: every entry from set 0.
+struct RestartArgs {
+    int64_t n, m;
+    const double *xc[2], *yc[2], *gxc[2], *atyc[2];
+    const int32_t *code, *x_inst, *y_inst;
+    double *x, *y, *xa, *ya, *gx, *aty, *gx0, *aty0, *xsum, *ysum;
+};
+void restart_copy(const RestartArgs &a, hipStream_t s);
 void unscale(const double *xs, const double *f, double *out, int64_t n, hipStream_t s);
+
+// mlp.hip
+void gemm_bf16(int ta, int tb, int64_t M, int64_t N, int64_t K, const uint16_t *a, int64_t lda,
+               const uint16_t *b, int64_t ldb, const float *bias, int relu, float *c32,
+               uint16_t *c16, int64_t ldc, hipStream_t s);
+void to_bf16(const float *in, uint16_t *out, int64_t n, hipStream_t s);
+void mse_grad(const float *out, const float *target, int64_t n, float inv, float *d32, uint16_t *d16,
+              double *part, hipStream_t s);
+void relu_back(const float *dh, const float *z, int64_t n, float *dz32, uint16_t *dz16, hipStream_t s);
+void colsum(const float *d, int64_t rows, int64_t cols, float *db, hipStream_t s);
+void adam(float *p, const float *g, float *m1, float *m2, int64_t n, float lr, float b1, float b2,
+          float eps, float c1, float c2, uint16_t *p16, hipStream_t s);
 void scale_in(const double *xu, const double *f, double *out, int64_t n, hipStream_t s);
 
 }  // namespace pdcs

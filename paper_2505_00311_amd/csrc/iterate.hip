@@ -15,34 +15,42 @@ static unsigned grid_for(int64_t n) {
 // The step decision, one workgroup after the dual pass (a kernel boundary
 // orders the passes' partials before it; a fenced last-workgroup hand-off
 // would write back an XCD's L2 once per workgroup).
-__global__ __launch_bounds__(kBlock) void decide_kernel(DevState *st, const double *px, int64_t ntx,
-                                                        const double *py, int64_t nty) {
-    if (st->halt) {
-        if (threadIdx.x == 0) st->skip_update = 1;
+__global__ __launch_bounds__(kBlock) void decide_kernel(DevState *st, const double *px,
+                                                        const int64_t *tx, int64_t ntx,
+                                                        const double *py, const int64_t *ty,
+                                                        int64_t nty) {
+    const int64_t b = blockIdx.x;
+    DevState *sb = st + b;
+    if (sb->halt) {
+        if (threadIdx.x == 0) sb->skip_update = 1;
         return;
     }
-    decide_body(st, px, ntx, py, nty);
+    const int64_t x0 = tx ? tx[b] : 0, x1 = tx ? tx[b + 1] : ntx;
+    const int64_t y0 = ty ? ty[b] : 0, y1 = ty ? ty[b + 1] : nty;
+    decide_body(sb, px + x0 * kPartials, x1 - x0, py + y0 * kPartials, y1 - y0);
 }
 
-void decide(DevState *st, const double *px, int64_t ntx, const double *py, int64_t nty,
-            hipStream_t s) {
-    hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(kBlock), 0, s, st, px, ntx, py, nty);
+void decide(DevState *st, int64_t B, const double *px, const int64_t *tx, int64_t ntx,
+            const double *py, const int64_t *ty, int64_t nty, hipStream_t s) {
+    hipLaunchKernelGGL(decide_kernel, dim3((unsigned)B), dim3(kBlock), 0, s, st, px, tx, ntx, py,
+                       ty, nty);
     PDCS_HIP(hipGetLastError());
 }
 
 // z^{k+1} = (k+1)/(k+2) ((1+beta) z^ - beta z^k) + z^0/(k+2) (Algorithm 1), the
 // same map on G~x and G~^T y, and sum += eta_used z^{k+1}.
 __global__ __launch_bounds__(kBlock) void halpern_kernel(HalpernArgs a) {
-    const DevState *st = a.st;
-    if (st->skip_update) return;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.n + a.m) return;
+    const DevState *st = a.st + (i < a.n ? inst_of(a.x_inst, i) : inst_of(a.y_inst, i - a.n));
+    if (st->skip_update) return;
     const double ha = st->ha, hb = st->hb, beta = st->beta, w = st->eta_used;
     if (i < a.n) {
         const double xn = ha * ((1.0 + beta) * a.xh[i] - beta * a.x[i]) + hb * a.xa[i];
         a.x[i] = xn;
         a.xsum[i] += w * xn;
         a.aty[i] = ha * ((1.0 + beta) * a.atyh[i] - beta * a.aty[i]) + hb * a.aty0[i];
-    } else if (i < a.n + a.m) {
+    } else {
         const int64_t j = i - a.n;
         const double yn = ha * ((1.0 + beta) * a.yh[j] - beta * a.y[j]) + hb * a.ya[j];
         a.y[j] = yn;
@@ -58,9 +66,14 @@ void halpern(const HalpernArgs &a, hipStream_t s) {
 }
 
 __global__ __launch_bounds__(kBlock) void reduce_kkt_kernel(const double *__restrict__ pr,
-                                                            int64_t ntr,
+                                                            const int64_t *ty, int64_t ntr,
                                                             const double *__restrict__ pc,
-                                                            int64_t ntc, KktRaw *out) {
+                                                            const int64_t *tx, int64_t ntc,
+                                                            KktRaw *out_all) {
+    const int64_t b = blockIdx.x;
+    KktRaw *out = out_all + b;
+    if (ty) pr += ty[b] * kPartials, ntr = ty[b + 1] - ty[b];
+    if (tx) pc += tx[b] * kPartials, ntc = tx[b + 1] - tx[b];
     double s[6] = {0, 0, 0, 0, 0, 0};
     double mx[6] = {0, 0, 0, 0, 0, 0};
     for (int64_t t = threadIdx.x; t < ntr; t += kBlock)
@@ -94,36 +107,35 @@ __global__ __launch_bounds__(kBlock) void reduce_kkt_kernel(const double *__rest
     }
 }
 
-void reduce_kkt(const double *prow, int64_t ntr, const double *pcol, int64_t ntc, KktRaw *out,
-                hipStream_t s) {
-    hipLaunchKernelGGL(reduce_kkt_kernel, dim3(1), dim3(kBlock), 0, s, prow, ntr, pcol, ntc, out);
+void reduce_kkt(int64_t B, const double *prow, const int64_t *ty, int64_t ntr, const double *pcol,
+                const int64_t *tx, int64_t ntc, KktRaw *out, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_kkt_kernel, dim3((unsigned)B), dim3(kBlock), 0, s, prow, ty, ntr, pcol,
+                       tx, ntc, out);
     PDCS_HIP(hipGetLastError());
 }
 
-__global__ void restart_kernel(int64_t n, int64_t m, const double *xc, const double *yc,
-                               const double *gxc, const double *atyc, double *x, double *y,
-                               double *xa, double *ya, double *gx, double *aty, double *gx0,
-                               double *aty0, double *xsum, double *ysum) {
+__global__ void restart_kernel(RestartArgs a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        x[i] = xa[i] = xc[i];
-        aty[i] = aty0[i] = atyc[i];
-        xsum[i] = 0.0;
-    } else if (i < n + m) {
-        const int64_t j = i - n;
-        y[j] = ya[j] = yc[j];
-        gx[j] = gx0[j] = gxc[j];
-        ysum[j] = 0.0;
+    if (i >= a.n + a.m) return;
+    const bool xs = i < a.n;
+    const int64_t j = xs ? i : i - a.n;
+    const int code = a.code ? a.code[xs ? inst_of(a.x_inst, j) : inst_of(a.y_inst, j)] : 1;
+    if (code == 0) return;
+    const int c = code - 1;
+    if (xs) {
+        a.x[j] = a.xa[j] = a.xc[c][j];
+        a.aty[j] = a.aty0[j] = a.atyc[c][j];
+        a.xsum[j] = 0.0;
+    } else {
+        a.y[j] = a.ya[j] = a.yc[c][j];
+        a.gx[j] = a.gx0[j] = a.gxc[c][j];
+        a.ysum[j] = 0.0;
     }
 }
 
-void restart_copy(int64_t n, int64_t m, const double *xc, const double *yc, const double *gxc,
-                  const double *atyc, double *x, double *y, double *xa, double *ya, double *gx,
-                  double *aty, double *gx0, double *aty0, double *xsum, double *ysum,
-                  hipStream_t s) {
-    if (n + m == 0) return;
-    hipLaunchKernelGGL(restart_kernel, dim3(grid_for(n + m)), dim3(kBlock), 0, s, n, m, xc, yc, gxc,
-                       atyc, x, y, xa, ya, gx, aty, gx0, aty0, xsum, ysum);
+void restart_copy(const RestartArgs &a, hipStream_t s) {
+    if (a.n + a.m == 0) return;
+    hipLaunchKernelGGL(restart_kernel, dim3(grid_for(a.n + a.m)), dim3(kBlock), 0, s, a);
     PDCS_HIP(hipGetLastError());
 }
 

@@ -252,6 +252,16 @@ void fill(double *p, int64_t n, double v, hipStream_t s) {
     PDCS_HIP(hipGetLastError());
 }
 
+__global__ void to_float_kernel(const double *in, float *out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
+}
+void to_float(const double *in, float *out, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(to_float_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, in, out, n);
+    PDCS_HIP(hipGetLastError());
+}
+
 __global__ void div_kernel(const double *a, const double *b, double *o, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) o[i] = a[i] / b[i];
@@ -282,14 +292,62 @@ void copy_vec(const double *a, double *out, int64_t n, hipStream_t s) {
     PDCS_HIP(hipGetLastError());
 }
 
-__global__ void scale_inv_sqrt_kernel(const double *w, const double *sumsq, double *v, int64_t n) {
+// v = w / sqrt(sumsq[instance]) (left unchanged where the norm is zero)
+__global__ void scale_inv_sqrt_kernel(const double *w, const double *sumsq, const int32_t *map,
+                                      double *v, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const double lam = sqrt(*sumsq);
-    if (i < n && lam > 0.0) v[i] = w[i] / lam;
+    if (i >= n) return;
+    const double lam = sqrt(sumsq[inst_of(map, i)]);
+    if (lam > 0.0) v[i] = w[i] / lam;
 }
-void scale_by_inv_sqrt(const double *w, const double *sumsq, double *v, int64_t n, hipStream_t s) {
+void scale_by_inv_sqrt(const double *w, const double *sumsq, const int32_t *map, double *v,
+                       int64_t n, hipStream_t s) {
     if (n == 0) return;
-    hipLaunchKernelGGL(scale_inv_sqrt_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, w, sumsq, v, n);
+    hipLaunchKernelGGL(scale_inv_sqrt_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, w, sumsq, map,
+                       v, n);
+    PDCS_HIP(hipGetLastError());
+}
+
+// out[i] = vals[instance of i]
+__global__ void fill_by_inst_kernel(double *out, const int32_t *map, const double *vals, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = vals[inst_of(map, i)];
+}
+void fill_by_inst(double *out, const int32_t *map, const double *vals, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(fill_by_inst_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, out, map, vals, n);
+    PDCS_HIP(hipGetLastError());
+}
+
+// One workgroup per segment [off[b], off[b+1]): sum of squares (MODE 0) or
+// max abs (MODE 1) into out[b], in a fixed order.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void reduce_seg_kernel(const double *__restrict__ a,
+                                                            const int64_t *__restrict__ off,
+                                                            double *__restrict__ out) {
+    const int64_t b = blockIdx.x;
+    double acc[1] = {0.0};
+    for (int64_t i = off[b] + threadIdx.x; i < off[b + 1]; i += kBlock)
+        acc[0] = MODE == 0 ? acc[0] + a[i] * a[i] : fmax(acc[0], fabs(a[i]));
+    if (MODE == 0) {
+        block_sum_all<1>(acc);
+    } else {
+        __shared__ double red[kBlock / kWave];
+        const double w = wave_max(acc[0]);
+        if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = w;
+        __syncthreads();
+        acc[0] = red[0];
+        for (int i = 1; i < kBlock / kWave; ++i) acc[0] = fmax(acc[0], red[i]);
+    }
+    if (threadIdx.x == 0) out[b] = acc[0];
+}
+void reduce_segments(int mode, const double *a, const int64_t *off, int64_t B, double *out,
+                     hipStream_t s) {
+    if (B == 0) return;
+    if (mode == 0)
+        hipLaunchKernelGGL(reduce_seg_kernel<0>, dim3((unsigned)B), dim3(kBlock), 0, s, a, off, out);
+    else
+        hipLaunchKernelGGL(reduce_seg_kernel<1>, dim3((unsigned)B), dim3(kBlock), 0, s, a, off, out);
     PDCS_HIP(hipGetLastError());
 }
 

@@ -250,6 +250,35 @@ def lp_soc_small(seed):
                  name="lp_soc_n1000_m500")
 
 
+def batch_lp_soc(seed, count, n_lo=1000, n_hi=100_000, density=0.005, soc_frac=0.2,
+                 soc_lo=3, soc_hi=50):
+    """A batch of independent planted LP/SOCP instances of uneven size:
+    n ~ U{n_lo..n_hi}, m = n/2, G Bernoulli(density) with N(0,1) entries;
+    soc_frac of the variables in SOC blocks of dims U{soc_lo..soc_hi}, the rest
+    nonnegative; rows half equality, half inequality."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(count):
+        n = int(rng.integers(n_lo, n_hi + 1))
+        m = n // 2
+        rp, ci, v = bernoulli_csr(rng, m, n, density)
+        dims, tot = [], 0
+        while tot < int(soc_frac * n):
+            k = int(rng.integers(soc_lo, soc_hi + 1))
+            k = min(k, n - tot)
+            dims.append(k)
+            tot += k
+        xt = [NONNEG] + [SOC] * len(dims)
+        xd = [n - tot] + dims
+        if xd[0] == 0:
+            xt, xd = xt[1:], xd[1:]
+        me = m // 2
+        rt = [ZERO, NONNEG] if me and m - me else ([ZERO] if me else [NONNEG])
+        rd = [me, m - me] if me and m - me else [m]
+        out.append(plant(rng, n, m, 0, rp, ci, v, xt, xd, rt, rd, name=f"batch{seed}_{b}_n{n}"))
+    return out
+
+
 def large_mixed(seed, n=1_000_000, m=500_000, n_box=None, n_soc_x=None, n_soc_r=None,
                 n_exp_r=None, mean_row_nnz=20):
     """The large single-instance workload (defaults: n=1e6, m=5e5, ~1e7 nnz).

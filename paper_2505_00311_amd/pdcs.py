@@ -39,7 +39,8 @@ class Settings(ctypes.Structure):
                 ("restart_sufficient", _dbl), ("restart_necessary", _dbl),
                 ("restart_artificial", _dbl), ("max_attempts", _i32), ("out_on_device", _i32),
                 ("step_mode", _i32), ("step_fixed", _dbl), ("power_iters", _i32),
-                ("use_graph", _i32), ("time_kernels", _i32)]
+                ("use_graph", _i32), ("time_kernels", _i32), ("precision", _i32),
+                ("polish_tol", _dbl), ("polish_stall", _i32), ("autotune", _i32)]
 
 KERNELS = ("primal", "spmv_g", "dual", "decide", "spmv_gt", "halpern")
 
@@ -48,7 +49,8 @@ class Info(ctypes.Structure):
     _fields_ = [("status", _i32), ("iterations", _i64), ("attempts", _i64), ("restarts", _i64),
                 ("spmv", _i64), ("pobj", _dbl), ("dobj", _dbl), ("err_p", _dbl), ("err_d", _dbl),
                 ("err_gap", _dbl), ("omega", _dbl), ("eta", _dbl), ("setup_s", _dbl),
-                ("solve_s", _dbl), ("kernel_ms", _dbl * 6), ("kernel_launches", _i64 * 6)]
+                ("solve_s", _dbl), ("kernel_ms", _dbl * 6), ("kernel_launches", _i64 * 6),
+                ("polish_iter", _i64)]
 
 
 class Trace(ctypes.Structure):
@@ -64,8 +66,11 @@ class PdcsError(RuntimeError):
 _lib = None
 
 SYMBOLS = ["pdcs_settings_default", "pdcs_problem_create", "pdcs_problem_create_device",
-           "pdcs_problem_destroy", "pdcs_solve", "pdcs_scaling", "pdcs_spmv", "pdcs_kkt",
-           "pdcs_project", "pdcs_status_string", "pdcs_last_error"]
+           "pdcs_problem_destroy", "pdcs_solve", "pdcs_scaling", "pdcs_spmv", "pdcs_spmv32",
+           "pdcs_kkt", "pdcs_project", "pdcs_batch_create", "pdcs_batch_solve", "pdcs_batch_size",
+           "pdcs_batch_destroy", "pdcs_mlp_create", "pdcs_mlp_num_params", "pdcs_mlp_forward",
+           "pdcs_mlp_gradient", "pdcs_mlp_train_step", "pdcs_mlp_get_params", "pdcs_mlp_destroy",
+           "pdcs_gemm_bf16", "pdcs_status_string", "pdcs_last_error"]
 
 
 def load():
@@ -92,8 +97,27 @@ def load():
                              ctypes.POINTER(Info), ctypes.POINTER(Trace)]
     L.pdcs_scaling.argtypes = [_vp, ctypes.POINTER(Settings), _vp, _vp]
     L.pdcs_spmv.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
+    L.pdcs_spmv32.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
     L.pdcs_kkt.argtypes = [_vp, _vp, _vp, _vp]
     L.pdcs_project.argtypes = [_i64, _pi32, _pi64, ctypes.c_int, _vp, _vp, _vp]
+    L.pdcs_batch_create.argtypes = [ctypes.POINTER(ProblemDesc), _i64, _vp, ctypes.POINTER(_vp)]
+    L.pdcs_batch_solve.argtypes = [_vp, ctypes.POINTER(Settings), ctypes.POINTER(_vp),
+                                   ctypes.POINTER(_vp), ctypes.POINTER(Info)]
+    L.pdcs_batch_size.argtypes = [_vp]
+    L.pdcs_batch_size.restype = _i64
+    L.pdcs_batch_destroy.argtypes = [_vp]
+    L.pdcs_batch_destroy.restype = None
+    L.pdcs_mlp_create.argtypes = [_i64, _i64, _i64, _i64, _vp, _vp, ctypes.POINTER(_vp)]
+    L.pdcs_mlp_num_params.argtypes = [_vp]
+    L.pdcs_mlp_num_params.restype = _i64
+    L.pdcs_mlp_forward.argtypes = [_vp, _vp, _i64, _vp]
+    L.pdcs_mlp_gradient.argtypes = [_vp, _vp, _vp, _i64, _vp, ctypes.POINTER(_dbl)]
+    L.pdcs_mlp_train_step.argtypes = [_vp, _vp, _vp, _i64, ctypes.c_float, ctypes.POINTER(_dbl)]
+    L.pdcs_mlp_get_params.argtypes = [_vp, _vp]
+    L.pdcs_mlp_destroy.argtypes = [_vp]
+    L.pdcs_mlp_destroy.restype = None
+    L.pdcs_gemm_bf16.argtypes = [ctypes.c_int, ctypes.c_int, _i64, _i64, _i64, _vp, _i64, _vp, _i64,
+                                 _vp, ctypes.c_int, _vp, _vp, _i64, _vp]
     L.pdcs_status_string.argtypes = [ctypes.c_int]
     L.pdcs_status_string.restype = ctypes.c_char_p
     L.pdcs_last_error.argtypes = []
@@ -129,6 +153,78 @@ def _dptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _desc(inst, host, keep, from_device=False):
+    """pdcs_problem_desc of an Instance; `host` pins the arrays it makes."""
+    n_box = int(inst.n_box)
+    rp, col, val = host(inst.row_ptr, np.int64), host(inst.col, np.int32), host(inst.val, np.float64)
+    c, h = host(inst.c, np.float64), host(inst.h, np.float64)
+    l = host(inst.l if n_box else np.zeros(1), np.float64)
+    u = host(inst.u if n_box else np.zeros(1), np.float64)
+    if from_device:
+        import torch
+        dev = [torch.from_numpy(a).cuda() for a in (rp, col, val, c, h, l, u)]
+        torch.cuda.synchronize()
+        keep += dev
+        ptrs = [_dptr(t) for t in dev]
+    else:
+        ptrs = [ctypes.c_void_p(a.ctypes.data) for a in (rp, col, val, c, h, l, u)]
+    xt, xd = host(inst.xcone_type, np.int32), host(inst.xcone_dim, np.int64)
+    rt, rd = host(inst.rcone_type, np.int32), host(inst.rcone_dim, np.int64)
+    return ProblemDesc(int(inst.n), int(inst.m), int(val.size), n_box, *ptrs,
+                       int(xt.size), xt.ctypes.data_as(_pi32), xd.ctypes.data_as(_pi64),
+                       int(rt.size), rt.ctypes.data_as(_pi32), rd.ctypes.data_as(_pi64))
+
+
+class Batch:
+    """A batch handle (pdcs_batch_create): independent instances solved together."""
+
+    def __init__(self, insts, stream=None):
+        L = load()
+        keep = []
+
+        def host(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            keep.append(a)
+            return a
+
+        self.sizes = [(int(i.n), int(i.m)) for i in insts]
+        self.stream = _stream(stream)
+        descs = (ProblemDesc * len(insts))(*[_desc(i, host, keep) for i in insts])
+        handle = ctypes.c_void_p()
+        _check(L.pdcs_batch_create(descs, len(insts), self.stream, ctypes.byref(handle)))
+        self.handle = handle
+
+    def solve(self, settings: Settings | None = None):
+        """pdcs_batch_solve -> list of dicts (info fields plus x, y)."""
+        L = load()
+        s = settings or settings_default()
+        s.out_on_device = 0
+        B = len(self.sizes)
+        xs = [np.empty(n) for n, _ in self.sizes]
+        ys = [np.empty(m) for _, m in self.sizes]
+        px = (_vp * B)(*[ctypes.c_void_p(a.ctypes.data) for a in xs])
+        py = (_vp * B)(*[ctypes.c_void_p(a.ctypes.data) for a in ys])
+        infos = (Info * B)()
+        _check(L.pdcs_batch_solve(self.handle, ctypes.byref(s), px, py, infos))
+        out = []
+        for b in range(B):
+            d = {k: getattr(infos[b], k) for k, _ in Info._fields_}
+            d["x"], d["y"] = xs[b], ys[b]
+            out.append(d)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().pdcs_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Problem:
     """A problem handle (pdcs_problem_create / pdcs_problem_create_device)."""
 
@@ -143,23 +239,7 @@ class Problem:
             self._keep.append(a)
             return a
 
-        rp, col, val = host(inst.row_ptr, np.int64), host(inst.col, np.int32), host(inst.val, np.float64)
-        c, h = host(inst.c, np.float64), host(inst.h, np.float64)
-        l = host(inst.l if self.n_box else np.zeros(1), np.float64)
-        u = host(inst.u if self.n_box else np.zeros(1), np.float64)
-        if from_device:
-            import torch
-            dev = [torch.from_numpy(a).cuda() for a in (rp, col, val, c, h, l, u)]
-            torch.cuda.synchronize()
-            self._keep += dev
-            ptrs = [_dptr(t) for t in dev]
-        else:
-            ptrs = [ctypes.c_void_p(a.ctypes.data) for a in (rp, col, val, c, h, l, u)]
-        xt, xd = host(inst.xcone_type, np.int32), host(inst.xcone_dim, np.int64)
-        rt, rd = host(inst.rcone_type, np.int32), host(inst.rcone_dim, np.int64)
-        desc = ProblemDesc(self.n, self.m, int(val.size), self.n_box, *ptrs,
-                           int(xt.size), xt.ctypes.data_as(_pi32), xd.ctypes.data_as(_pi64),
-                           int(rt.size), rt.ctypes.data_as(_pi32), rd.ctypes.data_as(_pi64))
+        desc = _desc(inst, host, self._keep, from_device)
         handle = ctypes.c_void_p()
         fn = L.pdcs_problem_create_device if from_device else L.pdcs_problem_create
         _check(fn(ctypes.byref(desc), self.stream, ctypes.byref(handle)))
@@ -233,10 +313,11 @@ class Problem:
                                    ctypes.c_void_p(e.ctypes.data), ctypes.c_void_p(f.ctypes.data)))
         return e, f
 
-    def spmv(self, x_dev, y_dev, transpose=False, stream=None):
-        """pdcs_spmv on device tensors: y = G x (or G^T x)."""
-        _check(load().pdcs_spmv(self.handle, 1 if transpose else 0, _dptr(x_dev), _dptr(y_dev),
-                                _stream(stream) if stream is not None else self.stream))
+    def spmv(self, x_dev, y_dev, transpose=False, stream=None, fp32=False):
+        """pdcs_spmv (pdcs_spmv32 with fp32) on device tensors: y = G x (or G^T x)."""
+        fn = load().pdcs_spmv32 if fp32 else load().pdcs_spmv
+        _check(fn(self.handle, 1 if transpose else 0, _dptr(x_dev), _dptr(y_dev),
+                  _stream(stream) if stream is not None else self.stream))
 
     def kkt(self, x_dev, y_dev):
         """pdcs_kkt at unscaled device tensors -> dict."""
@@ -253,3 +334,64 @@ def project(types, dims, v_dev, d_dev=None, dual=False, stream=None):
     _check(load().pdcs_project(int(t.size), t.ctypes.data_as(_pi32), k.ctypes.data_as(_pi64),
                                1 if dual else 0, None if d_dev is None else _dptr(d_dev),
                                _dptr(v_dev), _stream(stream)))
+
+
+class MLP:
+    """The warm-start network (pdcs_mlp_*): device-resident parameters, BF16
+    matrix-core GEMMs with FP32 accumulation, Adam training."""
+
+    def __init__(self, n_in, hidden, n_out, params, max_batch, stream=None):
+        L = load()
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self.n_in, self.hidden, self.n_out, self.max_batch = n_in, hidden, n_out, max_batch
+        handle = ctypes.c_void_p()
+        _check(L.pdcs_mlp_create(n_in, hidden, n_out, max_batch, ctypes.c_void_p(p.ctypes.data),
+                                 _stream(stream), ctypes.byref(handle)))
+        self.handle = handle
+        self.num_params = int(L.pdcs_mlp_num_params(handle))
+
+    def forward(self, theta_dev, out_dev):
+        _check(load().pdcs_mlp_forward(self.handle, _dptr(theta_dev), int(theta_dev.shape[0]), _dptr(out_dev)))
+
+    def gradient(self, theta_dev, target_dev):
+        g = np.empty(self.num_params, np.float32)
+        loss = ctypes.c_double()
+        _check(load().pdcs_mlp_gradient(self.handle, _dptr(theta_dev), _dptr(target_dev),
+                                        int(theta_dev.shape[0]), ctypes.c_void_p(g.ctypes.data),
+                                        ctypes.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, theta_dev, target_dev, lr):
+        loss = ctypes.c_double()
+        _check(load().pdcs_mlp_train_step(self.handle, _dptr(theta_dev), _dptr(target_dev),
+                                          int(theta_dev.shape[0]), float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def params(self):
+        p = np.empty(self.num_params, np.float32)
+        _check(load().pdcs_mlp_get_params(self.handle, ctypes.c_void_p(p.ctypes.data)))
+        return p
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().pdcs_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gemm_bf16(a_dev, b_dev, M, N, K, ta=0, tb=0, lda=None, ldb=None, bias_dev=None, relu=False,
+              c32_dev=None, c16_dev=None, ldc=None, stream=None):
+    """pdcs_gemm_bf16 on device tensors (a_dev, b_dev, c16_dev: int16/uint16 bit patterns)."""
+    lda = lda if lda is not None else (M if ta else K)
+    ldb = ldb if ldb is not None else (K if tb else N)
+    ldc = ldc if ldc is not None else N
+    nul = ctypes.c_void_p(None)
+    _check(load().pdcs_gemm_bf16(ta, tb, M, N, K, _dptr(a_dev), lda, _dptr(b_dev), ldb,
+                                 _dptr(bias_dev) if bias_dev is not None else nul, 1 if relu else 0,
+                                 _dptr(c32_dev) if c32_dev is not None else nul,
+                                 _dptr(c16_dev) if c16_dev is not None else nul, ldc, _stream(stream)))

@@ -17,3 +17,14 @@ def orc():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+@pytest.fixture(scope="session")
+def pd():
+    """The HIP library through its Python binding (GPU tests only)."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_00311_amd import pdcs
+    pdcs.load()
+    return pdcs

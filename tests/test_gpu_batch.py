@@ -1,0 +1,65 @@
+"""GPU tests of batched solves: independent instances of uneven size and cone
+mix laid out block-diagonally, every kernel covering all of them, each
+instance checked against the FP64 oracle on its own."""
+import numpy as np
+import pytest
+
+from paper_2505_00311_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+
+def mix():
+    return [I.small_mixed(1), I.lp_soc_small(20250501), I.small_mixed(4), I.ball_socp(2),
+            I.tiny_lp(3), I.box_only(), I.large_mixed(7, n=20000, m=10000), I.small_mixed(2)]
+
+
+@pytest.mark.parametrize("autotune", [0, 1])
+def test_batch_solves_each_instance_to_tolerance(pd, orc, autotune):
+    insts = mix()
+    batch = pd.Batch(insts)
+    res = batch.solve(pd.settings_default(autotune=autotune))
+    for inst, r in zip(insts, res):
+        assert r["status"] == 0, (inst.name, r["status"])
+        k = orc.kkt(inst, r["x"], r["y"])
+        assert max(k["err_p"], k["err_d"], k["err_gap"]) <= 1.01e-6, (inst.name, k)
+        single = pd.Problem(inst).solve(pd.settings_default())
+        assert r["pobj"] == pytest.approx(single["pobj"], rel=2e-6, abs=2e-6), inst.name
+        if inst.opt is not None:
+            assert r["pobj"] == pytest.approx(inst.opt, rel=1e-5, abs=1e-5), inst.name
+    batch.close()
+
+
+def test_batch_fixed_step_iterates_match_oracle(pd, orc):
+    """Fixed step (a rounding-stable map): after 200 iterations each instance's
+    iterate equals the oracle's single solve of it within 1e-10 relative."""
+    insts = [I.small_mixed(1), I.lp_soc_small(20250501), I.ball_socp(2), I.small_mixed(5),
+             I.large_mixed(7, n=20000, m=10000)]
+    kw = dict(max_iter=200, step_mode=1)
+    batch = pd.Batch(insts)
+    res = batch.solve(pd.settings_default(**kw))
+    for inst, r in zip(insts, res):
+        o = orc.solve(inst, orc.default_settings(**kw))
+        assert r["iterations"] == o["iterations"] and r["status"] == o["status"], inst.name
+        z = np.concatenate([r["x"], r["y"]])
+        zo = np.concatenate([o["x"], o["y"]])
+        err = np.linalg.norm(z - zo) / max(1.0, np.linalg.norm(zo))
+        bound = 1e-8 if inst.n >= 20000 else 1e-10
+        assert err <= bound, (inst.name, err)
+    batch.close()
+
+
+def test_batch_of_one_equals_single_problem(pd):
+    inst = I.small_mixed(3)
+    a = pd.Problem(inst).solve(pd.settings_default(max_iter=300))
+    b = pd.Batch([inst]).solve(pd.settings_default(max_iter=300))[0]
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["y"], b["y"])
+
+
+def test_batch_mixed_precision(pd, orc):
+    insts = [I.small_mixed(1), I.lp_soc_small(20250501), I.large_mixed(7, n=20000, m=10000)]
+    res = pd.Batch(insts).solve(pd.settings_default(precision=1))
+    for inst, r in zip(insts, res):
+        assert r["status"] == 0, inst.name
+        k = orc.kkt(inst, r["x"], r["y"])
+        assert max(k["err_p"], k["err_d"], k["err_gap"]) <= 1.01e-6, (inst.name, k)

@@ -1,0 +1,105 @@
+"""GPU tests of the warm-start network: the BF16 matrix-core GEMM against the
+oracle's FP64 product within the FP32-accumulation bound, the network's
+gradient against the oracle's backpropagation, and training."""
+import numpy as np
+import pytest
+
+from oracle import mlp as OM
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def bits_dev(x):
+    """BF16 values (float64 array) -> device int16 tensor of their bit patterns."""
+    u = (np.ascontiguousarray(np.asarray(x, np.float32)).view(np.uint32) >> 16).astype(np.uint16)
+    return torch.from_numpy(u.view(np.int16).copy()).cuda()
+
+
+def from_bits(t):
+    u = t.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    return u.view(np.float32).astype(np.float64)
+
+
+SHAPES = [(77, 131, 48), (64, 1000, 512), (37, 2051, 80), (128, 64, 16), (1, 5, 3)]
+
+
+@pytest.mark.parametrize("ta", [0, 1])
+@pytest.mark.parametrize("tb", [0, 1])
+@pytest.mark.parametrize("shape", SHAPES, ids=[f"{m}x{n}x{k}" for m, n, k in SHAPES])
+def test_gemm_matches_oracle(pd, ta, tb, shape):
+    M, N, K = shape
+    rng = np.random.default_rng(M * 7 + N * 3 + K + 10 * ta + 20 * tb)
+    A = OM.bf16(rng.standard_normal((M, K)))
+    B = OM.bf16(rng.standard_normal((K, N)))
+    a_st = A.T.copy() if ta else A        # stored layout the kernel reads
+    b_st = B.T.copy() if tb else B
+    bias = rng.standard_normal(N).astype(np.float32)
+    relu = (M + N) % 2 == 0
+    c32 = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    c16 = torch.empty((M, N), dtype=torch.int16, device="cuda")
+    pd.gemm_bf16(bits_dev(a_st), bits_dev(b_st), M, N, K, ta=ta, tb=tb,
+                 bias_dev=torch.from_numpy(bias).cuda(), relu=relu, c32_dev=c32, c16_dev=c16)
+    torch.cuda.synchronize()
+    ref, bound = OM.gemm(a_st, b_st, ta, tb, bias=bias.astype(np.float64), relu=relu)
+    got = c32.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - ref) <= bound + 1e-30), np.abs(got - ref).max()
+    assert np.array_equal(from_bits(c16), OM.bf16(got))
+
+
+def test_network_gradient_matches_oracle(pd):
+    """The GPU gradient against the oracle's backpropagation with the same BF16
+    rounding points.  Both sides may round an intermediate to neighbouring BF16
+    values where FP32 and FP64 sums straddle a rounding boundary, so each
+    parameter block is held to one BF16 unit (2^-8) in relative 2-norm."""
+    rng = np.random.default_rng(3)
+    n_in, hid, n_out, B = 64, 128, 300, 32
+    npar = hid * n_in + hid + hid * hid + hid + n_out * hid + n_out
+    p = np.concatenate([rng.standard_normal(hid * n_in) * np.sqrt(2 / n_in), np.zeros(hid) + 0.1,
+                        rng.standard_normal(hid * hid) * np.sqrt(2 / hid), np.zeros(hid) + 0.1,
+                        rng.standard_normal(n_out * hid) * np.sqrt(1 / hid), np.zeros(n_out)])
+    assert p.size == npar
+    theta = rng.standard_normal((B, n_in))
+    target = rng.standard_normal((B, n_out))
+    net = pd.MLP(n_in, hid, n_out, p.astype(np.float32), max_batch=B)
+    g, loss = net.gradient(torch.from_numpy(theta.astype(np.float32)).cuda(),
+                           torch.from_numpy(target.astype(np.float32)).cuda())
+    p32 = p.astype(np.float32).astype(np.float64)
+    lo, go = OM.loss_and_grad(p32, theta.astype(np.float32).astype(np.float64),
+                              target.astype(np.float32).astype(np.float64), n_in, hid, n_out)
+    assert loss == pytest.approx(lo, rel=1e-5)
+    sizes = [hid * n_in, hid, hid * hid, hid, n_out * hid, n_out]
+    o = 0
+    for name, s in zip(["W1", "b1", "W2", "b2", "W3", "b3"], sizes):
+        rel = np.linalg.norm(g[o:o + s] - go[o:o + s]) / np.linalg.norm(go[o:o + s])
+        assert rel <= 2.0 ** -8, (name, rel)
+        o += s
+    net.close()
+
+
+def test_training_fits_a_teacher(pd):
+    """Adam steps on the GPU fit the outputs of a random teacher network of the
+    same shape: the loss falls below a quarter of its starting value."""
+    rng = np.random.default_rng(4)
+    n_in, hid, n_out, B = 16, 64, 40, 128
+    def init(scale):
+        return np.concatenate([rng.standard_normal(hid * n_in) * np.sqrt(2 / n_in), np.zeros(hid),
+                               rng.standard_normal(hid * hid) * np.sqrt(2 / hid), np.zeros(hid),
+                               rng.standard_normal(n_out * hid) * scale * np.sqrt(1 / hid),
+                               np.zeros(n_out)])
+    teacher = init(1.0)
+    theta = rng.standard_normal((B, n_in))
+    target = OM.forward(teacher, theta, n_in, hid, n_out, quantize=False)["o"]
+    net = pd.MLP(n_in, hid, n_out, init(0.1).astype(np.float32), max_batch=B)
+    th = torch.from_numpy(theta.astype(np.float32)).cuda()
+    tg = torch.from_numpy(target.astype(np.float32)).cuda()
+    first = net.train_step(th, tg, 3e-3)
+    for _ in range(400):
+        last = net.train_step(th, tg, 3e-3)
+    assert last < 0.25 * first, (first, last)
+    out = torch.empty((B, n_out), dtype=torch.float32, device="cuda")
+    net.forward(th, out)
+    torch.cuda.synchronize()
+    ref = OM.forward(net.params(), theta.astype(np.float32), n_in, hid, n_out, quantize=True)["o"]
+    assert np.abs(out.cpu().numpy() - ref).max() <= 1e-3 * max(1.0, np.abs(ref).max())
+    net.close()

@@ -15,15 +15,6 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.fixture(scope="module")
-def pd():
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    from paper_2505_00311_amd import pdcs
-    pdcs.load()
-    return pdcs
-
-
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
