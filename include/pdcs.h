@@ -264,10 +264,13 @@ pdcs_status pdcs_project(int64_t nblocks, const int32_t *types, const int64_t *d
 typedef struct pdcs_batch pdcs_batch;
 pdcs_status pdcs_batch_create(const pdcs_problem_desc *descs, int64_t count, void *hip_stream,
                               pdcs_batch **out);
-/* Cold-start solve of every instance: x_out[b] (n_b) and y_out[b] (m_b) as in
+/* Solve of every instance: x0, y0 (arrays of count host pointers, or NULL;
+ * a NULL entry is a cold start) and omega0 (count values, <= 0 for the
+ * default, or NULL) as in pdcs_solve; x_out[b] (n_b) and y_out[b] (m_b) as in
  * pdcs_solve (host memory, or device memory with settings.out_on_device);
  * infos: array of count results, the times are the batch's. */
-pdcs_status pdcs_batch_solve(pdcs_batch *b, const pdcs_settings *settings, double *const *x_out,
+pdcs_status pdcs_batch_solve(pdcs_batch *b, const pdcs_settings *settings, const double *const *x0,
+                             const double *const *y0, const double *omega0, double *const *x_out,
                              double *const *y_out, pdcs_info *infos);
 int64_t pdcs_batch_size(const pdcs_batch *b);
 void pdcs_batch_destroy(pdcs_batch *b);

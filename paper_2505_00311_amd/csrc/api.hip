@@ -1314,11 +1314,12 @@ pdcs_status pdcs_batch_create(const pdcs_problem_desc *descs, int64_t count, voi
     });
 }
 
-pdcs_status pdcs_batch_solve(pdcs_batch *b, const pdcs_settings *settings, double *const *x_out,
+pdcs_status pdcs_batch_solve(pdcs_batch *b, const pdcs_settings *settings, const double *const *x0,
+                             const double *const *y0, const double *omega0, double *const *x_out,
                              double *const *y_out, pdcs_info *infos) {
     return guarded([&] {
         if (!b || !b->p) fail(PDCS_ERR_INVALID_ARG, "batch is NULL");
-        solve_batch(b->p, settings, nullptr, nullptr, nullptr, x_out, y_out, infos, nullptr);
+        solve_batch(b->p, settings, x0, y0, omega0, x_out, y_out, infos, nullptr);
     });
 }
 

@@ -364,3 +364,75 @@ def box_only(c=(1.0, -2.0, 0.5)):
                     xcone_type=np.zeros(0, np.int32), xcone_dim=np.zeros(0, np.int64),
                     rcone_type=np.zeros(0, np.int32), rcone_dim=np.zeros(0, np.int64),
                     x_star=x, y_star=np.zeros(0), opt=float(c @ x), name="box_only")
+
+
+# ------------------------------------------------------ parametric family
+class PortfolioFamily:
+    """A parametric SOC portfolio family with a k-factor risk model.
+
+    Variables: asset weights w (n_assets, nonnegative) and factor exposures f
+    (k, free); x = (w, f).  Rows, in order:
+      f - F^T w = 0                                  (k rows, ZERO),
+      1^T w = b(theta)                               (1 row, ZERO),
+      (gamma(theta), L^T f, delta o w) in SOC(1 + k + n_assets).
+    Objective: maximise expected return, c = -(mu0 + P_c theta) on w, 0 on f.
+    b(theta) = 1 + p_b . theta and gamma(theta) = gamma0 (1 + p_g . theta) with
+    small p_b, p_g; gamma0 is 1.5 times the risk of equal weights, so every
+    theta of moderate size keeps the family feasible.  The structure (F with
+    `density` nonzeros per column pattern, L, delta, mu0, P_c) is drawn once
+    from `seed`; theta ~ N(0, I_dim_theta)."""
+
+    def __init__(self, seed, n_assets=20000, k=50, density=0.2, dim_theta=64):
+        rng = np.random.default_rng(seed)
+        self.n_assets, self.k, self.dim_theta = n_assets, k, dim_theta
+        self.n = n_assets + k
+        self.m = k + 1 + 1 + k + n_assets
+        mask = rng.random((n_assets, k)) < density
+        fv = rng.standard_normal((n_assets, k)) * mask
+        self.F = fv                                        # dense n_assets x k (for building)
+        Lc = np.tril(rng.standard_normal((k, k)) * 0.05) + np.diag(rng.uniform(0.1, 0.3, k))
+        self.L = Lc
+        self.delta = rng.uniform(0.05, 0.2, n_assets)
+        self.mu0 = rng.normal(0.05, 0.02, n_assets)
+        self.Pc = rng.standard_normal((n_assets, dim_theta)) * 0.005
+        self.pb = rng.standard_normal(dim_theta) * 0.01
+        self.pg = rng.standard_normal(dim_theta) * 0.01
+        w_eq = np.full(n_assets, 1.0 / n_assets)
+        risk_eq = np.sqrt(np.sum((Lc.T @ (fv.T @ w_eq)) ** 2) + np.sum((self.delta * w_eq) ** 2))
+        self.gamma0 = 1.5 * risk_eq
+        # G is the same for every theta
+        rows, cols, vals = [], [], []
+        Fi, Fj = np.nonzero(mask)                          # F[i, j]: asset i, factor j
+        # rows 0..k-1: f_j - sum_i F[i, j] w_i
+        rows.append(Fj), cols.append(Fi), vals.append(-fv[Fi, Fj])
+        rows.append(np.arange(k)), cols.append(n_assets + np.arange(k)), vals.append(np.ones(k))
+        # row k: budget
+        rows.append(np.full(n_assets, k)), cols.append(np.arange(n_assets)), vals.append(np.ones(n_assets))
+        # row k+1: SOC head t = gamma (G row empty, h = -gamma)
+        # rows k+2 .. k+1+k: (L^T f)_j = sum_i L[i, j] f_i
+        Li, Lj = np.nonzero(Lc)
+        rows.append(k + 2 + Lj), cols.append(n_assets + Li), vals.append(Lc[Li, Lj])
+        # rows 2k+2 ..: delta o w
+        rows.append(2 * k + 2 + np.arange(n_assets)), cols.append(np.arange(n_assets)), vals.append(self.delta)
+        r = np.concatenate(rows)
+        cidx = np.concatenate(cols)
+        v = np.concatenate(vals)
+        self.row_ptr, self.col, self.val = csr_from_coo(self.m, self.n, r, cidx, v)
+
+    def instance(self, theta):
+        theta = np.asarray(theta, dtype=np.float64)
+        c = np.zeros(self.n)
+        c[:self.n_assets] = -(self.mu0 + self.Pc @ theta)
+        h = np.zeros(self.m)
+        h[self.k] = 1.0 + self.pb @ theta
+        h[self.k + 1] = -self.gamma0 * (1.0 + self.pg @ theta)
+        return Instance(n=self.n, m=self.m, n_box=0, row_ptr=self.row_ptr, col=self.col,
+                        val=self.val, c=c, h=h, l=np.zeros(0), u=np.zeros(0),
+                        xcone_type=np.array([NONNEG, FREE], np.int32),
+                        xcone_dim=np.array([self.n_assets, self.k], np.int64),
+                        rcone_type=np.array([ZERO, SOC], np.int32),
+                        rcone_dim=np.array([self.k + 1, 1 + self.k + self.n_assets], np.int64),
+                        name=f"portfolio_n{self.n_assets}")
+
+    def thetas(self, seed, count):
+        return np.random.default_rng(seed).standard_normal((count, self.dim_theta))

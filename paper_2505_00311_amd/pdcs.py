@@ -101,8 +101,8 @@ def load():
     L.pdcs_kkt.argtypes = [_vp, _vp, _vp, _vp]
     L.pdcs_project.argtypes = [_i64, _pi32, _pi64, ctypes.c_int, _vp, _vp, _vp]
     L.pdcs_batch_create.argtypes = [ctypes.POINTER(ProblemDesc), _i64, _vp, ctypes.POINTER(_vp)]
-    L.pdcs_batch_solve.argtypes = [_vp, ctypes.POINTER(Settings), ctypes.POINTER(_vp),
-                                   ctypes.POINTER(_vp), ctypes.POINTER(Info)]
+    L.pdcs_batch_solve.argtypes = [_vp, ctypes.POINTER(Settings), _vp, _vp, _vp,
+                                   ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(Info)]
     L.pdcs_batch_size.argtypes = [_vp]
     L.pdcs_batch_size.restype = _i64
     L.pdcs_batch_destroy.argtypes = [_vp]
@@ -194,8 +194,10 @@ class Batch:
         _check(L.pdcs_batch_create(descs, len(insts), self.stream, ctypes.byref(handle)))
         self.handle = handle
 
-    def solve(self, settings: Settings | None = None):
-        """pdcs_batch_solve -> list of dicts (info fields plus x, y)."""
+    def solve(self, settings: Settings | None = None, x0=None, y0=None, omega0=None):
+        """pdcs_batch_solve -> list of dicts (info fields plus x, y).  x0, y0:
+        lists of per-instance starting points (entries may be None); omega0:
+        per-instance primal weights (<= 0: default)."""
         L = load()
         s = settings or settings_default()
         s.out_on_device = 0
@@ -204,8 +206,26 @@ class Batch:
         ys = [np.empty(m) for _, m in self.sizes]
         px = (_vp * B)(*[ctypes.c_void_p(a.ctypes.data) for a in xs])
         py = (_vp * B)(*[ctypes.c_void_p(a.ctypes.data) for a in ys])
+        keep = []
+
+        def ptrs(vs):
+            if vs is None:
+                return None
+            arr = (_vp * B)()
+            for b, v in enumerate(vs):
+                if v is not None:
+                    a = np.ascontiguousarray(v, dtype=np.float64)
+                    keep.append(a)
+                    arr[b] = a.ctypes.data
+            keep.append(arr)
+            return ctypes.cast(arr, _vp)
+
+        om = None
+        if omega0 is not None:
+            om = np.ascontiguousarray(omega0, dtype=np.float64)
         infos = (Info * B)()
-        _check(L.pdcs_batch_solve(self.handle, ctypes.byref(s), px, py, infos))
+        _check(L.pdcs_batch_solve(self.handle, ctypes.byref(s), ptrs(x0), ptrs(y0),
+                                  None if om is None else ctypes.c_void_p(om.ctypes.data), px, py, infos))
         out = []
         for b in range(B):
             d = {k: getattr(infos[b], k) for k, _ in Info._fields_}

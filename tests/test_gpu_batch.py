@@ -14,6 +14,15 @@ def mix():
             I.tiny_lp(3), I.box_only(), I.large_mixed(7, n=20000, m=10000), I.small_mixed(2)]
 
 
+# Two answers that each meet 1e-6 relative KKT need not share their objective to
+# 1e-6: pobj - opt = <y*, Gx - h> + <lambda*, x> (from c = G^T y* + lambda*,
+# h = G x* - s* and complementarity), so the primal and dual residuals allowed
+# by err_p, err_d (relative to 1 + ||h||_inf, 1 + ||c||_inf, with rows scaled up
+# to 1e3 here) move it by up to ||y*||_1 res_p + ||x*||_1 res_d on top of the gap.
+# On these instances that is below 3e-5 relative.
+OBJ_REL = 3e-5
+
+
 @pytest.mark.parametrize("autotune", [0, 1])
 def test_batch_solves_each_instance_to_tolerance(pd, orc, autotune):
     insts = mix()
@@ -24,9 +33,9 @@ def test_batch_solves_each_instance_to_tolerance(pd, orc, autotune):
         k = orc.kkt(inst, r["x"], r["y"])
         assert max(k["err_p"], k["err_d"], k["err_gap"]) <= 1.01e-6, (inst.name, k)
         single = pd.Problem(inst).solve(pd.settings_default())
-        assert r["pobj"] == pytest.approx(single["pobj"], rel=2e-6, abs=2e-6), inst.name
+        assert r["pobj"] == pytest.approx(single["pobj"], rel=OBJ_REL, abs=OBJ_REL), inst.name
         if inst.opt is not None:
-            assert r["pobj"] == pytest.approx(inst.opt, rel=1e-5, abs=1e-5), inst.name
+            assert r["pobj"] == pytest.approx(inst.opt, rel=OBJ_REL, abs=OBJ_REL), inst.name
     batch.close()
 
 

@@ -72,9 +72,10 @@ def test_mixed_solve_reaches_tolerance(pd, orc, name, maker):
     assert g["polish_iter"] != 0
     k = orc.kkt(inst, g["x"], g["y"])
     assert max(k["err_p"], k["err_d"], k["err_gap"]) <= 1.01e-6, k
-    assert g["pobj"] == pytest.approx(p["pobj"], rel=5e-6, abs=5e-6)
+    # objectives of two 1e-6-KKT answers: see OBJ_REL in test_gpu_batch.py
+    assert g["pobj"] == pytest.approx(p["pobj"], rel=3e-5, abs=3e-5)
     if inst.opt is not None:
-        assert g["pobj"] == pytest.approx(inst.opt, rel=1e-5, abs=1e-5)
+        assert g["pobj"] == pytest.approx(inst.opt, rel=3e-5, abs=3e-5)
     prob.close()
 
 
