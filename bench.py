@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 METRIC = "time-to-1e-6 rel. KKT & PDHG iter/s (plain FP64 vs chosen form), HBM GB/s"
 SEED_LARGE = 20250502
 SEED_BATCH = 20250504
+SEED_FAMILY = 20250505
 HBM_PEAK_GBS = 8000.0
 CHECK = 64
 
@@ -123,6 +124,54 @@ def batched_form(pdcs, instances, torch, count):
             "iterations_max": max(r["iterations"] for r in rb)}
 
 
+def warm_start_form(pdcs, instances, torch, n_assets, n_train, n_test):
+    """Learned warm start on the parametric SOC portfolio family (k = 50 factors,
+    theta in R^64): batched solves of n_train parameters give the targets, the
+    network 64 -> 512 -> 512 -> (n + m + 1) is trained on the GPU, and n_test
+    held-out parameters are solved cold and from its predictions."""
+    from paper_2505_00311_amd import warmstart as W
+    fam = instances.PortfolioFamily(SEED_FAMILY, n_assets=n_assets, k=50)
+    tr = fam.thetas(SEED_FAMILY + 1, n_train)
+    te = fam.thetas(SEED_FAMILY + 2, n_test)
+    t0 = time.perf_counter()
+    res, _ = W.solve_family(fam, tr)
+    gen_s = time.perf_counter() - t0
+    T = W.targets_of(res)
+    net, norm, hist, train_s = W.train(tr, T, hidden=512, epochs=100, batch=256, lr=1e-3)
+    # the output layer's GEMM on the matrix cores: 256 x (n + m + 1) x 512
+    th = torch.randn(256, 64, dtype=torch.float32, device="cuda")
+    out = torch.empty(256, net.n_out, dtype=torch.float32, device="cuda")
+    net.forward(th, out)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(20):
+        net.forward(th, out)
+    b.record()
+    b.synchronize()
+    fwd_ms = a.elapsed_time(b) / 20
+    flops = 2.0 * 256 * (64 * 512 + 512 * 512 + 512 * net.n_out)
+    cold, cold_s = W.solve_family(fam, te)
+    starts = W.predict(net, norm, te, fam.n, fam.m)
+    warm, warm_s = W.solve_family(fam, te, starts=starts)
+    net.close()
+    it_c = float(np.mean([r["iterations"] for r in cold]))
+    it_w = float(np.mean([r["iterations"] for r in warm]))
+    ok = sum(r["status"] == 0 for r in warm)
+    log(f"warm start: held-out iterations cold {it_c:.0f} warm {it_w:.0f}; time {cold_s:.2f}s vs {warm_s:.2f}s")
+    return {"workload": f"SOC portfolio family, {n_assets} assets, 50 factors, theta in R^64, "
+                        f"{n_train} training and {n_test} held-out parameters, seed {SEED_FAMILY}",
+            "n": fam.n, "m": fam.m, "network": f"64-512-512-{net.n_out} BF16/FP32-accumulate",
+            "training_solves_s": round(gen_s, 2), "training_s": round(train_s, 2),
+            "loss_first_last": [hist[0], hist[-1]],
+            "held_out_iterations_cold": it_c, "held_out_iterations_warm": it_w,
+            "held_out_optimal_warm": ok,
+            "cold_s": round(cold_s, 3), "warm_s": round(warm_s, 3),
+            "speedup_time_to_tol": round(cold_s / warm_s, 3),
+            "forward_ms_batch256": round(fwd_ms, 4),
+            "forward_tflops": round(flops / (fwd_ms * 1e-3) / 1e12, 2),
+            "mfma_bf16_peak_tflops": 2500.0}
+
+
 def cpu_baseline(inst, iters):
     """The oracle as it stands, single thread, on the first `iters` iterations."""
     import oracle
@@ -148,6 +197,10 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=64)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--m", type=int, default=500_000)
+    ap.add_argument("--family-assets", type=int, default=20000,
+                    help="assets of the warm-start family (0: skip the warm-start measurement)")
+    ap.add_argument("--family-train", type=int, default=2048)
+    ap.add_argument("--family-test", type=int, default=256)
     ap.add_argument("--batch-count", type=int, default=32,
                     help="instances of the batched-form measurement (0: skip it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -288,6 +341,9 @@ def main():
 
     if args.batch_count > 0:
         out["batched"] = batched_form(pdcs, instances, torch, args.batch_count)
+    if args.family_assets > 0:
+        out["warm_start"] = warm_start_form(pdcs, instances, torch, args.family_assets,
+                                            args.family_train, args.family_test)
 
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample ...")
