@@ -79,11 +79,11 @@ def counter_traffic(kernel):
         return None
     rec = json.loads(m.group(1))
     src = os.path.join(ROOT, rec["source"])
-    if rec["kernel"] != kernel or not os.path.exists(src):
+    if kernel not in rec["kernels"] or not os.path.exists(src):
         return None
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["sha256"]:
         return None
-    return rec["bytes_per_launch"]
+    return rec["kernels"][kernel]["bytes_per_launch"]
 
 
 def batched_form(pdcs, instances, torch, count):
