@@ -96,6 +96,7 @@ def batched_form(pdcs, instances, torch, count):
     log(f"batched form: {count} instances, sum n {sum(i.n for i in insts)}, sum nnz {nnz}")
     batch = pdcs.Batch(insts)
     batch.solve(pdcs.settings_default(max_iter=64, autotune=1))   # tune and warm up
+    log("  batch created and tuned")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rb = batch.solve(pdcs.settings_default(time_limit=120.0, autotune=1))
@@ -104,7 +105,9 @@ def batched_form(pdcs, instances, torch, count):
     batch.close()
     seq = 0.0
     worst = 0.0
-    for inst, r in zip(insts, rb):
+    for i, (inst, r) in enumerate(zip(insts, rb)):
+        if i % 16 == 0:
+            log(f"  one by one: instance {i} of {count}")
         prob = pdcs.Problem(inst)
         prob.solve(pdcs.settings_default(max_iter=64))   # scaling and graph, as for the batch
         torch.cuda.synchronize()

@@ -129,6 +129,10 @@ typedef struct {
      * 64 lanes per row) on its own matrices with HIP events and keep the
      * fastest for that handle (not in the paper).  0: fixed rule. */
     int32_t autotune;
+    /* Batches: 1 hands the instances still running to problems of their own
+     * (restarted at their chosen candidate with their primal weight) once they
+     * hold at most 1/8 of the batch's nonzeros (not in the paper). */
+    int32_t batch_dropout;
 } pdcs_settings;
 
 /* Kernels of one step attempt, in launch order (indices of pdcs_info.kernel_ms). */

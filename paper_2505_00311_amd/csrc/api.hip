@@ -279,6 +279,11 @@ struct pdcs_problem {
     int64_t *x_off = nullptr, *y_off = nullptr, *k_off = nullptr;   // [B+1]
     int32_t *rcode = nullptr;          // [B] restart codes of a check
     double *seg = nullptr;             // [5 B] per-instance reductions
+    // host copy of a batch's concatenated data, for handing an instance to a
+    // problem of its own (empty for a single problem)
+    std::vector<int64_t> h_rp;
+    std::vector<int32_t> h_ci;
+    std::vector<double> h_val, h_c, h_h, h_l, h_u;
     std::vector<double> cinf, hinf, gmax, cs_norm, hs_norm;
     int scaled_ruiz = -1, scaled_pc = -1;
     // a captured batch of step attempts, replayed on a library stream
@@ -465,7 +470,9 @@ static pdcs_problem *create_impl(const pdcs_problem_desc *Ds, int64_t count, voi
         h2d(P->x_off, xo.data(), B + 1, s);
         h2d(P->y_off, yo.data(), B + 1, s);
         h2d(P->k_off, ko.data(), B + 1, s);
-        PDCS_HIP(hipStreamSynchronize(s));   // the host vectors die at the end of this block
+        PDCS_HIP(hipStreamSynchronize(s));
+        P->h_rp = std::move(rp), P->h_ci = std::move(ci), P->h_val = std::move(val);
+        P->h_c = std::move(c), P->h_h = std::move(h), P->h_l = std::move(l), P->h_u = std::move(u);
     }
     P->flag = M.alloc<int>(4);
     PDCS_HIP(hipMemsetAsync(P->flag, 0, sizeof(int) * 4, s));
@@ -806,6 +813,25 @@ static void run_graph(pdcs_problem *P, bool mixed, hipStream_t s) {
     PDCS_HIP(hipStreamWaitEvent(s, P->ev_out, 0));
 }
 
+// A problem of its own for instance b of a batch, from the batch's host copy.
+static pdcs_problem *extract_instance(const pdcs_problem *P, int64_t b) {
+    const InstDims &I = P->inst[b];
+    std::vector<int64_t> rp(I.m + 1);
+    std::vector<int32_t> ci(I.nnz);
+    for (int64_t r = 0; r <= I.m; ++r) rp[r] = P->h_rp[I.y0 + r] - I.k0;
+    for (int64_t k = 0; k < I.nnz; ++k) ci[k] = P->h_ci[I.k0 + k] - (int32_t)I.x0;
+    pdcs_problem_desc D{};
+    D.n = I.n, D.m = I.m, D.nnz = I.nnz, D.n_box = I.nb;
+    D.row_ptr = rp.data(), D.col = ci.data(), D.val = P->h_val.data() + I.k0;
+    D.c = P->h_c.data() + I.x0, D.h = P->h_h.data() + I.y0;
+    D.l = P->h_l.data() + I.x0, D.u = P->h_u.data() + I.x0;
+    D.n_xcones = P->xblk[b + 1] - P->xblk[b];
+    D.xcone_type = P->xt.data() + P->xblk[b], D.xcone_dim = P->xd.data() + P->xblk[b];
+    D.n_rcones = P->rblk[b + 1] - P->rblk[b];
+    D.rcone_type = P->rt.data() + P->rblk[b], D.rcone_dim = P->rd.data() + P->rblk[b];
+    return create_impl(&D, 1, P->stream, false);
+}
+
 // Algorithm 1 on every instance of P at once.  x0/y0/omega0/xo/yo/infos are
 // per instance (x0[b], y0[b] nullable: cold start; omega0 <= 0: default);
 // a trace is only for a single problem.
@@ -952,7 +978,9 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
         P->tev.resize(E * kGraphBatch, nullptr);
         for (hipEvent_t &e : P->tev) PDCS_HIP(hipEventCreate(&e));
     }
-    std::vector<int32_t> code(B, 0);
+    std::vector<int32_t> code(B, 0), last_src(B, -1);
+    std::vector<pdcs_info> handed(B);     // results of instances finished on their own
+    std::vector<char> was_handed(B, 0);
     while (any_active()) {
         // ---- step attempts until every running instance asks for a check ----
         while (any_running()) {
@@ -1026,6 +1054,7 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
             ++checks[b];
             const Kkt k1 = kkt_from_raw(P, b, raw[b]), k2 = kkt_from_raw(P, b, raw[B + b]);
             const int chosen = k2.avg() < k1.avg() ? 1 : 0;
+            last_src[b] = chosen;
             const Kkt kc = chosen ? k2 : k1;
             const double kcv = kc.avg(), kav = k_anchor[b].avg();
             int reason = 0, stop = 0;
@@ -1101,6 +1130,48 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
             spmv(P->Gts, P->pGt, P->ya, P->aty0, SpmvSkip{}, s);
             for (int64_t b = 0; b < B; ++b) checks[b] += 1;   // four more products each
         }
+        // Stragglers (reading, not in the paper): once the instances still
+        // running hold at most 1/8 of the batch's nonzeros, every launch over
+        // the batch costs more than their own work.  Each is handed to a problem
+        // of its own, restarted at its chosen candidate with its primal weight
+        // (a restart, as Algorithm 1 may take at any check), with the rest of
+        // the iteration and time budget.
+        if (B > 1 && S->batch_dropout && any_active()) {
+            int64_t act_nnz = 0;
+            for (int64_t b = 0; b < B; ++b)
+                if (active(b)) act_nnz += P->inst[b].nnz;
+            if (8 * act_nnz <= P->nnz) {
+                for (int64_t b = 0; b < B; ++b) {
+                    if (!active(b)) continue;
+                    const InstDims &I = P->inst[b];
+                    const int src = last_src[b];
+                    std::vector<double> hx(I.n), hy(I.m);
+                    unscale((src < 0 ? P->xa : P->xc[src]) + I.x0, P->f + I.x0, P->tmp_n + I.x0, I.n, s);
+                    unscale((src < 0 ? P->ya : P->yc[src]) + I.y0, P->e + I.y0, P->tmp_m + I.y0, I.m, s);
+                    d2h(hx.data(), P->tmp_n + I.x0, I.n, s);
+                    d2h(hy.data(), P->tmp_m + I.y0, I.m, s);
+                    PDCS_HIP(hipStreamSynchronize(s));
+                    std::unique_ptr<pdcs_problem> sub(extract_instance(P, b));
+                    pdcs_settings S2 = *S;
+                    S2.max_iter = std::max<int64_t>(0, S->max_iter - hs[b].n_iter);
+                    const double used = std::chrono::duration<double>(clk::now() - t_iter).count();
+                    if (S->time_limit > 0.0) S2.time_limit = std::max(1e-9, S->time_limit - used);
+                    const double *px = hx.data(), *py = hy.data();
+                    const double om = hs[b].omega;
+                    pdcs_info si{};
+                    solve_batch(sub.get(), &S2, &px, &py, &om, &xo[b], &yo[b], &si, nullptr);
+                    si.iterations += hs[b].n_iter;
+                    si.attempts += hs[b].attempts_total;
+                    si.restarts += restarts[b] + 1;
+                    si.spmv += hs[b].attempts_total + hs[b].attempts_cur + hs[b].n_iter + 2 + 4 * checks[b];
+                    handed[b] = si;
+                    was_handed[b] = 1;
+                    status[b] = si.status;
+                    out_src[b] = src;   // written by the problem of its own
+                    hs[b].halt = 1;
+                }
+            }
+        }
         for (int64_t b = 0; b < B; ++b)
             if (active(b)) hs[b].halt = 0;
         h2d(P->st, hs.data(), B, s);
@@ -1124,6 +1195,11 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
         // products: one with G~ per attempt, one with G~^T per accepted
         // iteration, two at the start and four per check
         const long long spmv_count = hs[b].attempts_total + hs[b].attempts_cur + hs[b].n_iter + 2 + 4 * checks[b];
+        if (was_handed[b]) {
+            infos[b] = handed[b];
+            infos[b].setup_s = setup_s, infos[b].solve_s = solve_s;
+            continue;
+        }
         fill_info(infos + b, status[b], hs[b], restarts[b], spmv_count, kout[b], setup_s, solve_s);
         for (int j = 0; j < PDCS_K_COUNT; ++j)
             infos[b].kernel_ms[j] = kms[j], infos[b].kernel_launches[j] = klaunch[j];
@@ -1189,6 +1265,7 @@ pdcs_status pdcs_settings_default(pdcs_settings *s) {
     s->polish_tol = 1e-5;
     s->polish_stall = 8;
     s->autotune = 0;
+    s->batch_dropout = 1;
     return PDCS_OK;
 }
 

@@ -40,7 +40,8 @@ class Settings(ctypes.Structure):
                 ("restart_artificial", _dbl), ("max_attempts", _i32), ("out_on_device", _i32),
                 ("step_mode", _i32), ("step_fixed", _dbl), ("power_iters", _i32),
                 ("use_graph", _i32), ("time_kernels", _i32), ("precision", _i32),
-                ("polish_tol", _dbl), ("polish_stall", _i32), ("autotune", _i32)]
+                ("polish_tol", _dbl), ("polish_stall", _i32), ("autotune", _i32),
+                ("batch_dropout", _i32)]
 
 KERNELS = ("primal", "spmv_g", "dual", "decide", "spmv_gt", "halpern")
 
