@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <new>
 #include <stdexcept>
@@ -248,6 +249,7 @@ using namespace pdcs;
 // Sizes and offsets of one instance inside the (block-diagonal) layout.
 struct InstDims {
     int64_t x0 = 0, n = 0, y0 = 0, m = 0, nb = 0, k0 = 0, nnz = 0;
+    int64_t nb_in = 0;   // entries of the internal box run (box, zero, free, nonnegative)
 };
 
 struct pdcs_problem {
@@ -258,7 +260,12 @@ struct pdcs_problem {
     DevMem mem;
     std::vector<int32_t> xt, rt;       // cone lists of all instances, in order
     std::vector<int64_t> xd, rd;
-    std::vector<int64_t> xblk, rblk;   // [B+1]: cone blocks of instance b
+    std::vector<int64_t> xblk, rblk;   // [B+1]: cone blocks of instance b (the caller's order)
+    // Internal order of x (column popularity): xperm[p] = the caller's index of
+    // internal entry p, xpos its inverse; the x-cone lists in internal order.
+    int32_t *xperm = nullptr, *xpos = nullptr;
+    std::vector<int32_t> ixt;
+    std::vector<int64_t> ixd, ixblk;
     Csr G, Gt;                         // unscaled
     Csr Gs, Gts;                       // scaled values, shared structure
     SpmvPlan pG, pGt;
@@ -496,13 +503,97 @@ static pdcs_problem *create_impl(const pdcs_problem_desc *Ds, int64_t count, voi
     d2h(hrp.data(), P->G.rp, m + 1, s);
     d2h(hrpt.data(), P->Gt.rp, n + 1, s);
     PDCS_HIP(hipStreamSynchronize(s));
+
+    // Internal order of x.  The gathers of x^ in G~x^ follow column popularity
+    // (power-law degrees put most of the accesses on few columns), so in each
+    // instance the hottest columns are renumbered to the front: first the
+    // entries of the elementwise sets (box; zero, free and nonnegative cones,
+    // all held as bounds [l, u]), then the SOC and exponential blocks, each
+    // kept whole and rated by its largest degree.  Hot columns then share cache
+    // lines.
+    {
+        std::vector<double> ul(n), uu(n);   // the caller's bounds, caller's order
+        d2h(ul.data(), P->l, n, s);
+        d2h(uu.data(), P->u, n, s);
+        PDCS_HIP(hipStreamSynchronize(s));
+        std::vector<int32_t> perm(n), pos(n);
+        std::vector<double> il(n), iu(n);
+        P->ixblk.assign(1, 0);
+        for (int64_t b = 0; b < B; ++b) {
+            InstDims &I = P->inst[b];
+            auto deg = [&](int64_t j) { return hrpt[I.x0 + j + 1] - hrpt[I.x0 + j]; };
+            struct Unit { int64_t start, dim, heat; int32_t type; };
+            std::vector<Unit> elem, blk;
+            for (int64_t j = 0; j < I.nb; ++j) elem.push_back({j, 1, deg(j), -1});
+            int64_t o = I.nb;
+            for (int64_t k = P->xblk[b]; k < P->xblk[b + 1]; ++k) {
+                const int32_t t = P->xt[k];
+                const int64_t d = P->xd[k];
+                if (t == kZero || t == kFree || t == kNonneg) {
+                    for (int64_t j = 0; j < d; ++j) elem.push_back({o + j, 1, deg(o + j), t});
+                } else {
+                    int64_t h = 0;
+                    for (int64_t j = 0; j < d; ++j) h = std::max(h, deg(o + j));
+                    blk.push_back({o, d, h, t});
+                }
+                o += d;
+            }
+            auto hotter = [](const Unit &a, const Unit &c) { return a.heat > c.heat; };
+// the hottest 1% of units move to the front, by degree; the others keep
+            // their order (sorting them all clusters the long rows of G~^T, which
+            // cost the transposed product more than the gathers gained: measured)
+            auto front = [&](std::vector<Unit> &v) {
+                if (v.empty()) return;
+                std::vector<int64_t> hs;
+                for (auto &u : v) hs.push_back(u.heat);
+                const size_t k = hs.size() / 100;
+                std::nth_element(hs.begin(), hs.begin() + k, hs.end(), std::greater<int64_t>());
+                const int64_t thr = hs[k];
+                auto mid = std::stable_partition(v.begin(), v.end(),
+                                                 [&](const Unit &u) { return u.heat > thr; });
+                std::stable_sort(v.begin(), mid, hotter);
+            };
+            front(elem);
+            front(blk);
+            int64_t q = 0;
+            for (const Unit &u : elem) {
+                const int64_t g = I.x0 + u.start, p = I.x0 + q++;
+                perm[p] = (int32_t)g;
+                il[p] = u.type < 0 ? ul[g] : (u.type == kFree ? -INFINITY : 0.0);
+                iu[p] = u.type < 0 ? uu[g] : (u.type == kZero ? 0.0 : INFINITY);
+            }
+            I.nb_in = q;
+            for (const Unit &u : blk) {
+                for (int64_t j = 0; j < u.dim; ++j) {
+                    const int64_t p = I.x0 + q++;
+                    perm[p] = (int32_t)(I.x0 + u.start + j);
+                    il[p] = -INFINITY, iu[p] = INFINITY;
+                }
+                P->ixt.push_back(u.type), P->ixd.push_back(u.dim);
+            }
+            P->ixblk.push_back((int64_t)P->ixt.size());
+        }
+        for (int64_t p = 0; p < n; ++p) pos[perm[p]] = (int32_t)p;
+        P->xperm = M.alloc<int32_t>(n), P->xpos = M.alloc<int32_t>(n);
+        h2d(P->xperm, perm.data(), n, s);
+        h2d(P->xpos, pos.data(), n, s);
+        h2d(P->l, il.data(), n, s);
+        h2d(P->u, iu.data(), n, s);
+        relabel(P->G.ci, nnz, P->xpos, s);
+        double *cu = M.alloc<double>(n);
+        copy_vec(P->c, cu, n, s);
+        gather(P->c, cu, P->xperm, n, s);
+        transpose_csr(P->G, P->Gt, s);
+        d2h(hrpt.data(), P->Gt.rp, n + 1, s);
+        PDCS_HIP(hipStreamSynchronize(s));   // the host vectors die at the end of this block
+    }
     P->pG = build_spmv_plan(M, hrp, s);
     P->pGt = build_spmv_plan(M, hrpt, s);
     HostPlan hx, hy;
     for (int64_t b = 0; b < B; ++b) {
         const InstDims &I = P->inst[b];
-        append_plan(hx, (int32_t)b, I.x0, I.nb, I.x0 + I.nb, P->xt.data() + P->xblk[b], P->xd.data() + P->xblk[b],
-                    P->xblk[b + 1] - P->xblk[b]);
+        append_plan(hx, (int32_t)b, I.x0, I.nb_in, I.x0 + I.nb_in, P->ixt.data() + P->ixblk[b],
+                    P->ixd.data() + P->ixblk[b], P->ixblk[b + 1] - P->ixblk[b]);
         append_plan(hy, (int32_t)b, I.y0, 0, I.y0, P->rt.data() + P->rblk[b], P->rd.data() + P->rblk[b],
                     P->rblk[b + 1] - P->rblk[b]);
     }
@@ -885,13 +976,14 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
     }
 
     // z^{0,0}: the mapped starting point projected onto X x Y (reading)
-    fill(P->tmp_n, n, 0.0, s);
+    fill(P->xc[1], n, 0.0, s);   // the caller's order, gathered into the internal one
     fill(P->tmp_m, m, 0.0, s);
     for (int64_t b = 0; b < B; ++b) {
         const InstDims &I = P->inst[b];
-        if (x0 && x0[b]) h2d(P->tmp_n + I.x0, x0[b], I.n, s);
+        if (x0 && x0[b]) h2d(P->xc[1] + I.x0, x0[b], I.n, s);
         if (y0 && y0[b]) h2d(P->tmp_m + I.y0, y0[b], I.m, s);
     }
+    gather(P->tmp_n, P->xc[1], P->xperm, n, s);
     scale_in(P->tmp_n, P->f, P->x, n, s);
     scale_in(P->tmp_m, P->e, P->y, m, s);
     pass_candidate(P->planX, false, CandArgs{P->x, P->ls, P->us, P->dx, P->st, 0, P->xa}, P->partX, s);
@@ -917,13 +1009,15 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
         const InstDims &I = P->inst[b];
         const double *sx = src < 0 ? P->xa : P->xc[src];
         const double *sy = src < 0 ? P->ya : P->yc[src];
+        // x: unscaled, then back to the caller's order (atyh is free between attempts)
+        unscale(sx + I.x0, P->f + I.x0, P->tmp_n + I.x0, I.n, s);
         if (S->out_on_device) {
-            unscale(sx + I.x0, P->f + I.x0, xo[b], I.n, s);
+            scatter(xo[b], P->tmp_n + I.x0, P->xperm + I.x0, I.n, I.x0, s);
             unscale(sy + I.y0, P->e + I.y0, yo[b], I.m, s);
         } else {
-            unscale(sx + I.x0, P->f + I.x0, P->tmp_n + I.x0, I.n, s);
+            scatter(P->atyh + I.x0, P->tmp_n + I.x0, P->xperm + I.x0, I.n, I.x0, s);
             unscale(sy + I.y0, P->e + I.y0, P->tmp_m + I.y0, I.m, s);
-            d2h(xo[b], P->tmp_n + I.x0, I.n, s);
+            d2h(xo[b], P->atyh + I.x0, I.n, s);
             d2h(yo[b], P->tmp_m + I.y0, I.m, s);
         }
         out_src[b] = src;
@@ -1023,8 +1117,9 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
             }
             if (tr && snap < tr->n_snap && hs[0].n_iter > it_before && tr->snap_iter[snap] == hs[0].n_iter) {
                 unscale(P->x, P->f, P->tmp_n, n, s);
+                scatter(P->atyh, P->tmp_n, P->xperm, n, 0, s);
                 unscale(P->y, P->e, P->tmp_m, m, s);
-                d2h(tr->snap_x + snap * n, P->tmp_n, n, s);
+                d2h(tr->snap_x + snap * n, P->atyh, n, s);
                 d2h(tr->snap_y + snap * m, P->tmp_m, m, s);
                 PDCS_HIP(hipStreamSynchronize(s));
                 ++snap;
@@ -1147,8 +1242,9 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
                     const int src = last_src[b];
                     std::vector<double> hx(I.n), hy(I.m);
                     unscale((src < 0 ? P->xa : P->xc[src]) + I.x0, P->f + I.x0, P->tmp_n + I.x0, I.n, s);
+                    scatter(P->atyh + I.x0, P->tmp_n + I.x0, P->xperm + I.x0, I.n, I.x0, s);
                     unscale((src < 0 ? P->ya : P->yc[src]) + I.y0, P->e + I.y0, P->tmp_m + I.y0, I.m, s);
-                    d2h(hx.data(), P->tmp_n + I.x0, I.n, s);
+                    d2h(hx.data(), P->atyh + I.x0, I.n, s);
                     d2h(hy.data(), P->tmp_m + I.y0, I.m, s);
                     PDCS_HIP(hipStreamSynchronize(s));
                     std::unique_ptr<pdcs_problem> sub(extract_instance(P, b));
@@ -1309,7 +1405,8 @@ pdcs_status pdcs_scaling(pdcs_problem *p, const pdcs_settings *settings, double 
         if (!p || !settings || !e_out || !f_out) fail(PDCS_ERR_INVALID_ARG, "NULL argument");
         ensure_scaling(p, settings->ruiz_iters, settings->pock_chambolle ? 1 : 0);
         d2h(e_out, p->e, p->m, p->stream);
-        d2h(f_out, p->f, p->n, p->stream);
+        scatter(p->tmp_n, p->f, p->xperm, p->n, 0, p->stream);
+        d2h(f_out, p->tmp_n, p->n, p->stream);
         PDCS_HIP(hipStreamSynchronize(p->stream));
     });
 }
@@ -1319,10 +1416,14 @@ pdcs_status pdcs_spmv(pdcs_problem *p, int transpose, const double *x_dev, doubl
     return guarded([&] {
         if (!p || !x_dev || !y_dev) fail(PDCS_ERR_INVALID_ARG, "NULL argument");
         hipStream_t s = hip_stream ? (hipStream_t)hip_stream : p->stream;
-        if (transpose)
-            spmv(p->Gt, p->pGt, x_dev, y_dev, SpmvSkip{}, s);
-        else
-            spmv(p->G, p->pG, x_dev, y_dev, SpmvSkip{}, s);
+        // columns are held in the internal order of x
+        if (transpose) {
+            spmv(p->Gt, p->pGt, x_dev, p->tmp_n, SpmvSkip{}, s);
+            scatter(y_dev, p->tmp_n, p->xperm, p->n, 0, s);
+        } else {
+            gather(p->tmp_n, x_dev, p->xperm, p->n, s);
+            spmv(p->G, p->pG, p->tmp_n, y_dev, SpmvSkip{}, s);
+        }
     });
 }
 
@@ -1338,9 +1439,16 @@ pdcs_status pdcs_spmv32(pdcs_problem *p, int transpose, const double *x_dev, dou
             p->x32 = p->mem.alloc<float>(std::max(p->n, p->m));
             p->G.v32 = g32, p->Gt.v32 = gt32;
         }
-        const Csr &A = transpose ? p->Gt : p->G;
-        to_float(x_dev, p->x32, A.cols, s);
-        spmv32(A, transpose ? p->pGt : p->pG, p->x32, y_dev, SpmvSkip{}, s);
+        // columns are held in the internal order of x
+        if (transpose) {
+            to_float(x_dev, p->x32, p->m, s);
+            spmv32(p->Gt, p->pGt, p->x32, p->tmp_n, SpmvSkip{}, s);
+            scatter(y_dev, p->tmp_n, p->xperm, p->n, 0, s);
+        } else {
+            gather(p->tmp_n, x_dev, p->xperm, p->n, s);
+            to_float(p->tmp_n, p->x32, p->n, s);
+            spmv32(p->G, p->pG, p->x32, y_dev, SpmvSkip{}, s);
+        }
     });
 }
 
@@ -1348,9 +1456,11 @@ pdcs_status pdcs_kkt(pdcs_problem *p, const double *x_dev, const double *y_dev, 
     return guarded([&] {
         if (!p || !x_dev || !y_dev || !out) fail(PDCS_ERR_INVALID_ARG, "NULL argument");
         hipStream_t s = p->stream;
-        spmv(p->G, p->pG, x_dev, p->gxc[0], SpmvSkip{}, s);
+        double *xi = p->xc[1];   // x in the internal order
+        gather(xi, x_dev, p->xperm, p->n, s);
+        spmv(p->G, p->pG, xi, p->gxc[0], SpmvSkip{}, s);
         spmv(p->Gt, p->pGt, y_dev, p->atyc[0], SpmvSkip{}, s);
-        enqueue_kkt(p, x_dev, y_dev, p->gxc[0], p->atyc[0], x_dev, y_dev, p->ones_m, p->ones_n, 0);
+        enqueue_kkt(p, xi, y_dev, p->gxc[0], p->atyc[0], xi, y_dev, p->ones_m, p->ones_n, 0);
         KktRaw r;
         d2h(&r, p->kraw, 1, s);
         PDCS_HIP(hipStreamSynchronize(s));

@@ -173,6 +173,10 @@ void copy_vec(const double *a, double *out, int64_t n, hipStream_t s);
 void scale_by_inv_sqrt(const double *w, const double *sumsq, const int32_t *map, double *v,
                        int64_t n, hipStream_t s);
 void fill_by_inst(double *out, const int32_t *map, const double *vals, int64_t n, hipStream_t s);
+void gather(double *out, const double *in, const int32_t *idx, int64_t n, hipStream_t s);
+void scatter(double *out, const double *in, const int32_t *idx, int64_t n, int64_t base,
+             hipStream_t s);
+void relabel(int32_t *ci, int64_t nnz, const int32_t *pos, hipStream_t s);
 void reduce_segments(int mode, const double *a, const int64_t *off, int64_t B, double *out,
                      hipStream_t s);
 

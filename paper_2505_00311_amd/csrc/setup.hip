@@ -351,4 +351,37 @@ void reduce_segments(int mode, const double *a, const int64_t *off, int64_t B, d
     PDCS_HIP(hipGetLastError());
 }
 
+// out[i] = in[idx[i]]
+__global__ void gather_kernel(double *out, const double *in, const int32_t *idx, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[idx[i]];
+}
+void gather(double *out, const double *in, const int32_t *idx, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(gather_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, out, in, idx, n);
+    PDCS_HIP(hipGetLastError());
+}
+// out[idx[i] - base] = in[i]
+__global__ void scatter_kernel(double *out, const double *in, const int32_t *idx, int64_t n,
+                               int64_t base) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[idx[i] - base] = in[i];
+}
+void scatter(double *out, const double *in, const int32_t *idx, int64_t n, int64_t base,
+             hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, out, in, idx, n, base);
+    PDCS_HIP(hipGetLastError());
+}
+// ci[k] = pos[ci[k]]: column indices renumbered
+__global__ void relabel_kernel(int32_t *ci, int64_t nnz, const int32_t *pos) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nnz) ci[k] = pos[ci[k]];
+}
+void relabel(int32_t *ci, int64_t nnz, const int32_t *pos, hipStream_t s) {
+    if (nnz == 0) return;
+    hipLaunchKernelGGL(relabel_kernel, dim3(grid_for(nnz)), dim3(kBlock), 0, s, ci, nnz, pos);
+    PDCS_HIP(hipGetLastError());
+}
+
 }  // namespace pdcs
