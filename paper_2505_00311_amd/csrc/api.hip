@@ -331,6 +331,10 @@ struct pdcs_mlp {
     uint16_t *xb, *h1b, *h2b, *d16;
     float *h1, *h2, *o, *d32, *dh;
     double *part;
+    // transposed operands of the backward GEMMs (all read along k) and the
+    // padded leading dimension of the output gradient (a multiple of 8)
+    uint16_t *ta, *tb, *wt;
+    int64_t ldo = 0;
 };
 
 constexpr int kGraphBatch = 64;   // step attempts per captured graph
@@ -1566,7 +1570,12 @@ pdcs_status pdcs_mlp_create(int64_t in, int64_t hid, int64_t out, int64_t max_ba
         M->h1 = D.alloc<float>(B * hid), M->h1b = D.alloc<uint16_t>(B * hid);
         M->h2 = D.alloc<float>(B * hid), M->h2b = D.alloc<uint16_t>(B * hid);
         M->o = D.alloc<float>(B * out);
-        M->d32 = D.alloc<float>(B * std::max(out, hid)), M->d16 = D.alloc<uint16_t>(B * std::max(out, hid));
+        M->ldo = (out + 7) / 8 * 8;
+        M->d32 = D.alloc<float>(B * std::max(out, hid));
+        M->d16 = D.alloc<uint16_t>(B * std::max(M->ldo, hid));
+        M->ta = D.alloc<uint16_t>(std::max(out, hid) * B);
+        M->tb = D.alloc<uint16_t>(std::max(hid, in) * B);
+        M->wt = D.alloc<uint16_t>(hid * std::max(M->ldo, hid));
         M->dh = D.alloc<float>(B * hid);
         M->part = D.alloc<double>((B * std::max(out, hid) + 255) / 256);
         PDCS_HIP(hipStreamSynchronize(s));
@@ -1591,20 +1600,31 @@ static double mlp_gradient(pdcs_mlp *M, const float *theta, const float *target,
     const int64_t in = M->in, hid = M->hid, O = M->out;
     mlp_forward(M, theta, B, M->o);
     const int64_t n = B * O, nblk = (n + 255) / 256;
-    mse_grad(M->o, target, n, (float)(1.0 / (double)n), M->d32, M->d16, M->part, s);
+    const int64_t ldo = M->ldo;
+    mse_grad(M->o, target, n, O, ldo, (float)(1.0 / (double)n), M->d32, M->d16, M->part, s);
     float *g = M->g;
+    // Every GEMM reads both operands along k: transposed copies of the
+    // activations (k = the batch) and of the weights (k = the output units).
     // layer 3: dW3 = dO^T H2, db3 = colsum(dO), dH2 = dO W3
-    gemm_bf16(1, 0, O, hid, B, M->d16, O, M->h2b, hid, nullptr, 0, g + M->off[4], nullptr, hid, s);
+    transpose_bf16(M->d16, B, O, ldo, M->ta, B, s);
+    transpose_bf16(M->h2b, B, hid, hid, M->tb, B, s);
+    gemm_bf16(0, 1, O, hid, B, M->ta, B, M->tb, B, nullptr, 0, g + M->off[4], nullptr, hid, s);
     colsum(M->d32, B, O, g + M->off[5], s);
-    gemm_bf16(0, 0, B, hid, O, M->d16, O, M->p16 + M->off[4], hid, nullptr, 0, M->dh, nullptr, hid, s);
+    transpose_bf16(M->p16 + M->off[4], O, hid, hid, M->wt, ldo, s);
+    gemm_bf16(0, 1, B, hid, O, M->d16, ldo, M->wt, ldo, nullptr, 0, M->dh, nullptr, hid, s);
     // layer 2
     relu_back(M->dh, M->h2, B * hid, M->d32, M->d16, s);
-    gemm_bf16(1, 0, hid, hid, B, M->d16, hid, M->h1b, hid, nullptr, 0, g + M->off[2], nullptr, hid, s);
+    transpose_bf16(M->d16, B, hid, hid, M->ta, B, s);
+    transpose_bf16(M->h1b, B, hid, hid, M->tb, B, s);
+    gemm_bf16(0, 1, hid, hid, B, M->ta, B, M->tb, B, nullptr, 0, g + M->off[2], nullptr, hid, s);
     colsum(M->d32, B, hid, g + M->off[3], s);
-    gemm_bf16(0, 0, B, hid, hid, M->d16, hid, M->p16 + M->off[2], hid, nullptr, 0, M->dh, nullptr, hid, s);
+    transpose_bf16(M->p16 + M->off[2], hid, hid, hid, M->wt, hid, s);
+    gemm_bf16(0, 1, B, hid, hid, M->d16, hid, M->wt, hid, nullptr, 0, M->dh, nullptr, hid, s);
     // layer 1
     relu_back(M->dh, M->h1, B * hid, M->d32, M->d16, s);
-    gemm_bf16(1, 0, hid, in, B, M->d16, hid, M->xb, in, nullptr, 0, g + M->off[0], nullptr, in, s);
+    transpose_bf16(M->d16, B, hid, hid, M->ta, B, s);
+    transpose_bf16(M->xb, B, in, in, M->tb, B, s);
+    gemm_bf16(0, 1, hid, in, B, M->ta, B, M->tb, B, nullptr, 0, g + M->off[0], nullptr, in, s);
     colsum(M->d32, B, hid, g + M->off[1], s);
     std::vector<double> part(nblk);
     d2h(part.data(), M->part, nblk, s);

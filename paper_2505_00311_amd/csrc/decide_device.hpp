@@ -15,12 +15,24 @@ namespace pdcs {
 // reduced in a fixed order, then thread 0 decides.
 __device__ void decide_body(DevState *__restrict__ st, const double *__restrict__ px, int64_t ntx,
                             const double *__restrict__ py, int64_t nty) {
-    double v[3] = {0.0, 0.0, 0.0};
-    for (int64_t t = threadIdx.x; t < ntx; t += kBlock) v[0] += px[t * kPartials + 0];
-    for (int64_t t = threadIdx.x; t < nty; t += kBlock) {
-        v[1] += py[t * kPartials + 0];
-        v[2] += py[t * kPartials + 1];
-    }
+    // four independent strided partial sums per thread keep four loads in
+    // flight (the reduction is latency-bound); combined in a fixed order
+    double a[4][3] = {};
+    for (int64_t t = threadIdx.x; t < ntx; t += 4 * kBlock)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t q = t + u * kBlock;
+            if (q < ntx) a[u][0] += px[q * kPartials + 0];
+        }
+    for (int64_t t = threadIdx.x; t < nty; t += 4 * kBlock)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t q = t + u * kBlock;
+            if (q < nty) a[u][1] += py[q * kPartials + 0], a[u][2] += py[q * kPartials + 1];
+        }
+    double v[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = (a[0][k] + a[1][k]) + (a[2][k] + a[3][k]);
     block_sum_all<3>(v);
     if (threadIdx.x != 0) return;
     const double nx2 = v[0], ny2 = v[1], ip = v[2];

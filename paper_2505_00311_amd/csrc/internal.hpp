@@ -254,8 +254,10 @@ void gemm_bf16(int ta, int tb, int64_t M, int64_t N, int64_t K, const uint16_t *
                const uint16_t *b, int64_t ldb, const float *bias, int relu, float *c32,
                uint16_t *c16, int64_t ldc, hipStream_t s);
 void to_bf16(const float *in, uint16_t *out, int64_t n, hipStream_t s);
-void mse_grad(const float *out, const float *target, int64_t n, float inv, float *d32, uint16_t *d16,
-              double *part, hipStream_t s);
+void mse_grad(const float *out, const float *target, int64_t n, int64_t cols, int64_t ld16,
+              float inv, float *d32, uint16_t *d16, double *part, hipStream_t s);
+void transpose_bf16(const uint16_t *in, int64_t rows, int64_t cols, int64_t ldi, uint16_t *out,
+                    int64_t ldo, hipStream_t s);
 void relu_back(const float *dh, const float *z, int64_t n, float *dz32, uint16_t *dz16, hipStream_t s);
 void colsum(const float *d, int64_t rows, int64_t cols, float *db, hipStream_t s);
 void adam(float *p, const float *g, float *m1, float *m2, int64_t n, float lr, float b1, float b2,

@@ -8,9 +8,11 @@
 // GEMM: C[M x N] = op(A) op(B) (+ bias[n]) (relu), A and B BF16, C FP32 and/or
 // BF16.  op(A)(m, k) = a[m lda + k] (ta = 0) or a[k lda + m] (ta = 1); op(B)(k, n)
 // = b[k ldb + n] (tb = 0) or b[n ldb + k] (tb = 1).  A workgroup of 4 wavefronts
-// owns a 64 x 64 tile of C, each wavefront a 32 x 32 block; K advances by 16
-// through LDS, where each row of A and each column of B keeps its 16 k-values
-// contiguous so a lane reads its 8 operands in one 16-byte access.
+// owns a 128 x 128 tile of C, each wavefront a 64 x 64 quarter (2 x 2 blocks of
+// 32 x 32 on the matrix cores); K advances by 32 through LDS, where each row of
+// A and each column of B keeps its k-values contiguous so a lane reads its 8
+// operands in one 16-byte access, and operands read along k come in 16-byte
+// vectors when their rows are aligned.
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
@@ -31,9 +33,47 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
     return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
 }
 
-constexpr int kTile = 64, kKStep = 16, kLdsK = 24;   // LDS row: 16 k-values + 8 padding
+constexpr int kTile = 128, kKStep = 32, kLdsK = 40;   // LDS row: 32 k-values + 8 padding
 
-template <int TA, int TB>
+// Stages op(X)[r0 .. r0+127][k0 .. k0+31] into S[r][k] (zero outside), where X
+// is read along k (KCONT: x[r ld + k], 16-byte vectors when VEC) or along r
+// (x[k ld + r]).
+template <bool KCONT, bool VEC>
+__device__ __forceinline__ void stage(uint16_t (*S)[kLdsK], const uint16_t *__restrict__ x,
+                                      int64_t ld, int64_t R, int64_t K, int64_t r0, int64_t k0) {
+    const int t = threadIdx.x;
+    if (KCONT && VEC) {
+        for (int e = t; e < kTile * (kKStep / 8); e += 256) {
+            const int r = e / (kKStep / 8), c = (e % (kKStep / 8)) * 8;
+            const int64_t gr = r0 + r, gk = k0 + c;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (gr < R && gk + 7 < K) {
+                v = *reinterpret_cast<const uint4 *>(x + gr * ld + gk);
+            } else if (gr < R) {   // the ragged end of k
+                uint32_t q[4];
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t lo = gk + 2 * j < K ? x[gr * ld + gk + 2 * j] : 0;
+                    const uint32_t hi = gk + 2 * j + 1 < K ? x[gr * ld + gk + 2 * j + 1] : 0;
+                    q[j] = lo | (hi << 16);
+                }
+                v = make_uint4(q[0], q[1], q[2], q[3]);
+            }
+            *reinterpret_cast<uint4 *>(&S[r][c]) = v;
+        }
+    } else {
+        for (int e = t; e < kTile * kKStep; e += 256) {
+            int r, kk;
+            if (KCONT) r = e / kKStep, kk = e % kKStep;   // consecutive threads walk k
+            else kk = e / kTile, r = e % kTile;           // consecutive threads walk r
+            const int64_t gr = r0 + r, gk = k0 + kk;
+            uint16_t v = 0;
+            if (gr < R && gk < K) v = KCONT ? x[gr * ld + gk] : x[gk * ld + gr];
+            S[r][kk] = v;
+        }
+    }
+}
+
+template <int TA, int TB, bool VA, bool VB>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(int64_t M, int64_t N, int64_t K,
                                                         const uint16_t *__restrict__ a, int64_t lda,
                                                         const uint16_t *__restrict__ b, int64_t ldb,
@@ -43,48 +83,47 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int64_t M, int64_t N, in
     __shared__ __attribute__((aligned(16))) uint16_t As[kTile][kLdsK];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[kTile][kLdsK];
     const int t = threadIdx.x, lane = t % 64, w = t / 64;
-    const int wm = w / 2, wn = w % 2;
+    const int wm = w / 2, wn = w % 2;                 // each wavefront: 64 x 64 of the tile
     const int64_t m0 = (int64_t)blockIdx.y * kTile, n0 = (int64_t)blockIdx.x * kTile;
-    f32x16 acc = {};
+    f32x16 acc[2][2] = {};
+    const int half = lane / 32, idx = lane % 32;
     for (int64_t k0 = 0; k0 < K; k0 += kKStep) {
-        // stage op(A)[m0 .. m0+63][k0 .. k0+15] and op(B)[k0 ..][n0 .. n0+63], zero outside
-        for (int e = t; e < kTile * kKStep; e += 256) {
-            int r, kk;
-            if (TA == 0) r = e / kKStep, kk = e % kKStep;   // consecutive threads walk k
-            else kk = e / kTile, r = e % kTile;             // consecutive threads walk m
-            const int64_t gm = m0 + r, gk = k0 + kk;
-            uint16_t v = 0;
-            if (gm < M && gk < K) v = TA == 0 ? a[gm * lda + gk] : a[gk * lda + gm];
-            As[r][kk] = v;
-        }
-        for (int e = t; e < kTile * kKStep; e += 256) {
-            int cidx, kk;
-            if (TB == 1) cidx = e / kKStep, kk = e % kKStep;
-            else kk = e / kTile, cidx = e % kTile;
-            const int64_t gn = n0 + cidx, gk = k0 + kk;
-            uint16_t v = 0;
-            if (gn < N && gk < K) v = TB == 1 ? b[gn * ldb + gk] : b[gk * ldb + gn];
-            Bs[cidx][kk] = v;
-        }
+        stage<TA == 0, VA>(As, a, lda, M, K, m0, k0);
+        stage<TB == 1, VB>(Bs, b, ldb, N, K, n0, k0);
         __syncthreads();
-        const int half = lane / 32, idx = lane % 32;
-        const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&As[wm * 32 + idx][8 * half]);
-        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&Bs[wn * 32 + idx][8 * half]);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+#pragma unroll
+        for (int kk = 0; kk < kKStep; kk += 16) {
+            bf16x8 av[2], bv[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                av[i] = *reinterpret_cast<const bf16x8 *>(&As[wm * 64 + i * 32 + idx][kk + 8 * half]);
+                bv[i] = *reinterpret_cast<const bf16x8 *>(&Bs[wn * 64 + i * 32 + idx][kk + 8 * half]);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
         __syncthreads();
     }
-    // acc[r]: row 8 (r / 4) + 4 (lane / 32) + r % 4, column lane % 32 of the block
-    const int64_t gn = n0 + wn * 32 + lane % 32;
-    if (gn >= N) return;
-    const float bn = bias ? bias[gn] : 0.0f;
+    // acc[i][j][r]: row 8 (r / 4) + 4 (lane / 32) + r % 4, column lane % 32 of block (i, j)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int64_t gm = m0 + wm * 32 + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
-        if (gm >= M) continue;
-        float v = acc[r] + bn;
-        if (relu && v < 0.0f) v = 0.0f;
-        if (c32) c32[gm * ldc + gn] = v;
-        if (c16) c16[gm * ldc + gn] = f32_to_bf16(v);
+    for (int j = 0; j < 2; ++j) {
+        const int64_t gn = n0 + wn * 64 + j * 32 + idx;
+        if (gn >= N) continue;
+        const float bn = bias ? bias[gn] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t gm = m0 + wm * 64 + i * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+                if (gm >= M) continue;
+                float v = acc[i][j][r] + bn;
+                if (relu && v < 0.0f) v = 0.0f;
+                if (c32) c32[gm * ldc + gn] = v;
+                if (c16) c16[gm * ldc + gn] = f32_to_bf16(v);
+            }
     }
 }
 
@@ -93,13 +132,26 @@ void gemm_bf16(int ta, int tb, int64_t M, int64_t N, int64_t K, const uint16_t *
                uint16_t *c16, int64_t ldc, hipStream_t s) {
     if (M == 0 || N == 0) return;
     const dim3 grid((unsigned)((N + kTile - 1) / kTile), (unsigned)((M + kTile - 1) / kTile));
-#define PDCS_GEMM(TA, TB)                                                                        \
-    hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB>), grid, dim3(256), 0, s, M, N, K, a, lda, b, ldb, \
-                       bias, relu, c32, c16, ldc)
-    if (ta == 0 && tb == 0) PDCS_GEMM(0, 0);
-    else if (ta == 0) PDCS_GEMM(0, 1);
-    else if (tb == 0) PDCS_GEMM(1, 0);
-    else PDCS_GEMM(1, 1);
+    // 16-byte loads along k need 8-aligned rows and a 16-byte aligned base
+    const bool va = ta == 0 && lda % 8 == 0 && ((uintptr_t)a % 16) == 0;
+    const bool vb = tb == 1 && ldb % 8 == 0 && ((uintptr_t)b % 16) == 0;
+#define PDCS_GEMM(TA, TB, VA, VB)                                                                \
+    hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, VA, VB>), grid, dim3(256), 0, s, M, N, K, a, lda, \
+                       b, ldb, bias, relu, c32, c16, ldc)
+    if (ta == 0 && tb == 1) {
+        if (va && vb) PDCS_GEMM(0, 1, true, true);
+        else if (va) PDCS_GEMM(0, 1, true, false);
+        else if (vb) PDCS_GEMM(0, 1, false, true);
+        else PDCS_GEMM(0, 1, false, false);
+    } else if (ta == 0) {
+        if (va) PDCS_GEMM(0, 0, true, false);
+        else PDCS_GEMM(0, 0, false, false);
+    } else if (tb == 1) {
+        if (vb) PDCS_GEMM(1, 1, false, true);
+        else PDCS_GEMM(1, 1, false, false);
+    } else {
+        PDCS_GEMM(1, 0, false, false);
+    }
 #undef PDCS_GEMM
     PDCS_HIP(hipGetLastError());
 }
@@ -115,16 +167,43 @@ void to_bf16(const float *in, uint16_t *out, int64_t n, hipStream_t s) {
     PDCS_HIP(hipGetLastError());
 }
 
-// d = (out - target) / (rows cols); loss partial sums of (out - target)^2 per block
-__global__ void mse_kernel(const float *out, const float *target, int64_t n, float inv,
-                           float *d32, uint16_t *d16, double *part) {
+// out[c ldo + r] = in[r ldi + c] for a rows x cols BF16 matrix, through a
+// 32 x 32 LDS tile so reads and writes are both along rows
+__global__ __launch_bounds__(256) void transpose_bf16_kernel(const uint16_t *in, int64_t rows,
+                                                             int64_t cols, int64_t ldi,
+                                                             uint16_t *out, int64_t ldo) {
+    __shared__ uint16_t tile[32][33];
+    const int64_t c0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+    for (int k = ty; k < 32; k += 8) {
+        const int64_t r = r0 + k, c = c0 + tx;
+        tile[k][tx] = (r < rows && c < cols) ? in[r * ldi + c] : 0;
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int64_t c = c0 + k, r = r0 + tx;
+        if (c < cols && r < rows) out[c * ldo + r] = tile[tx][k];
+    }
+}
+void transpose_bf16(const uint16_t *in, int64_t rows, int64_t cols, int64_t ldi, uint16_t *out,
+                    int64_t ldo, hipStream_t s) {
+    if (rows == 0 || cols == 0) return;
+    const dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
+    hipLaunchKernelGGL(transpose_bf16_kernel, grid, dim3(256), 0, s, in, rows, cols, ldi, out, ldo);
+    PDCS_HIP(hipGetLastError());
+}
+
+// d = (out - target) / (rows cols) for a rows x cols batch (d32 dense, d16 with
+// leading dimension ld16); loss partial sums of (out - target)^2 per block
+__global__ void mse_kernel(const float *out, const float *target, int64_t n, int64_t cols,
+                           int64_t ld16, float inv, float *d32, uint16_t *d16, double *part) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double acc[1] = {0.0};
     if (i < n) {
         const float r = out[i] - target[i];
         const float g = r * inv;
         d32[i] = g;
-        d16[i] = f32_to_bf16(g);
+        d16[(i / cols) * ld16 + i % cols] = f32_to_bf16(g);
         acc[0] = (double)r * (double)r;
     }
     block_sum_all<1>(acc);
@@ -164,10 +243,10 @@ __global__ void adam_kernel(float *p, const float *g, float *m1, float *m2, int6
     if (p16) p16[i] = f32_to_bf16(q);
 }
 
-void mse_grad(const float *out, const float *target, int64_t n, float inv, float *d32, uint16_t *d16,
-              double *part, hipStream_t s) {
+void mse_grad(const float *out, const float *target, int64_t n, int64_t cols, int64_t ld16,
+              float inv, float *d32, uint16_t *d16, double *part, hipStream_t s) {
     hipLaunchKernelGGL(mse_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, target,
-                       n, inv, d32, d16, part);
+                       n, cols, ld16, inv, d32, d16, part);
     PDCS_HIP(hipGetLastError());
 }
 void relu_back(const float *dh, const float *z, int64_t n, float *dz32, uint16_t *dz16, hipStream_t s) {

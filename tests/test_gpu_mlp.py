@@ -21,7 +21,8 @@ def from_bits(t):
     return u.view(np.float32).astype(np.float64)
 
 
-SHAPES = [(77, 131, 48), (64, 1000, 512), (37, 2051, 80), (128, 64, 16), (1, 5, 3)]
+SHAPES = [(77, 131, 48), (64, 1000, 512), (37, 2051, 80), (128, 64, 16), (1, 5, 3),
+          (256, 300, 520), (130, 257, 44)]
 
 
 @pytest.mark.parametrize("ta", [0, 1])
