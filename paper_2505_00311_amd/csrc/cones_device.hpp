@@ -31,7 +31,7 @@ __device__ __forceinline__ bool in_kexp_dual(double r, double s, double t) {
 }
 
 struct ExpPt {
-    double r0, s0, t0, dr, ds, dt, tau;
+    double r0, s0, t0, dr, ds, dt, tau, idr, idt;
 };
 
 // s_p(rho), r_d(rho) of eq. (sp_rd) with tau = ds / dr.
@@ -42,23 +42,26 @@ __device__ __forceinline__ void exp_sprd(const ExpPt &c, double rho, double &sp,
 }
 
 // e^{-|rho|} h(rho) of eq. (h_rho) and its derivative: same sign and roots as
-// h, no overflow for any rho.
+// h, no overflow for any rho.  One division per evaluation (1/den); 1/dr and
+// 1/dt are the cone's.
 __device__ __forceinline__ void exp_hs(const ExpPt &c, double rho, double &f, double &df) {
     const double den = rho * rho - rho + c.tau * c.tau;
+    const double iden = 1.0 / den;
     const double ns = c.s0 * c.tau - c.r0 + c.r0 * rho;
     const double nr = c.tau * c.r0 - rho * c.s0;
-    const double sp = ns / (c.dr * den);
-    const double rd = c.ds * nr / den;
-    const double dsp = (c.r0 * den - ns * (2.0 * rho - 1.0)) / (c.dr * den * den);
-    const double drd = c.ds * (-c.s0 * den - nr * (2.0 * rho - 1.0)) / (den * den);
+    const double sp = ns * iden * c.idr;
+    const double rd = c.ds * nr * iden;
+    const double q = 2.0 * rho - 1.0;
+    const double dsp = (c.r0 * den - ns * q) * (iden * iden) * c.idr;
+    const double drd = c.ds * (-c.s0 * den - nr * q) * (iden * iden);
     if (rho >= 0.0) {
         const double em = exp(-rho);
-        f = c.dt * sp - em * em * rd / c.dt - c.t0 * em;
-        df = c.dt * dsp + em * em * (2.0 * rd - drd) / c.dt + c.t0 * em;
+        f = c.dt * sp - em * em * rd * c.idt - c.t0 * em;
+        df = c.dt * dsp + em * em * (2.0 * rd - drd) * c.idt + c.t0 * em;
     } else {
         const double ep = exp(rho);
-        f = c.dt * ep * ep * sp - rd / c.dt - c.t0 * ep;
-        df = c.dt * ep * ep * (2.0 * sp + dsp) - drd / c.dt - c.t0 * ep;
+        f = c.dt * ep * ep * sp - rd * c.idt - c.t0 * ep;
+        df = c.dt * ep * ep * (2.0 * sp + dsp) - drd * c.idt - c.t0 * ep;
     }
 }
 
@@ -68,11 +71,12 @@ __device__ __forceinline__ double exp_hs_value(const ExpPt &c, double rho) {
     return f;
 }
 
-// Newton's method on the sign bracket [xneg, xpos], with a bisection step
-// whenever Newton would leave the bracket, would not halve the step, or meets
-// a non-finite value; stops at a step of 4 ulp of max(1, |rho|).
-__device__ double exp_root(const ExpPt &c, double xneg, double xpos) {
-    double rho = 0.5 * (xneg + xpos);
+// Newton's method on the sign bracket [xneg, xpos] from `start` (the bracket's
+// midpoint when start is not inside it), with a bisection step whenever Newton
+// would leave the bracket, would not halve the step, or meets a non-finite
+// value; stops at a step of 4 ulp of max(1, |rho|).
+__device__ double exp_root(const ExpPt &c, double xneg, double xpos, double start) {
+    double rho = (start >= fmin(xneg, xpos) && start <= fmax(xneg, xpos)) ? start : 0.5 * (xneg + xpos);
     double dxold = fabs(xpos - xneg), dx = dxold;
     double f, df;
     exp_hs(c, rho, f, df);
@@ -150,7 +154,7 @@ __device__ void exp_project(double r0, double s0, double t0, double dr, double d
     // is its limit to double precision: (0, 0, t0+) when a4 > 700 in case (iii),
     // (r0, s0, dt (s0/ds) e^a3) when a3 < -700 in case (ii).
     constexpr double R = 700.0;
-    const ExpPt c{r0, s0, t0, dr, ds, dt, ds / dr};
+    const ExpPt c{r0, s0, t0, dr, ds, dt, ds / dr, 1.0 / dr, 1.0 / dt};
     double xneg, xpos, lo, hi;   // [lo, hi]: the case-4 interval kept inside |rho| <= R
     int side;                    // 0: both ends finite, 1: (-inf, a3), 2: (a4, inf)
     if (r0 > 0.0 && s0 > 0.0) {
@@ -193,7 +197,8 @@ __device__ void exp_project(double r0, double s0, double t0, double dr, double d
             xpos = fmin(xneg + step, R);
         }
     }
-    const double rho = exp_root(c, xneg, xpos);
+    // Newton starts at the guess when there is one (its local bracket holds it)
+    const double rho = exp_root(c, xneg, xpos, guess);
     rho_out = rho;
     // v_p = s_p w(rho), w = (dr rho, ds, dt e^rho); at the root v0 - v_p is
     // orthogonal to w, so s_p = <v0, w>/||w||^2 (projection of v0 onto the ray
@@ -222,19 +227,39 @@ __device__ __forceinline__ void exp_dual_project(double r0, double s0, double t0
 }
 
 // ------------------------------------------------------- second-order cone
+// A lane's partner value under a DPP pattern (CTRL), for a double.
+template <int CTRL>
+__device__ __forceinline__ double dpp_partner(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Sum over an aligned group of LPB lanes (a power of two <= 64); every lane of
 // the group receives the same bits, which keeps the lanes of a group on one
-// path through the root finder.  That needs each exchange to add two rounded
-// values: with contraction the compiler may fuse the caller's last product into
-// the first exchange, fma(a, a, round(b*b)) in one lane against
+// path through the root finder.  Each stage adds a lane's value to that of its
+// partner under an involution (lanes i and j = p(i) exchange), so both hold
+// the same sum: within a row of 16 lanes by DPP (quad xor 1, quad xor 2, the
+// half-row mirror i <-> 7 - i, the row mirror i <-> 15 - i), across rows by
+// lane permutes (xor 16, xor 32).  That needs each exchange to add two rounded
+// values: with contraction the compiler may fuse the caller's last product
+// into the first exchange, fma(a, a, round(b*b)) in one lane against
 // fma(b, b, round(a*a)) in its partner, and the two halves of the group then
 // follow different Newton paths.  Contraction is therefore off for these adds.
 template <int LPB>
 __device__ __forceinline__ double group_sum(double v) {
 #pragma clang fp contract(off)
-#pragma unroll
-    for (int off = LPB / 2; off > 0; off >>= 1) {
-        const double o = __shfl_xor(v, off, kWave);
+    if (LPB >= 2) v = v + dpp_partner<0xB1>(v);    // quad_perm [1,0,3,2]
+    if (LPB >= 4) v = v + dpp_partner<0x4E>(v);    // quad_perm [2,3,0,1]
+    if (LPB >= 8) v = v + dpp_partner<0x141>(v);   // row_half_mirror
+    if (LPB >= 16) v = v + dpp_partner<0x140>(v);  // row_mirror
+    if (LPB >= 32) {
+        const double o = __shfl_xor(v, 16, kWave);
+        v = v + o;
+    }
+    if (LPB >= 64) {
+        const double o = __shfl_xor(v, 32, kWave);
         v = v + o;
     }
     return v;
