@@ -194,6 +194,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--layout", default=None,
+                    help="product layouts 'G,GT' as pdcs_set_layout codes (default: the library's)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-time-to-tol", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -234,9 +236,11 @@ def main():
     log(f"generated n={inst.n} m={inst.m} nnz={inst.nnz} in {time.perf_counter() - t:.1f}s")
     t = time.perf_counter()
     prob = pdcs.Problem(inst)
+    if args.layout:
+        prob.set_layout(*[int(v) for v in args.layout.split(",")])
     torch.cuda.synchronize()
     create_s = time.perf_counter() - t
-    log(f"problem created (upload, G^T, plans) in {create_s:.2f}s")
+    log(f"problem created (upload, G^T, plans) in {create_s:.2f}s; product layouts {prob.layout()}")
 
     # warmup: W check periods (also computes and caches the rescaling)
     prob.solve(pdcs.settings_default(max_iter=CHECK * max(args.warmup, 1)))

@@ -242,6 +242,30 @@ pdcs_status pdcs_spmv(pdcs_problem *p, int transpose, const double *x_dev, doubl
 pdcs_status pdcs_spmv32(pdcs_problem *p, int transpose, const double *x_dev, double *y_dev,
                         void *hip_stream);
 
+/* Kernel layout of the two products of eq. (5) (not in the paper; the same
+ * sums, formed in another order):
+ *   PDCS_LAYOUT_DEFAULT (0)  chosen from the shape at creation;
+ *   PDCS_LAYOUT_STREAM (-1)  CSR-stream: workgroups stream row ranges of at
+ *                            most 2048 entries through LDS;
+ *   L in {2,4,...,64}        row-split: L lanes per row;
+ *   PDCS_LAYOUT_SLABS(S)     S in {1,2,4,8} column slabs of equal entry counts,
+ *                            each slab's workgroups on 8/S of the 8 XCDs, so
+ *                            an XCD gathers from 1/S of the vector; the S slab
+ *                            sums of a row are added in slab order.
+ * In every layout a row with more entries than the layout's threshold
+ * (max(64, 32 L), L the lanes of the row-split rule for the mean row length,
+ * at most 2048 in the streamed layouts) is summed in chunks of 4096 entries,
+ * added in chunk order.  pdcs_set_layout
+ * rebuilds the plans of G x (layout_g) and G^T y (layout_gt) and keeps them
+ * (pdcs_settings.autotune then leaves them alone); pdcs_get_layout reports the
+ * layouts in use (0 only before any is chosen).  Errors: INVALID_ARG for an
+ * unknown code, NOT_SUPPORTED for slabs with 2^31 or more rows or entries. */
+#define PDCS_LAYOUT_DEFAULT 0
+#define PDCS_LAYOUT_STREAM (-1)
+#define PDCS_LAYOUT_SLABS(S) (-10 - (S))
+pdcs_status pdcs_set_layout(pdcs_problem *p, int layout_g, int layout_gt);
+pdcs_status pdcs_get_layout(const pdcs_problem *p, int *layout_g, int *layout_gt);
+
 /* Termination measures of eq. (PDCS_terminate_tolerance) at the unscaled
  * point (x_dev [n], y_dev [m], device memory).  out[5] (host) receives
  * err_p, err_d, err_gap, primal objective, dual objective. */

@@ -179,19 +179,126 @@ static ConePlan upload_plan(DevMem &mem, const HostPlan &H, hipStream_t s) {
     return P;
 }
 
-// Launch plan of one product.  Default: CSR-stream when rows average fewer
-// than 12 entries, else `choose_lanes` lanes per row.  `force` (from the
-// autotuner): 0 = default, -1 = CSR-stream, L > 0 = row-split with L lanes.
+// Product layouts by code: 0 = default, -1 = CSR-stream, L > 0 = row-split
+// with L lanes per row, slab_code(S) = column slabs (S in 1, 2, 4, 8).
+static int slab_code(int S) { return -10 - S; }
+static int slabs_of(int code) { return code <= -10 ? -10 - code : 0; }
+
+// Host copies of the structure a column-slab plan is cut from: the column
+// indices and, per column, the running count of entries (the row pointers of
+// the transpose).
+struct SlabSource {
+    const std::vector<int32_t> *ci = nullptr;
+    const std::vector<int64_t> *col_cum = nullptr;
+};
+
+// Column slabs of a plan whose long rows (and their chunks) are set: slab k
+// takes the columns [cb[k], cb[k+1]) that hold about nnz k/S .. nnz (k+1)/S
+// entries; each slab's entries of the short rows are kept in row order (and in
+// CSR order within a row), and cut into blocks of at most kStreamNnz entries
+// and kSlabRows rows.  Block i of the launch runs on XCD i mod kXcds; XCDs
+// k g .. k g + g - 1 (g = kXcds / S) take the blocks of slab k, padded with
+// empty blocks so that every slab keeps its XCDs.
+static void add_slabs(DevMem &mem, SpmvPlan &P, const std::vector<int64_t> &rp,
+                      const SlabSource &src, int S, hipStream_t s) {
+    if (!src.ci || !src.col_cum) fail(PDCS_ERR_NOT_SUPPORTED, "column-slab plan without its structure");
+    if (S != 1 && S != 2 && S != 4 && S != 8) fail(PDCS_ERR_NOT_SUPPORTED, "slab count must divide 8");
+    const std::vector<int32_t> &ci = *src.ci;
+    const std::vector<int64_t> &cc = *src.col_cum;
+    const int64_t rows = (int64_t)rp.size() - 1, nnz = rp.back(), cols = (int64_t)cc.size() - 1;
+    if (rows >= INT32_MAX || nnz >= INT32_MAX)
+        fail(PDCS_ERR_NOT_SUPPORTED, "column-slab plan limited to 2^31 rows and entries");
+    std::vector<int64_t> cb(S + 1, 0);
+    cb[S] = cols;
+    for (int k = 1; k < S; ++k) {
+        const int64_t t = nnz * k / S;
+        int64_t c = std::lower_bound(cc.begin(), cc.end(), t) - cc.begin();
+        cb[k] = std::min(cols, std::max(cb[k - 1], c));
+    }
+    std::vector<int8_t> slab_of(cols);
+    for (int k = 0; k < S; ++k)
+        for (int64_t j = cb[k]; j < cb[k + 1]; ++j) slab_of[j] = (int8_t)k;
+    const int64_t R1 = rows + 1;
+    std::vector<int32_t> lrp((size_t)(S * R1), 0);
+    auto is_long = [&](int64_t r) { return rp[r + 1] - rp[r] > P.long_thr; };
+    for (int64_t r = 0; r < rows; ++r) {
+        if (is_long(r)) continue;
+        for (int64_t e = rp[r]; e < rp[r + 1]; ++e) ++lrp[slab_of[ci[e]] * R1 + r + 1];
+    }
+    P.n_slabs = S;
+    P.slab_base[0] = 0;
+    for (int k = 0; k < S; ++k) {
+        int32_t *l = lrp.data() + k * R1;
+        for (int64_t r = 0; r < rows; ++r) l[r + 1] += l[r];
+        P.slab_base[k + 1] = P.slab_base[k] + l[rows];
+    }
+    for (int k = S + 1; k <= kMaxSlabs; ++k) P.slab_base[k] = P.slab_base[S];
+    const int64_t total = P.slab_base[S];
+    std::vector<int32_t> sci(total), sperm(total), cur(lrp);
+    for (int64_t r = 0; r < rows; ++r) {
+        if (is_long(r)) continue;
+        for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+            const int k = slab_of[ci[e]];
+            const int64_t q = P.slab_base[k] + cur[k * R1 + r]++;
+            sci[q] = ci[e], sperm[q] = (int32_t)e;
+        }
+    }
+    for (int k = 0; k < S; ++k)   // row pointers into the concatenated slab arrays
+        for (int64_t r = 0; r <= rows; ++r) lrp[k * R1 + r] += (int32_t)P.slab_base[k];
+    std::vector<std::vector<SlabBlock>> lists(S);
+    for (int k = 0; k < S; ++k) {
+        const int32_t *l = lrp.data() + k * R1;
+        auto close = [&](int64_t a, int64_t b) {
+            lists[k].push_back({(int32_t)a, (int32_t)b, l[a], (l[b] - l[a]) | (k << 16)});
+        };
+        int64_t start = 0, acc = 0;
+        for (int64_t r = 0; r < rows; ++r) {
+            const int64_t len = l[r + 1] - l[r];
+            if (acc + len > kStreamNnz || r - start >= kStreamRows) {
+                close(start, r);
+                start = r, acc = 0;
+            }
+            acc += len;
+        }
+        if (rows > start) close(start, rows);
+    }
+    const int g = kXcds / S;
+    size_t rounds = 0;
+    for (int k = 0; k < S; ++k) rounds = std::max(rounds, (lists[k].size() + g - 1) / g);
+    std::vector<SlabBlock> blk(rounds * kXcds, SlabBlock{0, 0, 0, 0});
+    for (int k = 0; k < S; ++k)
+        for (size_t j = 0; j < lists[k].size(); ++j)
+            blk[(j / g) * kXcds + k * g + j % g] = lists[k][j];
+    P.n_slab_blocks = (int64_t)blk.size();
+    P.slab_rp = mem.alloc<int32_t>(S * R1);
+    P.slab_ci = mem.alloc<int32_t>(total);
+    P.slab_perm = mem.alloc<int32_t>(total);
+    P.slab_blk = mem.alloc<SlabBlock>(P.n_slab_blocks);
+    P.slab_part = mem.alloc<double>(S * rows);
+    h2d(P.slab_rp, lrp.data(), S * R1, s);
+    h2d(P.slab_ci, sci.data(), total, s);
+    h2d(P.slab_perm, sperm.data(), total, s);
+    h2d(P.slab_blk, blk.data(), P.n_slab_blocks, s);
+    PDCS_HIP(hipStreamSynchronize(s));
+}
+
+// Launch plan of one product (layout codes above).  Default: CSR-stream when
+// rows average fewer than 12 entries, else `choose_lanes` lanes per row.  Rows
+// longer than max(64, 32 L) entries (L = choose_lanes or the forced lanes,
+// at most kStreamNnz in the streamed layouts) are long.
 static SpmvPlan build_spmv_plan(DevMem &mem, const std::vector<int64_t> &rp, hipStream_t s,
-                                int force = 0) {
+                                int force = 0, const SlabSource &src = SlabSource{}) {
     SpmvPlan P;
     const int64_t rows = (int64_t)rp.size() - 1;
     const int64_t nnz = rp.back();
     const double avg = rows > 0 ? (double)nnz / (double)rows : 0.0;
+    const int slabs = slabs_of(force);
     P.lanes = force > 0 ? force : choose_lanes(rows > 0 ? avg : 1.0);
     P.long_thr = std::max<int64_t>(64, 32 * P.lanes);
-    P.stream = force == -1 ? 1 : force > 0 ? 0 : (avg < 12.0 ? 1 : 0);
-    if (P.stream) P.long_thr = std::min<int64_t>(P.long_thr, kStreamNnz);
+    P.stream = force == -1 ? 1 : force != 0 ? 0 : (avg < 12.0 ? 1 : 0);
+    // rows one thread adds up in a streamed block stay short: longer rows go
+    // to the chunks
+    if (P.stream || slabs) P.long_thr = std::min<int64_t>(P.long_thr, kStreamNnz);
     // rows longer than long_thr: chunks of kLongChunk entries
     std::vector<int32_t> lr, crow;
     std::vector<int64_t> cptr{0}, cbeg;
@@ -215,7 +322,7 @@ static SpmvPlan build_spmv_plan(DevMem &mem, const std::vector<int64_t> &rp, hip
                 start = i + 1, acc = 0;
                 continue;
             }
-            if (acc + len > kStreamNnz) {
+            if (acc + len > kStreamNnz || i - start >= kStreamRows) {
                 sb.push_back(start), sb.push_back(i);
                 start = i, acc = 0;
             }
@@ -223,6 +330,7 @@ static SpmvPlan build_spmv_plan(DevMem &mem, const std::vector<int64_t> &rp, hip
         }
         if (rows > start) sb.push_back(start), sb.push_back(rows);
     }
+    if (slabs) add_slabs(mem, P, rp, src, slabs, s);
     P.n_long = (int64_t)lr.size();
     P.n_chunks = (int64_t)cbeg.size();
     P.n_sblocks = (int64_t)sb.size() / 2;
@@ -269,8 +377,8 @@ struct pdcs_problem {
     Csr G, Gt;                         // unscaled
     Csr Gs, Gts;                       // scaled values, shared structure
     SpmvPlan pG, pGt;
-    int tuned = 0;                     // 1 once the autotuner has chosen the product plans
-    int forceG = 0, forceGt = 0;       // the chosen configurations (0: default)
+    std::unique_ptr<DevMem> planmem[2];   // arrays of pG, pGt (replaced with the plan)
+    int tuned = 0;                     // 1 once the plans are chosen (autotuner or caller)
     ConePlan planX, planY;
     // l, u: length n, -inf/+inf outside the box entries of each instance
     double *c, *h, *l, *u, *ones_n, *ones_m;
@@ -381,6 +489,25 @@ static void check_desc(const pdcs_problem_desc *D) {
         (D->n_box > 0 && (!D->l || !D->u)))
         fail(PDCS_ERR_INVALID_ARG, "NULL array");
 }
+
+// Values of each matrix in the slab order of the plan it is used with (G and
+// G~ with pG, G^T and G~^T with pGt); plans without slabs need none.  Called
+// whenever a plan or the values change.
+static void sync_slab_values(pdcs_problem *P) {
+    hipStream_t s = P->stream;
+    auto one = [&](Csr &A, const SpmvPlan &pl) {
+        if (pl.n_slabs == 0 || !A.v) return;
+        if (!A.sv) A.sv = P->mem.alloc<double>(A.nnz);
+        if (A.v32 && !A.sv32) A.sv32 = P->mem.alloc<float>(A.nnz);
+        slab_values(A, pl, s);
+    };
+    one(P->G, P->pG);
+    one(P->Gs, P->pG);
+    one(P->Gt, P->pGt);
+    one(P->Gts, P->pGt);
+}
+
+static void set_plan(pdcs_problem *P, int side, int code);
 
 // A problem, or a batch of `count` independent problems laid out block-
 // diagonally: instance b owns entries [x0, x0 + n) of x, rows [y0, y0 + m) and
@@ -591,8 +718,8 @@ static pdcs_problem *create_impl(const pdcs_problem_desc *Ds, int64_t count, voi
         d2h(hrpt.data(), P->Gt.rp, n + 1, s);
         PDCS_HIP(hipStreamSynchronize(s));   // the host vectors die at the end of this block
     }
-    P->pG = build_spmv_plan(M, hrp, s);
-    P->pGt = build_spmv_plan(M, hrpt, s);
+    set_plan(P.get(), 0, 0);
+    set_plan(P.get(), 1, 0);
     HostPlan hx, hy;
     for (int64_t b = 0; b < B; ++b) {
         const InstDims &I = P->inst[b];
@@ -645,6 +772,7 @@ static pdcs_problem *create_impl(const pdcs_problem_desc *Ds, int64_t count, voi
     P->hinf.assign(r.begin() + B, r.end());
     for (int64_t b = 0; b < B; ++b)
         if (P->inst[b].m == 0) P->hinf[b] = 0.0;
+    sync_slab_values(P.get());
     return P.release();
 }
 
@@ -676,6 +804,7 @@ static void ensure_scaling(pdcs_problem *P, int ruiz, int pc) {
         to_float(P->Gs.v, P->Gs.v32, P->nnz, s);
         to_float(P->Gts.v, P->Gts.v32, P->nnz, s);
     }
+    sync_slab_values(P);
     scale_problem_vectors(n, m, n, P->c, P->h, P->l, P->u, P->e, P->f, P->cs, P->hs, P->ls,
                           P->us, P->dx, P->dy, s);
     std::vector<double> r(3 * B, 0.0);
@@ -710,12 +839,77 @@ static void ensure_fp32(pdcs_problem *P) {
     to_float(P->Gs.v, g32, P->nnz, s);
     to_float(P->Gts.v, gt32, P->nnz, s);
     P->Gs.v32 = g32, P->Gts.v32 = gt32;
+    sync_slab_values(P);
 }
 
-// Autotuner of the product plans: times each candidate configuration (CSR-
-// stream, row-split with 2..64 lanes per row) of G~ and G~^T on the problem's
-// own matrices with HIP events and keeps the fastest.  Runs once per problem,
-// before the first graph capture.
+// Host copies of G's (or G^T's) column indices and the running column counts.
+static void slab_source(pdcs_problem *P, bool transposed, std::vector<int32_t> &ci,
+                        std::vector<int64_t> &cc) {
+    const Csr &A = transposed ? P->Gt : P->G;
+    const Csr &At = transposed ? P->G : P->Gt;
+    ci.resize(A.nnz), cc.resize(At.rows + 1);
+    d2h(ci.data(), A.ci, A.nnz, P->stream);
+    d2h(cc.data(), At.rp, At.rows + 1, P->stream);
+    PDCS_HIP(hipStreamSynchronize(P->stream));
+}
+
+// The layout code of a plan (see pdcs_set_layout).
+static int layout_code(const SpmvPlan &pl) {
+    return pl.n_slabs > 0 ? slab_code(pl.n_slabs) : pl.stream ? -1 : pl.lanes;
+}
+
+static bool valid_layout(int code) {
+    if (code == 0 || code == -1) return true;
+    for (int L = 2; L <= 64; L <<= 1)
+        if (code == L) return true;
+    const int S = slabs_of(code);
+    return S == 1 || S == 2 || S == 4 || S == 8;
+}
+
+// The default layout of a product: column slabs when the gathered vector
+// passes half an XCD's L2 (one slab per 2 MB of it, 2 to 8 slabs), so each
+// XCD keeps its slab cached beside the streamed entries; else 0 (CSR-stream for rows averaging fewer than 12
+// entries, row-split otherwise).  Batches keep the latter (their instances'
+// vectors are small; the autotuner can still pick slabs).
+static int default_layout(const pdcs_problem *P, int side) {
+    const Csr &A = side == 0 ? P->G : P->Gt;
+    const double bytes = 8.0 * (double)A.cols;
+    if (P->B != 1 || bytes <= kXcdL2Bytes / 2 || A.nnz >= INT32_MAX || A.rows >= INT32_MAX) return 0;
+    int S = 2;
+    while (S < kMaxSlabs && bytes > S * (kXcdL2Bytes / 2.0)) S <<= 1;
+    return slab_code(S);
+}
+
+// Rebuilds the plan of G x (side 0) or G^T y (side 1) in layout `code`, frees
+// the old plan's arrays once the device is idle, and drops the captured graphs
+// (they hold the old plan).  The caller refreshes the slab values.
+static void set_plan(pdcs_problem *P, int side, int code) {
+    hipStream_t s = P->stream;
+    if (code == 0) code = default_layout(P, side);
+    const Csr &A = side == 0 ? P->G : P->Gt;
+    std::vector<int64_t> rp(A.rows + 1);
+    d2h(rp.data(), A.rp, A.rows + 1, s);
+    PDCS_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> ci;
+    std::vector<int64_t> cc;
+    if (slabs_of(code)) {
+        if (P->nnz >= INT32_MAX || A.rows >= INT32_MAX)
+            fail(PDCS_ERR_NOT_SUPPORTED, "column slabs need fewer than 2^31 rows and entries");
+        slab_source(P, side == 1, ci, cc);
+    }
+    auto mem = std::make_unique<DevMem>();
+    const SpmvPlan pl = build_spmv_plan(*mem, rp, s, code, SlabSource{&ci, &cc});
+    PDCS_HIP(hipDeviceSynchronize());   // no launch in flight still reads the old plan
+    for (hipGraphExec_t &g : P->gexec)
+        if (g) (void)hipGraphExecDestroy(g), g = nullptr;
+    (side == 0 ? P->pG : P->pGt) = pl;
+    P->planmem[side] = std::move(mem);
+}
+
+// Autotuner of the product plans: times each candidate layout (CSR-stream,
+// row-split with 2..64 lanes per row, 2, 4 or 8 column slabs) of G~ and G~^T
+// on the problem's own matrices with HIP events and keeps the fastest.  Runs
+// once per problem, before the first graph capture.
 static void autotune_spmv(pdcs_problem *P) {
     if (P->tuned) return;
     hipStream_t s = P->stream;
@@ -726,17 +920,28 @@ static void autotune_spmv(pdcs_problem *P) {
     hipEvent_t a, b;
     PDCS_HIP(hipEventCreate(&a));
     PDCS_HIP(hipEventCreate(&b));
-    const int cands[] = {-1, 2, 4, 8, 16, 32, 64};
+    const bool slab_ok = P->nnz < INT32_MAX && P->m < INT32_MAX && P->n < INT32_MAX;
+    std::vector<int> cands{-1, 2, 4, 8, 16, 32, 64};
+    if (slab_ok)
+        for (int S : {2, 4, 8}) cands.push_back(slab_code(S));
     for (int side = 0; side < 2; ++side) {
-        const Csr &A = side == 0 ? P->Gs : P->Gts;
+        Csr A = side == 0 ? P->Gs : P->Gts;
         const std::vector<int64_t> &rp = side == 0 ? hrp : hrpt;
+        std::vector<int32_t> hci;
+        std::vector<int64_t> hcc;
+        if (slab_ok) slab_source(P, side == 1, hci, hcc);
+        const SlabSource src{&hci, &hcc};
         double *in = side == 0 ? P->ones_n : P->ones_m;
         double *out = side == 0 ? P->tmp_m : P->tmp_n;
+        DevMem vals;
+        A.sv = slab_ok ? vals.alloc<double>(A.nnz) : nullptr;
+        A.sv32 = nullptr;
         float best = INFINITY;
         int best_c = 0;
         for (int c : cands) {
             DevMem tmp;
-            const SpmvPlan plan = build_spmv_plan(tmp, rp, s, c);
+            const SpmvPlan plan = build_spmv_plan(tmp, rp, s, c, src);
+            slab_values(A, plan, s);
             spmv(A, plan, in, out, SpmvSkip{}, s);   // warm
             PDCS_HIP(hipEventRecord(a, s));
             for (int r = 0; r < 5; ++r) spmv(A, plan, in, out, SpmvSkip{}, s);
@@ -746,16 +951,11 @@ static void autotune_spmv(pdcs_problem *P) {
             PDCS_HIP(hipEventElapsedTime(&ms, a, b));
             if (ms < best) best = ms, best_c = c;
         }
-        if (side == 0) {
-            P->forceG = best_c;
-            P->pG = build_spmv_plan(P->mem, rp, s, best_c);
-        } else {
-            P->forceGt = best_c;
-            P->pGt = build_spmv_plan(P->mem, rp, s, best_c);
-        }
+        set_plan(P, side, best_c);
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
+    sync_slab_values(P);
     P->tuned = 1;
 }
 
@@ -951,11 +1151,7 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
     hipStream_t s = P->stream;
     const int64_t n = P->n, m = P->m;
     ensure_scaling(P, S->ruiz_iters, S->pock_chambolle ? 1 : 0);
-    if (S->autotune && !P->tuned) {
-        autotune_spmv(P);
-        for (hipGraphExec_t &g : P->gexec)   // captured with the old plans
-            if (g) (void)hipGraphExecDestroy(g), g = nullptr;
-    }
+    if (S->autotune && !P->tuned) autotune_spmv(P);   // drops graphs of the old plans
     bool mixed = S->precision == 1;
     if (mixed) ensure_fp32(P);
     int64_t polish_iter = mixed ? -1 : 0;
@@ -1442,6 +1638,7 @@ pdcs_status pdcs_spmv32(pdcs_problem *p, int transpose, const double *x_dev, dou
             to_float(p->Gt.v, gt32, p->nnz, s);
             p->x32 = p->mem.alloc<float>(std::max(p->n, p->m));
             p->G.v32 = g32, p->Gt.v32 = gt32;
+            sync_slab_values(p);
         }
         // columns are held in the internal order of x
         if (transpose) {
@@ -1453,6 +1650,27 @@ pdcs_status pdcs_spmv32(pdcs_problem *p, int transpose, const double *x_dev, dou
             to_float(p->tmp_n, p->x32, p->n, s);
             spmv32(p->G, p->pG, p->x32, y_dev, SpmvSkip{}, s);
         }
+    });
+}
+
+pdcs_status pdcs_set_layout(pdcs_problem *p, int layout_g, int layout_gt) {
+    return guarded([&] {
+        if (!p) fail(PDCS_ERR_INVALID_ARG, "NULL problem");
+        if (!valid_layout(layout_g) || !valid_layout(layout_gt))
+            fail(PDCS_ERR_INVALID_ARG, "unknown layout code");
+        set_plan(p, 0, layout_g);
+        set_plan(p, 1, layout_gt);
+        sync_slab_values(p);
+        PDCS_HIP(hipStreamSynchronize(p->stream));
+        p->tuned = 1;
+    });
+}
+
+pdcs_status pdcs_get_layout(const pdcs_problem *p, int *layout_g, int *layout_gt) {
+    return guarded([&] {
+        if (!p || !layout_g || !layout_gt) fail(PDCS_ERR_INVALID_ARG, "NULL argument");
+        *layout_g = layout_code(p->pG);
+        *layout_gt = layout_code(p->pGt);
     });
 }
 

@@ -71,13 +71,27 @@ struct Csr {
     int32_t *ci = nullptr;
     double *v = nullptr;
     float *v32 = nullptr;   // FP32 copy of v (mixed-precision form), or null
+    // v and v32 in the entry order of a column-slab plan (null unless the
+    // matrix is used with one; filled by slab_values)
+    double *sv = nullptr;
+    float *sv32 = nullptr;
 };
 
 // Launch plan of one sparse product: short rows take `lanes` lanes each; rows
 // longer than long_thr are cut into chunks of kLongChunk entries, one
 // workgroup per chunk, and summed per row in chunk order.
 constexpr int64_t kLongChunk = 4096;
-constexpr int kStreamNnz = 1024;   // entries per workgroup of the CSR-stream kernel
+constexpr int kStreamNnz = 2048;   // entries per streamed workgroup (CSR-stream, slabs)
+constexpr int kStreamRows = 1024;  // rows per streamed workgroup
+constexpr int kMaxSlabs = 8;
+constexpr int kXcds = 8;           // MI355X: workgroup i runs on XCD i mod 8
+constexpr double kXcdL2Bytes = 4.0 * 1024 * 1024;   // L2 of one XCD
+// One workgroup of the column-slab kernel: rows [r0, r1) of slab `slab`, whose
+// entries are [k0, k0 + cnt) of the slab arrays; cs = cnt | slab << 16.  One
+// 16-byte load.
+struct alignas(16) SlabBlock {
+    int32_t r0, r1, k0, cs;
+};
 struct SpmvPlan {
     int lanes = 8;
     int stream = 0;                    // 1: CSR-stream kernel for the short rows
@@ -91,6 +105,20 @@ struct SpmvPlan {
     int32_t *chunk_row = nullptr;      // [n_chunks] long-row index
     int64_t *chunk_begin = nullptr;    // [n_chunks] first nnz
     double *chunk_part = nullptr;      // [n_chunks]
+    // Column-slab form (n_slabs > 0): the columns are cut into n_slabs ranges
+    // of equal entry counts and each slab is a CSR matrix over all rows, its
+    // entries held contiguously from slab_base[s] (column slab_ci, values in
+    // the matrix's sv/sv32, taken from entry slab_perm of the plain CSR); its
+    // workgroups run on the XCDs given to it, so each XCD gathers from one
+    // slab of x, and the slab sums of a row are added in slab order.
+    int n_slabs = 0;
+    int64_t n_slab_blocks = 0;
+    int64_t slab_base[kMaxSlabs + 1] = {};
+    int32_t *slab_rp = nullptr;        // [n_slabs (rows+1)] row pointers into the slab arrays
+    int32_t *slab_ci = nullptr;        // [nnz - long-row entries]
+    int32_t *slab_perm = nullptr;      // [same]
+    SlabBlock *slab_blk = nullptr;     // [n_slab_blocks]
+    double *slab_part = nullptr;       // [n_slabs rows] per-slab row sums
 };
 
 // Iteration state kept on the device, read and written by the step kernels.
@@ -177,6 +205,9 @@ void gather(double *out, const double *in, const int32_t *idx, int64_t n, hipStr
 void scatter(double *out, const double *in, const int32_t *idx, int64_t n, int64_t base,
              hipStream_t s);
 void relabel(int32_t *ci, int64_t nnz, const int32_t *pos, hipStream_t s);
+// A.sv (and A.sv32 when both A.v32 and A.sv32 are set) <- the values in the
+// slab order of p (the caller allocates them).  No-op for a plan without slabs.
+void slab_values(const Csr &A, const SpmvPlan &p, hipStream_t s);
 void reduce_segments(int mode, const double *a, const int64_t *off, int64_t B, double *out,
                      hipStream_t s);
 

@@ -12,6 +12,15 @@
 // ~1e5 long) are cut into chunks of kLongChunk entries, one workgroup per
 // chunk, and each row's chunk sums are added in chunk order, so every row's
 // sum is formed in a fixed order on every run.
+//
+// Column-slab form: gathers of x with power-law column popularity miss each
+// XCD's L2 on almost every entry once x outgrows it.  The plan cuts the
+// columns into S slabs of equal entry counts; workgroup i runs on XCD i mod 8
+// and the plan orders the workgroups so that each XCD takes the blocks of one
+// slab only, whose slice of x (|x|/S) then stays in that XCD's L2.  Each
+// workgroup streams a row range of its slab like the CSR-stream kernel and
+// writes the slab's row sums; a second kernel adds a row's S slab sums in slab
+// order (a fixed order, so results repeat bit for bit from run to run).
 #include "device_common.hpp"
 
 namespace pdcs {
@@ -76,10 +85,64 @@ __global__ __launch_bounds__(kBlock) void spmv_rows_kernel(int64_t rows, const i
     if (lane == 0) y[row] = acc;
 }
 
+// One streamed block: rows [0, nrows) of a row range whose entries are
+// [k0, k0 + cnt) (cnt <= kStreamNnz, nrows <= kStreamRows); rp points at the
+// range's first row pointer, ci, v and out are offset to the range.  Every
+// thread first issues all of its loads (row pointers into LDS, then its
+// kStreamNnz / kBlock column indices and values, then the gathers of x), so a
+// block waits on two memory latencies rather than one per entry; the products
+// go to LDS and one thread per row adds its segment in entry order.
+template <class T, class RP>
+__device__ __forceinline__ void stream_block(int nrows, const RP *__restrict__ rp, RP k0, int cnt,
+                                             const int32_t *__restrict__ ci,
+                                             const T *__restrict__ v, const T *__restrict__ x,
+                                             double *__restrict__ out) {
+    __shared__ double prod[kStreamNnz];
+    __shared__ int32_t seg[kStreamRows + 1];
+    constexpr int U = kStreamNnz / kBlock;
+    constexpr int UR = (kStreamRows + kBlock) / kBlock;   // covers nrows + 1 <= kStreamRows + 1
+    const int t = threadIdx.x;
+    // loads at clamped indices, unconditional, so none waits behind a branch
+    int32_t sg[UR];
+#pragma unroll
+    for (int u = 0; u < UR; ++u) sg[u] = (int32_t)(rp[min(t + u * kBlock, nrows)] - k0);
+    if (cnt > 0) {
+        int32_t c[U];
+        T w[U], xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = min(t + u * kBlock, cnt - 1);
+            c[u] = ci[i];
+            w[u] = v[i];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (t + u * kBlock < cnt) prod[t + u * kBlock] = (double)w[u] * (double)xv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < UR; ++u)
+        if (t + u * kBlock <= nrows) seg[t + u * kBlock] = sg[u];
+    __syncthreads();
+    for (int r = t; r < nrows; r += kBlock) {
+        int i = seg[r];
+        const int e = seg[r + 1];
+        double acc = 0.0;
+        for (; i + 4 <= e; i += 4) {   // four reads in flight, added in entry order
+            const double a0 = prod[i], a1 = prod[i + 1], a2 = prod[i + 2], a3 = prod[i + 3];
+            acc += a0;
+            acc += a1;
+            acc += a2;
+            acc += a3;
+        }
+        for (; i < e; ++i) acc += prod[i];
+        out[r] = acc;
+    }
+}
+
 // CSR-stream: after the chunk workgroups, workgroup b owns the rows
-// [sb[2b], sb[2b+1]) whose entries (at most kStreamNnz, long rows excluded by the
-// plan) it streams with unit stride into LDS as products, then one thread per
-// row adds its segment in order.
+// [sb[2b], sb[2b+1]) (long rows excluded by the plan), streamed as above.
 template <class T>
 __global__ __launch_bounds__(kBlock) void spmv_stream_kernel(const int64_t *__restrict__ rp,
                                                              const int32_t *__restrict__ ci,
@@ -93,7 +156,6 @@ __global__ __launch_bounds__(kBlock) void spmv_stream_kernel(const int64_t *__re
             long_chunk(blockIdx.x, rp, ci, v, x, p);
         return;
     }
-    __shared__ double prod[kStreamNnz];
     const int64_t bb = (int64_t)blockIdx.x - p.n_chunks;
     const int64_t r0 = p.sblock[2 * bb], r1 = p.sblock[2 * bb + 1];
     // a batch: skip the workgroup when all its rows belong to one flagged
@@ -102,15 +164,8 @@ __global__ __launch_bounds__(kBlock) void spmv_stream_kernel(const int64_t *__re
         row_skipped(skip, r0))
         return;
     const int64_t k0 = rp[r0];
-    const int cnt = (int)(rp[r1] - k0);
-    for (int i = threadIdx.x; i < cnt; i += kBlock) prod[i] = (double)v[k0 + i] * (double)x[ci[k0 + i]];
-    __syncthreads();
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += kBlock) {
-        const int a = (int)(rp[r] - k0), b = (int)(rp[r + 1] - k0);
-        double acc = 0.0;
-        for (int i = a; i < b; ++i) acc += prod[i];
-        y[r] = acc;
-    }
+    stream_block<T, int64_t>((int)(r1 - r0), rp + r0, k0, (int)(rp[r1] - k0), ci + k0, v + k0, x,
+                             y + r0);
 }
 
 // smallest power of two >= half the mean row length, within [2, 64]
@@ -128,11 +183,87 @@ static void launch_rows(const Csr &A, const SpmvPlan &p, const T *v, const T *x,
                        A.rp, A.ci, v, x, y, p, skip);
 }
 
+// Column-slab blocks [0, n_slab_blocks), then the long-row chunks.  A block
+// streams its slab's entries of rows [r0, r1) like a CSR-stream block and
+// writes the slab sums of those rows (0 for an empty segment).
 template <class T>
-static void spmv_impl(const Csr &A, const SpmvPlan &p, const T *v, const T *x, double *y,
-                      const SpmvSkip &skip, hipStream_t s) {
+__global__ __launch_bounds__(kBlock) void spmv_slab_kernel(int64_t rows,
+                                                           const int64_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ ci,
+                                                           const T *__restrict__ v,
+                                                           const T *__restrict__ sv,
+                                                           const T *__restrict__ x, SpmvPlan p,
+                                                           SpmvSkip skip) {
+    if (!skip.row_inst && row_skipped(skip, 0)) return;   // one problem: one flag
+    if ((int64_t)blockIdx.x >= p.n_slab_blocks) {
+        const int64_t c = (int64_t)blockIdx.x - p.n_slab_blocks;
+        if (!row_skipped(skip, p.long_rows[p.chunk_row[c]])) long_chunk(c, rp, ci, v, x, p);
+        return;
+    }
+    const SlabBlock d = p.slab_blk[blockIdx.x];
+    if (d.r1 <= d.r0) return;   // padding that keeps the slab-to-XCD assignment
+    if (skip.row_inst && inst_of(skip.row_inst, d.r0) == inst_of(skip.row_inst, d.r1 - 1) &&
+        row_skipped(skip, d.r0))
+        return;
+    const int cnt = d.cs & 0xffff, slab = d.cs >> 16;
+    const int32_t *__restrict__ lrp = p.slab_rp + (int64_t)slab * (rows + 1) + d.r0;
+    stream_block<T, int32_t>(d.r1 - d.r0, lrp, d.k0, cnt, p.slab_ci + d.k0, sv + d.k0, x,
+                             p.slab_part + (int64_t)slab * rows + d.r0);
+}
+
+// y[i] = sum over slabs s = 0..S-1 of slab_part[s][i], in slab order.  Long
+// rows have no slab entries (their 0 is overwritten by spmv_chunks_finish).
+template <int S>
+__global__ __launch_bounds__(kBlock) void spmv_slab_sum(int64_t rows, const double *__restrict__ part,
+                                                        double *__restrict__ y, SpmvSkip skip) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= rows || row_skipped(skip, i)) return;
+    double t[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) t[k] = part[k * rows + i];
+    double acc = t[0];
+#pragma unroll
+    for (int k = 1; k < S; ++k) acc += t[k];
+    y[i] = acc;
+}
+
+template <class T>
+__global__ void slab_values_kernel(const T *__restrict__ v, const int32_t *__restrict__ perm,
+                                   T *__restrict__ out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = v[perm[i]];
+}
+
+void slab_values(const Csr &A, const SpmvPlan &p, hipStream_t s) {
+    const int64_t n = p.slab_base[p.n_slabs];
+    if (p.n_slabs == 0 || n == 0) return;
+    if (!A.sv) throw_hip(hipErrorInvalidValue, "slab values not allocated", __FILE__, __LINE__);
+    const unsigned g = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL((slab_values_kernel<double>), dim3(g), dim3(256), 0, s, A.v, p.slab_perm, A.sv, n);
+    if (A.v32 && A.sv32)
+        hipLaunchKernelGGL((slab_values_kernel<float>), dim3(g), dim3(256), 0, s, A.v32, p.slab_perm,
+                           A.sv32, n);
+    PDCS_HIP(hipGetLastError());
+}
+
+template <class T>
+static void spmv_impl(const Csr &A, const SpmvPlan &p, const T *v, const T *sv, const T *x,
+                      double *y, const SpmvSkip &skip, hipStream_t s) {
     if (A.rows == 0) return;
-    if (p.stream) {
+    if (p.n_slabs > 0) {
+        if (!sv) throw_hip(hipErrorInvalidValue, "column-slab plan without slab values", __FILE__, __LINE__);
+        const int64_t blocks = p.n_slab_blocks + p.n_chunks;
+        if (blocks > 0)
+            hipLaunchKernelGGL((spmv_slab_kernel<T>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                               A.rows, A.rp, A.ci, v, sv, x, p, skip);
+        const dim3 g((unsigned)((A.rows + kBlock - 1) / kBlock));
+        switch (p.n_slabs) {
+        case 1: hipLaunchKernelGGL(spmv_slab_sum<1>, g, dim3(kBlock), 0, s, A.rows, p.slab_part, y, skip); break;
+        case 2: hipLaunchKernelGGL(spmv_slab_sum<2>, g, dim3(kBlock), 0, s, A.rows, p.slab_part, y, skip); break;
+        case 4: hipLaunchKernelGGL(spmv_slab_sum<4>, g, dim3(kBlock), 0, s, A.rows, p.slab_part, y, skip); break;
+        default: hipLaunchKernelGGL(spmv_slab_sum<8>, g, dim3(kBlock), 0, s, A.rows, p.slab_part, y, skip); break;
+        }
+    } else if (p.stream) {
         const int64_t blocks = p.n_sblocks + p.n_chunks;
         if (blocks > 0)
             hipLaunchKernelGGL((spmv_stream_kernel<T>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
@@ -155,13 +286,13 @@ static void spmv_impl(const Csr &A, const SpmvPlan &p, const T *v, const T *x, d
 
 void spmv(const Csr &A, const SpmvPlan &p, const double *x, double *y, const SpmvSkip &skip,
           hipStream_t s) {
-    spmv_impl<double>(A, p, A.v, x, y, skip, s);
+    spmv_impl<double>(A, p, A.v, A.sv, x, y, skip, s);
 }
 
 void spmv32(const Csr &A, const SpmvPlan &p, const float *x, double *y, const SpmvSkip &skip,
             hipStream_t s) {
     if (A.rows > 0 && !A.v32) throw_hip(hipErrorInvalidValue, "spmv32 without FP32 values", __FILE__, __LINE__);
-    spmv_impl<float>(A, p, A.v32, x, y, skip, s);
+    spmv_impl<float>(A, p, A.v32, A.sv32, x, y, skip, s);
 }
 
 }  // namespace pdcs

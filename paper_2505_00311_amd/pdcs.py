@@ -68,7 +68,7 @@ _lib = None
 
 SYMBOLS = ["pdcs_settings_default", "pdcs_problem_create", "pdcs_problem_create_device",
            "pdcs_problem_destroy", "pdcs_solve", "pdcs_scaling", "pdcs_spmv", "pdcs_spmv32",
-           "pdcs_kkt", "pdcs_project", "pdcs_batch_create", "pdcs_batch_solve", "pdcs_batch_size",
+           "pdcs_set_layout", "pdcs_get_layout", "pdcs_kkt", "pdcs_project", "pdcs_batch_create", "pdcs_batch_solve", "pdcs_batch_size",
            "pdcs_batch_destroy", "pdcs_mlp_create", "pdcs_mlp_num_params", "pdcs_mlp_forward",
            "pdcs_mlp_gradient", "pdcs_mlp_train_step", "pdcs_mlp_get_params", "pdcs_mlp_destroy",
            "pdcs_gemm_bf16", "pdcs_status_string", "pdcs_last_error"]
@@ -99,6 +99,8 @@ def load():
     L.pdcs_scaling.argtypes = [_vp, ctypes.POINTER(Settings), _vp, _vp]
     L.pdcs_spmv.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
     L.pdcs_spmv32.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
+    L.pdcs_set_layout.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
+    L.pdcs_get_layout.argtypes = [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     L.pdcs_kkt.argtypes = [_vp, _vp, _vp, _vp]
     L.pdcs_project.argtypes = [_i64, _pi32, _pi64, ctypes.c_int, _vp, _vp, _vp]
     L.pdcs_batch_create.argtypes = [ctypes.POINTER(ProblemDesc), _i64, _vp, ctypes.POINTER(_vp)]
@@ -246,6 +248,15 @@ class Batch:
             pass
 
 
+LAYOUT_DEFAULT = 0
+LAYOUT_STREAM = -1
+
+
+def slabs(S):
+    """Layout code of the column-slab product with S slabs (PDCS_LAYOUT_SLABS)."""
+    return -10 - int(S)
+
+
 class Problem:
     """A problem handle (pdcs_problem_create / pdcs_problem_create_device)."""
 
@@ -339,6 +350,16 @@ class Problem:
         fn = load().pdcs_spmv32 if fp32 else load().pdcs_spmv
         _check(fn(self.handle, 1 if transpose else 0, _dptr(x_dev), _dptr(y_dev),
                   _stream(stream) if stream is not None else self.stream))
+
+    def set_layout(self, layout_g, layout_gt):
+        """pdcs_set_layout: product layouts by code (LAYOUT_* / slabs(S) / lanes)."""
+        _check(load().pdcs_set_layout(self.handle, int(layout_g), int(layout_gt)))
+
+    def layout(self):
+        """pdcs_get_layout -> (layout of G x, layout of G^T y)."""
+        g, gt = ctypes.c_int(0), ctypes.c_int(0)
+        _check(load().pdcs_get_layout(self.handle, ctypes.byref(g), ctypes.byref(gt)))
+        return g.value, gt.value
 
     def kkt(self, x_dev, y_dev):
         """pdcs_kkt at unscaled device tensors -> dict."""
