@@ -340,6 +340,12 @@ static SpmvPlan build_spmv_plan(DevMem &mem, const std::vector<int64_t> &rp, hip
     P.chunk_begin = mem.alloc<int64_t>(P.n_chunks);
     P.chunk_part = mem.alloc<double>(P.n_chunks);
     P.sblock = mem.alloc<int64_t>((int64_t)sb.size());
+    if (P.n_long > 0) {
+        std::vector<int32_t> lof(rows, -1);
+        for (int64_t l = 0; l < P.n_long; ++l) lof[lr[l]] = (int32_t)l;
+        P.long_of = mem.alloc<int32_t>(rows);
+        h2d(P.long_of, lof.data(), rows, s);
+    }
     h2d(P.long_rows, lr.data(), P.n_long, s);
     h2d(P.long_chunk_ptr, cptr.data(), P.n_long + 1, s);
     h2d(P.chunk_row, crow.data(), P.n_chunks, s);
@@ -1044,12 +1050,26 @@ static void enqueue_attempts(pdcs_problem *P, long long batch, bool mixed, hipSt
                              const hipEvent_t *ev = nullptr) {
     const PrimalArgs pa{P->x, P->aty, P->cs, P->ls, P->us, P->dx, P->xh, P->st,
                         mixed ? P->xh32 : nullptr};
-    const DualArgs da{P->y, P->gxh, P->gx, P->hs, P->dy, P->yh, P->st, mixed ? P->yh32 : nullptr};
-    const HalpernArgs ha{P->x,  P->aty, P->xsum, P->xh, P->atyh, P->xa, P->aty0, P->y, P->gx,
-                         P->ysum, P->yh, P->gxh, P->ya, P->gx0,  P->n,    P->m,  P->st,
-                         P->x_inst, P->y_inst};
+    // each product is one launch: its finishing sums are taken by the dual
+    // pass (G~x^) and the Halpern step (G~^T y^)
+    DualArgs da{P->y, P->gxh, P->gx, P->hs, P->dy, P->yh, P->st, mixed ? P->yh32 : nullptr};
+    da.gt = tail_of(P->pG, P->m);
+    da.gxh_out = P->gxh;
+    HalpernArgs ha{P->x,  P->aty, P->xsum, P->xh, P->atyh, P->xa, P->aty0, P->y, P->gx,
+                   P->ysum, P->yh, P->gxh, P->ya, P->gx0,  P->n,    P->m,  P->st,
+                   P->x_inst, P->y_inst};
+    ha.at = tail_of(P->pGt, P->n);
+    // the step decision runs in the G~^T launch, so that product cannot wait
+    // for it: it is formed for every running instance (and unused after a
+    // rejected attempt); the decision's halt takes effect in the next attempt
+    ha.promote = P->st;
+    ha.n_inst = P->B;
+    DecideArgs dec;
+    dec.st = P->st, dec.B = P->B;
+    dec.px = P->partX, dec.tx = P->planX.inst_tiles, dec.ntx = P->planX.ntiles;
+    dec.py = P->partY, dec.ty = P->planY.inst_tiles, dec.nty = P->planY.ntiles;
     const SpmvSkip on_halt{P->st, P->y_inst, SkipHalt};       // rows of G~: y entries
-    const SpmvSkip on_reject{P->st, P->x_inst, SkipUpdate};   // rows of G~^T: x entries
+    const SpmvSkip on_halt_t{P->st, P->x_inst, SkipHalt};     // rows of G~^T: x entries
     constexpr int E = PDCS_K_COUNT + 1;
     auto mark = [&](long long b, int j) {
         if (ev) PDCS_HIP(hipEventRecord(ev[E * b + j], s));
@@ -1059,19 +1079,17 @@ static void enqueue_attempts(pdcs_problem *P, long long batch, bool mixed, hipSt
         pass_primal(P->planX, pa, P->partX, s);
         mark(b, PDCS_K_SPMV_G);
         if (mixed)
-            spmv32(P->Gs, P->pG, P->xh32, P->gxh, on_halt, s);
+            spmv32_head(P->Gs, P->pG, P->xh32, P->gxh, on_halt, s);
         else
-            spmv(P->Gs, P->pG, P->xh, P->gxh, on_halt, s);
+            spmv_head(P->Gs, P->pG, P->xh, P->gxh, on_halt, s);
         mark(b, PDCS_K_DUAL);
         pass_dual(P->planY, da, P->partY, s);
-        mark(b, PDCS_K_DECIDE);
-        decide(P->st, P->B, P->partX, P->planX.inst_tiles, P->planX.ntiles, P->partY,
-               P->planY.inst_tiles, P->planY.ntiles, s);
+        mark(b, PDCS_K_DECIDE);   // no launch of its own: inside the next one
         mark(b, PDCS_K_SPMV_GT);
         if (mixed)
-            spmv32(P->Gts, P->pGt, P->yh32, P->atyh, on_reject, s);
+            spmv32_head(P->Gts, P->pGt, P->yh32, P->atyh, on_halt_t, s, dec);
         else
-            spmv(P->Gts, P->pGt, P->yh, P->atyh, on_reject, s);
+            spmv_head(P->Gts, P->pGt, P->yh, P->atyh, on_halt_t, s, dec);
         mark(b, PDCS_K_HALPERN);
         halpern(ha, s);
         mark(b, PDCS_K_COUNT);
@@ -1245,7 +1263,7 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
         if (k_anchor[b].mx() <= S->tol) status[b] = PDCS_SOLVE_OPTIMAL;
         if (!(k_anchor[b].mx() == k_anchor[b].mx())) status[b] = PDCS_SOLVE_NUMERICAL;
         if (status[b] < 0 && S->max_iter <= 0) status[b] = PDCS_SOLVE_ITER_LIMIT;
-        h.halt = status[b] >= 0 ? 1 : 0;
+        h.halt = h.halt_next = status[b] >= 0 ? 1 : 0;
     }
     h2d(P->st, hs.data(), B, s);
     const auto t_iter = clk::now();
@@ -1468,8 +1486,10 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
                 }
             }
         }
-        for (int64_t b = 0; b < B; ++b)
+        for (int64_t b = 0; b < B; ++b) {
             if (active(b)) hs[b].halt = 0;
+            hs[b].halt_next = hs[b].halt;
+        }
         h2d(P->st, hs.data(), B, s);
     }
 

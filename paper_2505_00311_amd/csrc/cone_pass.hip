@@ -65,8 +65,13 @@ struct OpDual {  // y^ = Proj_Y(y + sigma (h~ - 2 G~x^ + G~x)), acc: |dy|^2, <dy
         sigma = st->sigma;
     }
     __device__ bool skip() const { return st->halt != 0; }
+    // G~x^ at row i (finished here when the product left its last sums);
+    // load and store of a row run on the same thread
+    __device__ double gxh(int64_t i) const { return a.gt.active() ? a.gt.value(a.gxh, i) : a.gxh[i]; }
     __device__ double load(int64_t i) const {
-        return a.y[i] + sigma * (a.hs[i] - 2.0 * a.gxh[i] + a.gx[i]);
+        const double g = gxh(i);
+        if (a.gt.active()) a.gxh_out[i] = g;
+        return a.y[i] + sigma * (a.hs[i] - 2.0 * g + a.gx[i]);
     }
     __device__ double scale(int64_t i) const { return a.dy[i]; }
     __device__ double box(int64_t, double v) const { return v; }
@@ -75,7 +80,7 @@ struct OpDual {  // y^ = Proj_Y(y + sigma (h~ - 2 G~x^ + G~x)), acc: |dy|^2, <dy
         if (a.yh32) a.yh32[i] = (float)p;
         const double d = p - a.y[i];
         acc.s[0] += d * d;
-        acc.s[1] += d * (a.gxh[i] - a.gx[i]);
+        acc.s[1] += d * (gxh(i) - a.gx[i]);
     }
     __device__ void store_box(int64_t i, double v, double p, Acc &acc) const { store(i, v, p, acc); }
     __device__ double *scratch() const { return a.yh; }

@@ -12,7 +12,8 @@ namespace pdcs {
 // with N = 1 + attempts so far.  Reflection parameter (reading): grows by
 // beta_grow (capped at 1) while ||dz||_omega falls, else shrinks by beta_shrink.
 // Runs on all threads of one workgroup; the partials of both passes are
-// reduced in a fixed order, then thread 0 decides.
+// reduced in a fixed order, then thread 0 decides.  A halt takes effect in
+// the next attempt (halt_next, copied to halt by the Halpern step).
 __device__ void decide_body(DevState *__restrict__ st, const double *__restrict__ px, int64_t ntx,
                             const double *__restrict__ py, int64_t nty) {
     // four independent strided partial sums per thread keep four loads in
@@ -43,7 +44,7 @@ __device__ void decide_body(DevState *__restrict__ st, const double *__restrict_
     const double ebar = den > 0.0 ? (omega * nx2 + ny2 / omega) / den : INFINITY;
     if (ebar != ebar) {
         st->status = 3;
-        st->halt = 1;
+        st->halt_next = 1;
         st->skip_update = 1;
         return;
     }
@@ -81,17 +82,32 @@ __device__ void decide_body(DevState *__restrict__ st, const double *__restrict_
         st->n_iter = it + 1;
         st->kin = k + 1;
         st->skip_update = 0;
-        if ((k + 1) % st->check_every == 0 || it + 1 >= st->max_iter) st->halt = 1;
+        if ((k + 1) % st->check_every == 0 || it + 1 >= st->max_iter) st->halt_next = 1;
     } else {
         st->eta = enew;
         st->skip_update = 1;
         if (st->attempts_cur >= st->max_attempts) {
             st->status = 3;
-            st->halt = 1;
+            st->halt_next = 1;
         }
     }
     st->tau = st->eta / st->omega;
     st->sigma = st->eta * st->omega;
+}
+
+// Instance b's decision from the per-instance tile ranges (a halted instance
+// only marks its update skipped).
+__device__ __forceinline__ void decide_instance(DevState *st, int64_t b, const double *px,
+                                                const int64_t *tx, int64_t ntx, const double *py,
+                                                const int64_t *ty, int64_t nty) {
+    DevState *sb = st + b;
+    if (sb->halt) {
+        if (threadIdx.x == 0) sb->skip_update = 1;
+        return;
+    }
+    const int64_t x0 = tx ? tx[b] : 0, x1 = tx ? tx[b + 1] : ntx;
+    const int64_t y0 = ty ? ty[b] : 0, y1 = ty ? ty[b + 1] : nty;
+    decide_body(sb, px + x0 * kPartials, x1 - x0, py + y0 * kPartials, y1 - y0);
 }
 
 }  // namespace pdcs

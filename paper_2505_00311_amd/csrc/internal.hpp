@@ -119,7 +119,52 @@ struct SpmvPlan {
     int32_t *slab_perm = nullptr;      // [same]
     SlabBlock *slab_blk = nullptr;     // [n_slab_blocks]
     double *slab_part = nullptr;       // [n_slabs rows] per-slab row sums
+    int32_t *long_of = nullptr;        // [rows] index of a long row in long_rows, else -1
+                                       // (null when there is no long row)
 };
+
+// The finishing step of a sparse product (the slab sums of a row, or the chunk
+// sums of a long row), left to the kernel that consumes the product so that
+// the product costs one launch: value(y, i) is row i of the product, where y
+// is what the product's first kernel wrote.  The sums are formed in the order
+// of spmv's own finishing kernels (slab order, chunk order), so the results
+// are the same bits.
+struct ProductTail {
+    const double *part = nullptr;   // [n_slabs rows] slab sums, or null
+    int64_t rows = 0;
+    int n_slabs = 0;
+    const int32_t *long_of = nullptr;
+    const int64_t *long_chunk_ptr = nullptr;
+    const double *chunk_part = nullptr;
+    __host__ __device__ bool active() const { return n_slabs > 0 || long_of != nullptr; }
+#ifdef __HIPCC__
+    __device__ double value(const double *y, int64_t i) const {
+        if (long_of) {
+            const int32_t l = long_of[i];
+            if (l >= 0) {
+                double s = 0.0;
+                for (int64_t c = long_chunk_ptr[l]; c < long_chunk_ptr[l + 1]; ++c) s += chunk_part[c];
+                return s;
+            }
+        }
+        if (n_slabs == 0) return y[i];
+        double acc = part[i];
+        for (int k = 1; k < n_slabs; ++k) acc += part[k * rows + i];
+        return acc;
+    }
+#endif
+};
+
+inline ProductTail tail_of(const SpmvPlan &p, int64_t rows) {
+    ProductTail t;
+    t.part = p.n_slabs > 0 ? p.slab_part : nullptr;
+    t.rows = rows;
+    t.n_slabs = p.n_slabs;
+    t.long_of = p.n_long > 0 ? p.long_of : nullptr;
+    t.long_chunk_ptr = p.long_chunk_ptr;
+    t.chunk_part = p.chunk_part;
+    return t;
+}
 
 // Iteration state kept on the device, read and written by the step kernels.
 struct DevState {
@@ -130,6 +175,10 @@ struct DevState {
     double nx2, ny2, ip;              // reductions of the last attempt
     long long n_iter, kin, attempts_total, max_iter;
     int attempts_cur, halt, skip_update, status;
+    // the step decision sets halt_next; the Halpern step of the same attempt
+    // copies it to halt (the kernels of that attempt read a halt that does not
+    // change under them); the host writes both
+    int halt_next, pad_halt;
     int check_every, max_attempts, beta_mode, step_mode;
     double beta_const, beta_grow, beta_shrink, step_reduce_exp, step_grow_exp;
     long long log_cap;
@@ -173,6 +222,25 @@ void spmv(const Csr &A, const SpmvPlan &plan, const double *x, double *y, const 
 // FP32 values (A.v32) and FP32 x, FP64 products and sums
 void spmv32(const Csr &A, const SpmvPlan &plan, const float *x, double *y, const SpmvSkip &skip,
             hipStream_t s);
+// The step decision of each instance, run by extra workgroups of a product's
+// launch (see spmv_head): the partials of the primal and dual passes and
+// their per-instance tile ranges (null for one problem).
+struct DecideArgs {
+    DevState *st = nullptr;   // null: no decision in this launch
+    int64_t B = 0;
+    const double *px = nullptr, *py = nullptr;
+    const int64_t *tx = nullptr, *ty = nullptr;
+    int64_t ntx = 0, nty = 0;
+    int64_t nblk = 0;         // workgroups given to it (set by the launcher)
+};
+// The product's first kernel only; row i is then tail_of(plan, rows).value(y, i).
+// With dec.st set, the launch also takes the step decision (workgroups
+// [0, B rounded up to a multiple of 8), ahead of the product's, so the slab
+// workgroups keep their XCDs).
+void spmv_head(const Csr &A, const SpmvPlan &plan, const double *x, double *y,
+               const SpmvSkip &skip, hipStream_t s, const DecideArgs &dec = DecideArgs{});
+void spmv32_head(const Csr &A, const SpmvPlan &plan, const float *x, double *y,
+                 const SpmvSkip &skip, hipStream_t s, const DecideArgs &dec = DecideArgs{});
 void to_float(const double *in, float *out, int64_t n, hipStream_t s);
 int choose_lanes(double avg_row_nnz);
 
@@ -224,6 +292,10 @@ struct DualArgs {
     double *yh;
     const DevState *st;
     float *yh32 = nullptr;   // FP32 copy of y^ for the FP32 product (mixed form)
+    // when active, G~x^ is finished here from what spmv_head left in gxh, and
+    // written to gxh_out
+    ProductTail gt{};
+    double *gxh_out = nullptr;
 };
 struct CandArgs {  // projection of src / div onto the scaled set, into dst
     const double *src, *ls, *us, *d;
@@ -253,10 +325,6 @@ void pass_project(const ConePlan &p, bool dual, const ProjArgs &a, double *parti
                   hipStream_t s);
 
 // iterate.hip
-// One workgroup per instance b reduces the partials of its tiles ([tx[b],
-// tx[b+1]) and [ty[b], ty[b+1]); null ranges: all tiles, B = 1) and decides.
-void decide(DevState *st, int64_t B, const double *px, const int64_t *tx, int64_t ntx,
-            const double *py, const int64_t *ty, int64_t nty, hipStream_t s);
 struct HalpernArgs {
     double *x, *aty, *xsum;
     const double *xh, *atyh, *xa, *aty0;
@@ -265,6 +333,13 @@ struct HalpernArgs {
     int64_t n, m;
     const DevState *st;
     const int32_t *x_inst = nullptr, *y_inst = nullptr;   // batch: instance per entry
+    // when active, G~^T y^ is finished here from what spmv_head left in atyh
+    // (atyh itself is not updated)
+    ProductTail at{};
+    // when set, halt <- halt_next for these n_inst states (the decision ran in
+    // the same attempt's G~^T launch)
+    DevState *promote = nullptr;
+    int64_t n_inst = 0;
 };
 void halpern(const HalpernArgs &a, hipStream_t s);
 void reduce_kkt(int64_t B, const double *prow, const int64_t *ty, int64_t ntr, const double *pcol,

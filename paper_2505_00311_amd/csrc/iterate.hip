@@ -1,9 +1,10 @@
-// iterate.hip -- the scalar and elementwise steps of Algorithm 1 that sit
-// between the projection passes and the sparse products:
+// iterate.hip -- the elementwise steps of Algorithm 1 that sit between the
+// projection passes and the sparse products (the step decision runs inside the
+// launch of G~^T y^, see spmv.hip):
 //   halpern  : ReflectedHalpern (and the same affine map applied to the kept
 //              products G~x and G~^T y) fused with the weighted average;
 //   reduce_kkt, restart_copy, unscale: pieces of the periodic check.
-#include "decide_device.hpp"
+#include "device_common.hpp"
 
 namespace pdcs {
 
@@ -12,34 +13,11 @@ static unsigned grid_for(int64_t n) {
     return (unsigned)(g < 1 ? 1 : g);
 }
 
-// The step decision, one workgroup after the dual pass (a kernel boundary
-// orders the passes' partials before it; a fenced last-workgroup hand-off
-// would write back an XCD's L2 once per workgroup).
-__global__ __launch_bounds__(kBlock) void decide_kernel(DevState *st, const double *px,
-                                                        const int64_t *tx, int64_t ntx,
-                                                        const double *py, const int64_t *ty,
-                                                        int64_t nty) {
-    const int64_t b = blockIdx.x;
-    DevState *sb = st + b;
-    if (sb->halt) {
-        if (threadIdx.x == 0) sb->skip_update = 1;
-        return;
-    }
-    const int64_t x0 = tx ? tx[b] : 0, x1 = tx ? tx[b + 1] : ntx;
-    const int64_t y0 = ty ? ty[b] : 0, y1 = ty ? ty[b + 1] : nty;
-    decide_body(sb, px + x0 * kPartials, x1 - x0, py + y0 * kPartials, y1 - y0);
-}
-
-void decide(DevState *st, int64_t B, const double *px, const int64_t *tx, int64_t ntx,
-            const double *py, const int64_t *ty, int64_t nty, hipStream_t s) {
-    hipLaunchKernelGGL(decide_kernel, dim3((unsigned)B), dim3(kBlock), 0, s, st, px, tx, ntx, py,
-                       ty, nty);
-    PDCS_HIP(hipGetLastError());
-}
-
 // z^{k+1} = (k+1)/(k+2) ((1+beta) z^ - beta z^k) + z^0/(k+2) (Algorithm 1), the
 // same map on G~x and G~^T y, and sum += eta_used z^{k+1}.
 __global__ __launch_bounds__(kBlock) void halpern_kernel(HalpernArgs a) {
+    if (a.promote && blockIdx.x == 0)   // no thread of this launch reads halt
+        for (int64_t t = threadIdx.x; t < a.n_inst; t += kBlock) a.promote[t].halt = a.promote[t].halt_next;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= a.n + a.m) return;
     const DevState *st = a.st + (i < a.n ? inst_of(a.x_inst, i) : inst_of(a.y_inst, i - a.n));
@@ -49,7 +27,8 @@ __global__ __launch_bounds__(kBlock) void halpern_kernel(HalpernArgs a) {
         const double xn = ha * ((1.0 + beta) * a.xh[i] - beta * a.x[i]) + hb * a.xa[i];
         a.x[i] = xn;
         a.xsum[i] += w * xn;
-        a.aty[i] = ha * ((1.0 + beta) * a.atyh[i] - beta * a.aty[i]) + hb * a.aty0[i];
+        const double atyh = a.at.active() ? a.at.value(a.atyh, i) : a.atyh[i];
+        a.aty[i] = ha * ((1.0 + beta) * atyh - beta * a.aty[i]) + hb * a.aty0[i];
     } else {
         const int64_t j = i - a.n;
         const double yn = ha * ((1.0 + beta) * a.yh[j] - beta * a.y[j]) + hb * a.ya[j];

@@ -21,7 +21,7 @@
 // workgroup streams a row range of its slab like the CSR-stream kernel and
 // writes the slab's row sums; a second kernel adds a row's S slab sums in slab
 // order (a fixed order, so results repeat bit for bit from run to run).
-#include "device_common.hpp"
+#include "decide_device.hpp"
 
 namespace pdcs {
 
@@ -30,6 +30,18 @@ __device__ __forceinline__ bool row_skipped(const SpmvSkip &k, int64_t row) {
     if (k.flag == SkipNone) return false;
     const DevState &s = k.st[inst_of(k.row_inst, row)];
     return k.flag == SkipHalt ? s.halt != 0 : s.skip_update != 0;
+}
+
+// Workgroups [0, dec.nblk) of a product launch take the step decision (one
+// per instance, the rest idle); returns true for them, else shifts bid to the
+// product's own numbering.
+__device__ __forceinline__ bool decide_blocks(const DecideArgs &dec, int64_t &bid) {
+    if (bid >= dec.nblk) {
+        bid -= dec.nblk;
+        return false;
+    }
+    if (bid < dec.B) decide_instance(dec.st, bid, dec.px, dec.tx, dec.ntx, dec.py, dec.ty, dec.nty);
+    return true;
 }
 
 // One chunk of a long row: its sum goes to chunk_part[c]; a second kernel adds
@@ -64,14 +76,15 @@ __global__ __launch_bounds__(kBlock) void spmv_rows_kernel(int64_t rows, const i
                                                            const T *__restrict__ v,
                                                            const T *__restrict__ x,
                                                            double *__restrict__ y, SpmvPlan p,
-                                                           SpmvSkip skip) {
+                                                           SpmvSkip skip, DecideArgs dec) {
+    int64_t bid = blockIdx.x;
+    if (decide_blocks(dec, bid)) return;
     if (!skip.row_inst && row_skipped(skip, 0)) return;   // one problem: one flag
-    if ((int64_t)blockIdx.x < p.n_chunks) {
-        if (!row_skipped(skip, p.long_rows[p.chunk_row[blockIdx.x]]))
-            long_chunk(blockIdx.x, rp, ci, v, x, p);
+    if (bid < p.n_chunks) {
+        if (!row_skipped(skip, p.long_rows[p.chunk_row[bid]])) long_chunk(bid, rp, ci, v, x, p);
         return;
     }
-    const int64_t gid = ((int64_t)blockIdx.x - p.n_chunks) * kBlock + threadIdx.x;
+    const int64_t gid = (bid - p.n_chunks) * kBlock + threadIdx.x;
     const int64_t row = gid / L;
     const int lane = (int)(gid % L);
     if (row >= rows) return;           // uniform within the L-lane group
@@ -149,14 +162,15 @@ __global__ __launch_bounds__(kBlock) void spmv_stream_kernel(const int64_t *__re
                                                              const T *__restrict__ v,
                                                              const T *__restrict__ x,
                                                              double *__restrict__ y, SpmvPlan p,
-                                                             SpmvSkip skip) {
+                                                             SpmvSkip skip, DecideArgs dec) {
+    int64_t bid = blockIdx.x;
+    if (decide_blocks(dec, bid)) return;
     if (!skip.row_inst && row_skipped(skip, 0)) return;   // one problem: one flag
-    if ((int64_t)blockIdx.x < p.n_chunks) {
-        if (!row_skipped(skip, p.long_rows[p.chunk_row[blockIdx.x]]))
-            long_chunk(blockIdx.x, rp, ci, v, x, p);
+    if (bid < p.n_chunks) {
+        if (!row_skipped(skip, p.long_rows[p.chunk_row[bid]])) long_chunk(bid, rp, ci, v, x, p);
         return;
     }
-    const int64_t bb = (int64_t)blockIdx.x - p.n_chunks;
+    const int64_t bb = bid - p.n_chunks;
     const int64_t r0 = p.sblock[2 * bb], r1 = p.sblock[2 * bb + 1];
     // a batch: skip the workgroup when all its rows belong to one flagged
     // instance (rows of a flagged instance are otherwise computed and unused)
@@ -177,10 +191,10 @@ int choose_lanes(double avg) {
 
 template <int L, class T>
 static void launch_rows(const Csr &A, const SpmvPlan &p, const T *v, const T *x, double *y,
-                        const SpmvSkip &skip, hipStream_t s) {
-    const int64_t blocks = (A.rows * L + kBlock - 1) / kBlock + p.n_chunks;
+                        const SpmvSkip &skip, const DecideArgs &dec, hipStream_t s) {
+    const int64_t blocks = dec.nblk + (A.rows * L + kBlock - 1) / kBlock + p.n_chunks;
     hipLaunchKernelGGL((spmv_rows_kernel<L, T>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A.rows,
-                       A.rp, A.ci, v, x, y, p, skip);
+                       A.rp, A.ci, v, x, y, p, skip, dec);
 }
 
 // Column-slab blocks [0, n_slab_blocks), then the long-row chunks.  A block
@@ -193,14 +207,16 @@ __global__ __launch_bounds__(kBlock) void spmv_slab_kernel(int64_t rows,
                                                            const T *__restrict__ v,
                                                            const T *__restrict__ sv,
                                                            const T *__restrict__ x, SpmvPlan p,
-                                                           SpmvSkip skip) {
+                                                           SpmvSkip skip, DecideArgs dec) {
+    int64_t bid = blockIdx.x;
+    if (decide_blocks(dec, bid)) return;
     if (!skip.row_inst && row_skipped(skip, 0)) return;   // one problem: one flag
-    if ((int64_t)blockIdx.x >= p.n_slab_blocks) {
-        const int64_t c = (int64_t)blockIdx.x - p.n_slab_blocks;
+    if (bid >= p.n_slab_blocks) {
+        const int64_t c = bid - p.n_slab_blocks;
         if (!row_skipped(skip, p.long_rows[p.chunk_row[c]])) long_chunk(c, rp, ci, v, x, p);
         return;
     }
-    const SlabBlock d = p.slab_blk[blockIdx.x];
+    const SlabBlock d = p.slab_blk[bid];
     if (d.r1 <= d.r0) return;   // padding that keeps the slab-to-XCD assignment
     if (skip.row_inst && inst_of(skip.row_inst, d.r0) == inst_of(skip.row_inst, d.r1 - 1) &&
         row_skipped(skip, d.r0))
@@ -246,16 +262,31 @@ void slab_values(const Csr &A, const SpmvPlan &p, hipStream_t s) {
     PDCS_HIP(hipGetLastError());
 }
 
+// finish = false: the first kernel only (see ProductTail).  dec_in.st set:
+// the launch also takes the step decision.
 template <class T>
 static void spmv_impl(const Csr &A, const SpmvPlan &p, const T *v, const T *sv, const T *x,
-                      double *y, const SpmvSkip &skip, hipStream_t s) {
-    if (A.rows == 0) return;
+                      double *y, const SpmvSkip &skip, hipStream_t s, bool finish,
+                      const DecideArgs &dec_in = DecideArgs{}) {
+    DecideArgs dec = dec_in;
+    dec.nblk = dec.st ? (dec.B + kXcds - 1) / kXcds * kXcds : 0;
+    if (A.rows == 0) {   // no product: the decision still runs
+        if (dec.nblk > 0)
+            hipLaunchKernelGGL((spmv_stream_kernel<T>), dim3((unsigned)dec.nblk), dim3(kBlock), 0, s,
+                               A.rp, A.ci, v, x, y, p, skip, dec);
+        PDCS_HIP(hipGetLastError());
+        return;
+    }
     if (p.n_slabs > 0) {
         if (!sv) throw_hip(hipErrorInvalidValue, "column-slab plan without slab values", __FILE__, __LINE__);
-        const int64_t blocks = p.n_slab_blocks + p.n_chunks;
+        const int64_t blocks = dec.nblk + p.n_slab_blocks + p.n_chunks;
         if (blocks > 0)
             hipLaunchKernelGGL((spmv_slab_kernel<T>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                               A.rows, A.rp, A.ci, v, sv, x, p, skip);
+                               A.rows, A.rp, A.ci, v, sv, x, p, skip, dec);
+        if (!finish) {
+            PDCS_HIP(hipGetLastError());
+            return;
+        }
         const dim3 g((unsigned)((A.rows + kBlock - 1) / kBlock));
         switch (p.n_slabs) {
         case 1: hipLaunchKernelGGL(spmv_slab_sum<1>, g, dim3(kBlock), 0, s, A.rows, p.slab_part, y, skip); break;
@@ -264,21 +295,21 @@ static void spmv_impl(const Csr &A, const SpmvPlan &p, const T *v, const T *sv, 
         default: hipLaunchKernelGGL(spmv_slab_sum<8>, g, dim3(kBlock), 0, s, A.rows, p.slab_part, y, skip); break;
         }
     } else if (p.stream) {
-        const int64_t blocks = p.n_sblocks + p.n_chunks;
+        const int64_t blocks = dec.nblk + p.n_sblocks + p.n_chunks;
         if (blocks > 0)
             hipLaunchKernelGGL((spmv_stream_kernel<T>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                               A.rp, A.ci, v, x, y, p, skip);
+                               A.rp, A.ci, v, x, y, p, skip, dec);
     } else {
         switch (p.lanes) {
-        case 2: launch_rows<2>(A, p, v, x, y, skip, s); break;
-        case 4: launch_rows<4>(A, p, v, x, y, skip, s); break;
-        case 8: launch_rows<8>(A, p, v, x, y, skip, s); break;
-        case 16: launch_rows<16>(A, p, v, x, y, skip, s); break;
-        case 32: launch_rows<32>(A, p, v, x, y, skip, s); break;
-        default: launch_rows<64>(A, p, v, x, y, skip, s); break;
+        case 2: launch_rows<2>(A, p, v, x, y, skip, dec, s); break;
+        case 4: launch_rows<4>(A, p, v, x, y, skip, dec, s); break;
+        case 8: launch_rows<8>(A, p, v, x, y, skip, dec, s); break;
+        case 16: launch_rows<16>(A, p, v, x, y, skip, dec, s); break;
+        case 32: launch_rows<32>(A, p, v, x, y, skip, dec, s); break;
+        default: launch_rows<64>(A, p, v, x, y, skip, dec, s); break;
         }
     }
-    if (p.n_long > 0)
+    if (p.n_long > 0 && finish)
         hipLaunchKernelGGL(spmv_chunks_finish, dim3((unsigned)((p.n_long + 255) / 256)), dim3(256),
                            0, s, p, y, skip);
     PDCS_HIP(hipGetLastError());
@@ -286,13 +317,24 @@ static void spmv_impl(const Csr &A, const SpmvPlan &p, const T *v, const T *sv, 
 
 void spmv(const Csr &A, const SpmvPlan &p, const double *x, double *y, const SpmvSkip &skip,
           hipStream_t s) {
-    spmv_impl<double>(A, p, A.v, A.sv, x, y, skip, s);
+    spmv_impl<double>(A, p, A.v, A.sv, x, y, skip, s, true);
+}
+
+void spmv_head(const Csr &A, const SpmvPlan &p, const double *x, double *y, const SpmvSkip &skip,
+               hipStream_t s, const DecideArgs &dec) {
+    spmv_impl<double>(A, p, A.v, A.sv, x, y, skip, s, false, dec);
 }
 
 void spmv32(const Csr &A, const SpmvPlan &p, const float *x, double *y, const SpmvSkip &skip,
             hipStream_t s) {
     if (A.rows > 0 && !A.v32) throw_hip(hipErrorInvalidValue, "spmv32 without FP32 values", __FILE__, __LINE__);
-    spmv_impl<float>(A, p, A.v32, A.sv32, x, y, skip, s);
+    spmv_impl<float>(A, p, A.v32, A.sv32, x, y, skip, s, true);
+}
+
+void spmv32_head(const Csr &A, const SpmvPlan &p, const float *x, double *y, const SpmvSkip &skip,
+                 hipStream_t s, const DecideArgs &dec) {
+    if (A.rows > 0 && !A.v32) throw_hip(hipErrorInvalidValue, "spmv32 without FP32 values", __FILE__, __LINE__);
+    spmv_impl<float>(A, p, A.v32, A.sv32, x, y, skip, s, false, dec);
 }
 
 }  // namespace pdcs
