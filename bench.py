@@ -86,6 +86,22 @@ def counter_traffic(kernel):
     return rec["kernels"][kernel]["bytes_per_launch"]
 
 
+def layout_name(code):
+    if code <= -10:
+        return f"{-10 - code} column slabs (spmv_slab_kernel)"
+    if code == -1:
+        return "CSR-stream (spmv_stream_kernel)"
+    return f"row-split, {code} lanes per row (spmv_rows_kernel)"
+
+
+def product_name(kernel, layouts):
+    g, gt = layouts
+    if kernel == "spmv_g":
+        return f"SpMV G~ x^: {layout_name(g)}; slab sums finished in the dual pass"
+    return (f"SpMV G~^T y^: {layout_name(gt)}; step decision in the same launch, "
+            "slab and long-row chunk sums finished in the Halpern step")
+
+
 def batched_form(pdcs, instances, torch, count):
     """Time to 1e-6 of `count` independent planted LP/SOCP instances (n uniform
     in 1e3..2e4, m = n/2, 0.5% density, 20% of the variables in SOC blocks of
@@ -274,8 +290,7 @@ def main():
     ach = b_dom / t_dom / 1e9
     log("in-solve kernel averages (us): " + ", ".join(f"{k} {v:.1f}" for k, v in kus.items())
         + f"; event-timed solve {rk['iterations'] / rk['solve_s']:.1f} iter/s")
-    dom_name = {"spmv_g": "SpMV G~ x^ (spmv_rows_kernel, row-split vector CSR)",
-                "spmv_gt": "SpMV G~^T y^ (spmv_stream_kernel + chunked long rows)"}[dom]
+    dom_name = product_name(dom, prob.layout())
 
     out = {
         "metric": METRIC,
