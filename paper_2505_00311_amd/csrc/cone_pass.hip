@@ -24,6 +24,95 @@ __device__ __forceinline__ int dual_kind(int k) {
     }
 }
 
+// Projection of one elementwise entry of kind k (box: [lo, hi]).
+__device__ __forceinline__ double elem_proj(int k, double v, double lo, double hi) {
+    switch (k) {
+    case kTileBox: return fmin(fmax(v, lo), hi);
+    case kTileZero: return 0.0;
+    case kTileFree: return v;
+    default: return v > 0.0 ? v : 0.0;
+    }
+}
+
+// Elementwise tiles of the two step passes.  A thread's entries are taken
+// kElemRound at a time with all of their loads issued first (clamped indices;
+// the arrays are restrict-qualified so that the compiler may move loads ahead
+// of the previous entries' stores), then projected and stored in entry order,
+// so the partial sums are those of the one-entry-at-a-time loop.
+constexpr int kElemRound = 4;
+
+__device__ __forceinline__ void primal_elem(int kind, int64_t start, int64_t end, double tau,
+                                            const double *__restrict__ x,
+                                            const double *__restrict__ cs,
+                                            const double *__restrict__ aty,
+                                            const double *__restrict__ ls,
+                                            const double *__restrict__ us,
+                                            double *__restrict__ xh, float *__restrict__ xh32,
+                                            Acc &acc) {
+    constexpr int U = kElemRound;
+    const bool box = kind == kTileBox;
+    for (int64_t j0 = start + threadIdx.x; j0 < end; j0 += U * kBlock) {
+        double xv[U], cv[U], av[U], lv[U], uv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t j = min(j0 + (int64_t)u * kBlock, end - 1);
+            xv[u] = x[j], cv[u] = cs[j], av[u] = aty[j];
+            lv[u] = box ? ls[j] : 0.0;
+            uv[u] = box ? us[j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t j = j0 + (int64_t)u * kBlock;
+            if (j >= end) break;
+            const double p = elem_proj(kind, xv[u] - tau * (cv[u] - av[u]), lv[u], uv[u]);
+            xh[j] = p;
+            if (xh32) xh32[j] = (float)p;
+            const double d = p - xv[u];
+            acc.s[0] += d * d;
+        }
+    }
+}
+
+__device__ __forceinline__ void dual_elem(int kind, int64_t start, int64_t end, double sigma,
+                                          const ProductTail &gt, const double *__restrict__ y,
+                                          const double *__restrict__ gxh_in,
+                                          const double *__restrict__ gx,
+                                          const double *__restrict__ hs,
+                                          double *__restrict__ yh, float *__restrict__ yh32,
+                                          double *__restrict__ gxh_out, Acc &acc) {
+    constexpr int U = kElemRound;
+    const bool tail = gt.active();
+    for (int64_t i0 = start + threadIdx.x; i0 < end; i0 += U * kBlock) {
+        double yv[U], gv[U], xv[U], hv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = min(i0 + (int64_t)u * kBlock, end - 1);
+            yv[u] = y[i], xv[u] = gx[i], hv[u] = hs[i];
+            gv[u] = tail ? gt.value(gxh_in, i) : gxh_in[i];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + (int64_t)u * kBlock;
+            if (i >= end) break;
+            const double p = elem_proj(kind, yv[u] + sigma * (hv[u] - 2.0 * gv[u] + xv[u]), 0.0, 0.0);
+            if (tail) gxh_out[i] = gv[u];
+            yh[i] = p;
+            if (yh32) yh32[i] = (float)p;
+            const double d = p - yv[u];
+            acc.s[0] += d * d;
+            acc.s[1] += d * (gv[u] - xv[u]);
+        }
+    }
+}
+
+// What a load hands to the store of the same entry: the value before the
+// projection (v) and, for the step passes, the inputs the store needs again
+// (so the store does not re-read them after the writes of earlier entries,
+// which the compiler cannot reorder and each of which waits a memory latency).
+struct Ld {
+    double v, u, w, z;
+};
+
 // ---------------------------------------------------------------- ops
 // An op supplies: skip(), load(j) -> value before projection, scale(j) ->
 // diagonal of D (1 when unscaled), box(j, v) -> projection of a box entry,
@@ -53,6 +142,22 @@ struct OpPrimal {  // x^ = Proj_X(x - tau (c~ - G~^T y)), acc.s0 += (x^ - x)^2
     }
     __device__ void store_box(int64_t j, double v, double p, Acc &acc) const { store(j, v, p, acc); }
     __device__ double *scratch() const { return a.xh; }
+    // kCarry: elem() is the pipelined elementwise tile, load_ld/store_ld carry
+    // x from the load to the store
+    static constexpr bool kCarry = true;
+    __device__ void elem(int kind, int64_t start, int64_t end, Acc &acc) const {
+        primal_elem(kind, start, end, tau, a.x, a.cs, a.aty, a.ls, a.us, a.xh, a.xh32, acc);
+    }
+    __device__ Ld load_ld(int64_t j) const {
+        const double x = a.x[j];
+        return Ld{x - tau * (a.cs[j] - a.aty[j]), x, 0.0, 0.0};
+    }
+    __device__ void store_ld(int64_t j, const Ld &l, double p, Acc &acc) const {
+        a.xh[j] = p;
+        if (a.xh32) a.xh32[j] = (float)p;
+        const double d = p - l.u;
+        acc.s[0] += d * d;
+    }
 };
 
 struct OpDual {  // y^ = Proj_Y(y + sigma (h~ - 2 G~x^ + G~x)), acc: |dy|^2, <dy, G~dx>
@@ -84,10 +189,28 @@ struct OpDual {  // y^ = Proj_Y(y + sigma (h~ - 2 G~x^ + G~x)), acc: |dy|^2, <dy
     }
     __device__ void store_box(int64_t i, double v, double p, Acc &acc) const { store(i, v, p, acc); }
     __device__ double *scratch() const { return a.yh; }
+    static constexpr bool kCarry = true;
+    __device__ void elem(int kind, int64_t start, int64_t end, Acc &acc) const {
+        dual_elem(kind, start, end, sigma, a.gt, a.y, a.gxh, a.gx, a.hs, a.yh, a.yh32, a.gxh_out, acc);
+    }
+    // carries y, G~x^ and G~x; G~x^ is stored (when finished here) with y^
+    __device__ Ld load_ld(int64_t i) const {
+        const double y = a.y[i], g = gxh(i), gx = a.gx[i];
+        return Ld{y + sigma * (a.hs[i] - 2.0 * g + gx), y, g, gx};
+    }
+    __device__ void store_ld(int64_t i, const Ld &l, double p, Acc &acc) const {
+        if (a.gt.active()) a.gxh_out[i] = l.w;
+        a.yh[i] = p;
+        if (a.yh32) a.yh32[i] = (float)p;
+        const double d = p - l.u;
+        acc.s[0] += d * d;
+        acc.s[1] += d * (l.w - l.z);
+    }
 };
 
 struct OpCand {  // dst = Proj(src / div), div = 1 or the sum of step weights
     static constexpr bool kWarm = false;
+    static constexpr bool kCarry = false;
     CandArgs a;
     double div;
     __device__ void begin(int inst) { div = a.use_avg ? a.st[inst].eta_sum : 1.0; }
@@ -103,6 +226,7 @@ struct OpCand {  // dst = Proj(src / div), div = 1 or the sum of step weights
 // rows of eq. (PDCS_terminate_tolerance): r = G x - h (unscaled), P(r) onto K_d^*
 struct OpKktRows {
     static constexpr bool kWarm = false;
+    static constexpr bool kCarry = false;
     KktRowsArgs a;
     __device__ void begin(int) {}
     __device__ bool skip() const { return false; }
@@ -125,6 +249,7 @@ struct OpKktRows {
 // of eq. (defn_Lambda1), cone entries against K_p^*
 struct OpKktCols {
     static constexpr bool kWarm = false;
+    static constexpr bool kCarry = false;
     KktColsArgs a;
     __device__ void begin(int) {}
     __device__ bool skip() const { return false; }
@@ -155,6 +280,7 @@ struct OpKktCols {
 
 struct OpProject {
     static constexpr bool kWarm = false;
+    static constexpr bool kCarry = false;
     ProjArgs a;
     __device__ void begin(int) {}
     __device__ bool skip() const { return false; }
@@ -165,6 +291,21 @@ struct OpProject {
     __device__ void store_box(int64_t j, double v, double p, Acc &acc) const { store(j, v, p, acc); }
     __device__ double *scratch() const { return a.v; }
 };
+
+template <class Op>
+__device__ __forceinline__ Ld load_ld(const Op &op, int64_t j) {
+    if constexpr (Op::kCarry)
+        return op.load_ld(j);
+    else
+        return Ld{op.load(j), 0.0, 0.0, 0.0};
+}
+template <class Op>
+__device__ __forceinline__ void store_ld(const Op &op, int64_t j, const Ld &l, double p, Acc &acc) {
+    if constexpr (Op::kCarry)
+        op.store_ld(j, l, p, acc);
+    else
+        op.store(j, l.v, p, acc);
+}
 
 // ------------------------------------------------- workgroup-per-SOC block
 template <class Op>
@@ -280,20 +421,30 @@ __device__ __forceinline__ void soc_tile(Op &op, const Tile &tl, const int64_t *
     const int64_t b = tl.start + gi;
     const int64_t off = soc_off[b];
     const int dim = soc_dim[b];
+    const double guess = soc_root ? soc_root[b] : __builtin_nan("");
+    // loads at clamped indices, unconditional, so none waits behind a branch
+    Ld l[R];
     double v[R], d[R], p[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int e = g + LPB * r;
-        v[r] = e < dim ? op.load(off + e) : 0.0;
-        d[r] = e < dim ? op.scale(off + e) : 1.0;
+        const int64_t j = off + (e < dim ? e : dim - 1);
+        l[r] = load_ld(op, j);
+        d[r] = op.scale(j);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool on = g + LPB * r < dim;
+        v[r] = on ? l[r].v : 0.0;
+        d[r] = on ? d[r] : 1.0;
     }
     double s_new;
-    soc_project_group<LPB, R>(dim, v, d, p, soc_root ? soc_root[b] : __builtin_nan(""), s_new);
+    soc_project_group<LPB, R>(dim, v, d, p, guess, s_new);
     if (soc_root && g == 0 && s_new == s_new) soc_root[b] = s_new;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int e = g + LPB * r;
-        if (e < dim) op.store(off + e, v[r], p[r], acc);
+        if (e < dim) store_ld(op, off + e, l[r], p[r], acc);
     }
 }
 
@@ -314,24 +465,40 @@ __global__ __launch_bounds__(kBlock) void cone_pass_kernel(Op op, const Tile *__
     Acc acc;
     switch (kind) {
     case kTileBox:
+        if constexpr (Op::kCarry) {
+            op.elem(kind, tl.start, tl.start + tl.count, acc);
+            break;
+        }
         for (int64_t j = tl.start + tid; j < tl.start + tl.count; j += kBlock) {
             const double v = op.load(j);
             op.store_box(j, v, op.box(j, v), acc);
         }
         break;
     case kTileZero:
+        if constexpr (Op::kCarry) {
+            op.elem(kind, tl.start, tl.start + tl.count, acc);
+            break;
+        }
         for (int64_t j = tl.start + tid; j < tl.start + tl.count; j += kBlock) {
             const double v = op.load(j);
             op.store(j, v, 0.0, acc);
         }
         break;
     case kTileFree:
+        if constexpr (Op::kCarry) {
+            op.elem(kind, tl.start, tl.start + tl.count, acc);
+            break;
+        }
         for (int64_t j = tl.start + tid; j < tl.start + tl.count; j += kBlock) {
             const double v = op.load(j);
             op.store(j, v, v, acc);
         }
         break;
     case kTileNonneg:
+        if constexpr (Op::kCarry) {
+            op.elem(kind, tl.start, tl.start + tl.count, acc);
+            break;
+        }
         for (int64_t j = tl.start + tid; j < tl.start + tl.count; j += kBlock) {
             const double v = op.load(j);
             op.store(j, v, v > 0.0 ? v : 0.0, acc);
@@ -351,7 +518,8 @@ __global__ __launch_bounds__(kBlock) void cone_pass_kernel(Op op, const Tile *__
     case kTileExpDual:
         if (tid < tl.count) {
             const int64_t off = exp_off[tl.start + tid];
-            const double r0 = op.load(off), s0 = op.load(off + 1), t0 = op.load(off + 2);
+            const Ld lr = load_ld(op, off), ls = load_ld(op, off + 1), lt = load_ld(op, off + 2);
+            const double r0 = lr.v, s0 = ls.v, t0 = lt.v;
             const double dr = op.scale(off), ds = op.scale(off + 1), dt = op.scale(off + 2);
             double pr, ps, pt, rho;
             const double guess = exp_root ? exp_root[tl.start + tid] : __builtin_nan("");
@@ -360,9 +528,9 @@ __global__ __launch_bounds__(kBlock) void cone_pass_kernel(Op op, const Tile *__
             else
                 exp_dual_project(r0, s0, t0, dr, ds, dt, pr, ps, pt, guess, rho);
             if (exp_root && rho == rho) exp_root[tl.start + tid] = rho;
-            op.store(off, r0, pr, acc);
-            op.store(off + 1, s0, ps, acc);
-            op.store(off + 2, t0, pt, acc);
+            store_ld(op, off, lr, pr, acc);
+            store_ld(op, off + 1, ls, ps, acc);
+            store_ld(op, off + 2, lt, pt, acc);
         }
         break;
     }
