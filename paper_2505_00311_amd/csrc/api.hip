@@ -301,13 +301,14 @@ static SpmvPlan build_spmv_plan(DevMem &mem, const std::vector<int64_t> &rp, hip
     if (P.stream || slabs) P.long_thr = std::min<int64_t>(P.long_thr, kStreamNnz);
     // rows longer than long_thr: chunks of kLongChunk entries
     std::vector<int32_t> lr, crow;
-    std::vector<int64_t> cptr{0}, cbeg;
+    std::vector<int64_t> cptr{0}, cbeg, cend;
     for (int64_t i = 0; i < rows; ++i) {
         const int64_t len = rp[i + 1] - rp[i];
         if (len <= P.long_thr) continue;
         const int32_t li = (int32_t)lr.size();
         lr.push_back((int32_t)i);
-        for (int64_t b = rp[i]; b < rp[i + 1]; b += kLongChunk) crow.push_back(li), cbeg.push_back(b);
+        for (int64_t b = rp[i]; b < rp[i + 1]; b += kLongChunk)
+            crow.push_back(li), cbeg.push_back(b), cend.push_back(std::min(b + kLongChunk, rp[i + 1]));
         cptr.push_back((int64_t)cbeg.size());
     }
     // CSR-stream row ranges (start, end) of consecutive short rows whose entries
@@ -338,6 +339,7 @@ static SpmvPlan build_spmv_plan(DevMem &mem, const std::vector<int64_t> &rp, hip
     P.long_chunk_ptr = mem.alloc<int64_t>(P.n_long + 1);
     P.chunk_row = mem.alloc<int32_t>(P.n_chunks);
     P.chunk_begin = mem.alloc<int64_t>(P.n_chunks);
+    P.chunk_end = mem.alloc<int64_t>(P.n_chunks);
     P.chunk_part = mem.alloc<double>(P.n_chunks);
     P.sblock = mem.alloc<int64_t>((int64_t)sb.size());
     if (P.n_long > 0) {
@@ -350,6 +352,7 @@ static SpmvPlan build_spmv_plan(DevMem &mem, const std::vector<int64_t> &rp, hip
     h2d(P.long_chunk_ptr, cptr.data(), P.n_long + 1, s);
     h2d(P.chunk_row, crow.data(), P.n_chunks, s);
     h2d(P.chunk_begin, cbeg.data(), P.n_chunks, s);
+    h2d(P.chunk_end, cend.data(), P.n_chunks, s);
     h2d(P.sblock, sb.data(), (int64_t)sb.size(), s);
     PDCS_HIP(hipStreamSynchronize(s));
     return P;

@@ -104,6 +104,7 @@ struct SpmvPlan {
     int64_t *long_chunk_ptr = nullptr; // [n_long+1]
     int32_t *chunk_row = nullptr;      // [n_chunks] long-row index
     int64_t *chunk_begin = nullptr;    // [n_chunks] first nnz
+    int64_t *chunk_end = nullptr;      // [n_chunks] one past the last nnz
     double *chunk_part = nullptr;      // [n_chunks]
     // Column-slab form (n_slabs > 0): the columns are cut into n_slabs ranges
     // of equal entry counts and each slab is a CSR matrix over all rows, its

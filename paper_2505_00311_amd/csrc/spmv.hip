@@ -44,18 +44,41 @@ __device__ __forceinline__ bool decide_blocks(const DecideArgs &dec, int64_t &bi
     return true;
 }
 
-// One chunk of a long row: its sum goes to chunk_part[c]; a second kernel adds
-// each row's chunk sums in chunk order (a kernel boundary orders the writes).
+// Whether chunk c's row is skipped; a single problem's one flag was checked at
+// the kernel's start, so only a batch looks the row up.
+__device__ __forceinline__ bool chunk_skipped(const SpmvSkip &k, const SpmvPlan &p, int64_t c) {
+    return k.row_inst && row_skipped(k, p.long_rows[p.chunk_row[c]]);
+}
+
+// One chunk of a long row: its sum goes to chunk_part[c]; a second kernel (or
+// the product's consumer) adds each row's chunk sums in chunk order.  Each
+// thread takes its entries kChunkRound at a time with all loads issued first
+// and adds them in entry order, then the workgroup sum is formed in a fixed
+// order.
+constexpr int kChunkRound = 8;
 template <class T>
-__device__ __forceinline__ void long_chunk(int64_t c, const int64_t *__restrict__ rp,
+__device__ __forceinline__ void long_chunk(int64_t c, const int64_t *__restrict__,
                                            const int32_t *__restrict__ ci,
                                            const T *__restrict__ v,
                                            const T *__restrict__ x, const SpmvPlan &p) {
-    const int64_t row = p.long_rows[p.chunk_row[c]];
-    const int64_t b = p.chunk_begin[c];
-    const int64_t e = min(b + kLongChunk, rp[row + 1]);
+    constexpr int U = kChunkRound;
+    const int64_t b = p.chunk_begin[c], e = p.chunk_end[c];
     double acc[1] = {0.0};
-    for (int64_t k = b + threadIdx.x; k < e; k += kBlock) acc[0] += (double)v[k] * (double)x[ci[k]];
+    for (int64_t k0 = b + threadIdx.x; k0 < e; k0 += U * kBlock) {
+        int32_t cc[U];
+        T w[U], xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = min(k0 + (int64_t)u * kBlock, e - 1);
+            cc[u] = ci[k];
+            w[u] = v[k];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = x[cc[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + (int64_t)u * kBlock < e) acc[0] += (double)w[u] * (double)xv[u];
+    }
     block_sum_all<1>(acc);
     if (threadIdx.x == 0) p.chunk_part[c] = acc[0];
 }
@@ -81,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void spmv_rows_kernel(int64_t rows, const i
     if (decide_blocks(dec, bid)) return;
     if (!skip.row_inst && row_skipped(skip, 0)) return;   // one problem: one flag
     if (bid < p.n_chunks) {
-        if (!row_skipped(skip, p.long_rows[p.chunk_row[bid]])) long_chunk(bid, rp, ci, v, x, p);
+        if (!chunk_skipped(skip, p, bid)) long_chunk(bid, rp, ci, v, x, p);
         return;
     }
     const int64_t gid = (bid - p.n_chunks) * kBlock + threadIdx.x;
@@ -167,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void spmv_stream_kernel(const int64_t *__re
     if (decide_blocks(dec, bid)) return;
     if (!skip.row_inst && row_skipped(skip, 0)) return;   // one problem: one flag
     if (bid < p.n_chunks) {
-        if (!row_skipped(skip, p.long_rows[p.chunk_row[bid]])) long_chunk(bid, rp, ci, v, x, p);
+        if (!chunk_skipped(skip, p, bid)) long_chunk(bid, rp, ci, v, x, p);
         return;
     }
     const int64_t bb = bid - p.n_chunks;
@@ -213,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void spmv_slab_kernel(int64_t rows,
     if (!skip.row_inst && row_skipped(skip, 0)) return;   // one problem: one flag
     if (bid >= p.n_slab_blocks) {
         const int64_t c = bid - p.n_slab_blocks;
-        if (!row_skipped(skip, p.long_rows[p.chunk_row[c]])) long_chunk(c, rp, ci, v, x, p);
+        if (!chunk_skipped(skip, p, c)) long_chunk(c, rp, ci, v, x, p);
         return;
     }
     const SlabBlock d = p.slab_blk[bid];
