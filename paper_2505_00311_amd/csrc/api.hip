@@ -192,13 +192,16 @@ struct SlabSource {
     const std::vector<int64_t> *col_cum = nullptr;
 };
 
-// Column slabs of a plan whose long rows (and their chunks) are set: slab k
-// takes the columns [cb[k], cb[k+1]) that hold about nnz k/S .. nnz (k+1)/S
-// entries; each slab's entries of the short rows are kept in row order (and in
-// CSR order within a row), and cut into blocks of at most kStreamNnz entries
-// and kSlabRows rows.  Block i of the launch runs on XCD i mod kXcds; XCDs
-// k g .. k g + g - 1 (g = kXcds / S) take the blocks of slab k, padded with
-// empty blocks so that every slab keeps its XCDs.
+// Column slabs: slab k takes the columns [cb[k], cb[k+1]) that hold about
+// nnz k/S .. nnz (k+1)/S entries.  Each slab's arrays hold first the entries
+// of its short rows (in row order, CSR order within a row), cut into streamed
+// blocks of at most kStreamNnz entries and kStreamRows rows, then the slab's
+// entries of the long rows (rows of more than long_thr entries), row after
+// row, cut into chunks of at most kLongChunk entries.  A long row's chunks are
+// listed slab by slab, and its sum adds them in that order.  Block i of the
+// launch runs on XCD i mod kXcds; XCDs k g .. k g + g - 1 (g = kXcds / S)
+// take the blocks of slab k (its chunks first: they are the longest), padded
+// with empty blocks so that every slab keeps its XCDs.
 static void add_slabs(DevMem &mem, SpmvPlan &P, const std::vector<int64_t> &rp,
                       const SlabSource &src, int S, hipStream_t s) {
     if (!src.ci || !src.col_cum) fail(PDCS_ERR_NOT_SUPPORTED, "column-slab plan without its structure");
@@ -219,33 +222,74 @@ static void add_slabs(DevMem &mem, SpmvPlan &P, const std::vector<int64_t> &rp,
     for (int k = 0; k < S; ++k)
         for (int64_t j = cb[k]; j < cb[k + 1]; ++j) slab_of[j] = (int8_t)k;
     const int64_t R1 = rows + 1;
-    std::vector<int32_t> lrp((size_t)(S * R1), 0);
     auto is_long = [&](int64_t r) { return rp[r + 1] - rp[r] > P.long_thr; };
-    for (int64_t r = 0; r < rows; ++r) {
-        if (is_long(r)) continue;
-        for (int64_t e = rp[r]; e < rp[r + 1]; ++e) ++lrp[slab_of[ci[e]] * R1 + r + 1];
+    std::vector<int32_t> lr;   // long rows
+    for (int64_t r = 0; r < rows; ++r)
+        if (is_long(r)) lr.push_back((int32_t)r);
+    const int64_t NL = (int64_t)lr.size();
+    // entries per (slab, short row) and per (slab, long row)
+    std::vector<int32_t> lrp((size_t)(S * R1), 0);
+    std::vector<int64_t> lcnt((size_t)(S * NL), 0);
+    for (int64_t r = 0, l = 0; r < rows; ++r) {
+        const bool lg = l < NL && lr[l] == r;
+        for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+            const int k = slab_of[ci[e]];
+            if (lg)
+                ++lcnt[k * NL + l];
+            else
+                ++lrp[k * R1 + r + 1];
+        }
+        if (lg) ++l;
     }
     P.n_slabs = S;
     P.slab_base[0] = 0;
+    std::vector<int64_t> long0(S);   // start of slab k's long-row region
     for (int k = 0; k < S; ++k) {
         int32_t *l = lrp.data() + k * R1;
         for (int64_t r = 0; r < rows; ++r) l[r + 1] += l[r];
-        P.slab_base[k + 1] = P.slab_base[k] + l[rows];
+        int64_t nlong = 0;
+        for (int64_t q = 0; q < NL; ++q) nlong += lcnt[k * NL + q];
+        long0[k] = P.slab_base[k] + l[rows];
+        P.slab_base[k + 1] = long0[k] + nlong;
     }
     for (int k = S + 1; k <= kMaxSlabs; ++k) P.slab_base[k] = P.slab_base[S];
     const int64_t total = P.slab_base[S];
+    // place the entries
     std::vector<int32_t> sci(total), sperm(total), cur(lrp);
-    for (int64_t r = 0; r < rows; ++r) {
-        if (is_long(r)) continue;
+    std::vector<int64_t> lpos(S * NL);   // next position of (slab, long row)
+    for (int k = 0; k < S; ++k) {
+        int64_t o = long0[k];
+        for (int64_t q = 0; q < NL; ++q) lpos[k * NL + q] = o, o += lcnt[k * NL + q];
+    }
+    std::vector<int64_t> lstart(lpos);
+    for (int64_t r = 0, l = 0; r < rows; ++r) {
+        const bool lg = l < NL && lr[l] == r;
         for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
             const int k = slab_of[ci[e]];
-            const int64_t q = P.slab_base[k] + cur[k * R1 + r]++;
+            const int64_t q = lg ? lpos[k * NL + l]++ : P.slab_base[k] + cur[k * R1 + r]++;
             sci[q] = ci[e], sperm[q] = (int32_t)e;
         }
+        if (lg) ++l;
     }
     for (int k = 0; k < S; ++k)   // row pointers into the concatenated slab arrays
         for (int64_t r = 0; r <= rows; ++r) lrp[k * R1 + r] += (int32_t)P.slab_base[k];
+    // chunks of the long rows, row by row, slab by slab
     std::vector<std::vector<SlabBlock>> lists(S);
+    std::vector<int32_t> crow;
+    std::vector<int64_t> cptr{0};
+    for (int64_t q = 0; q < NL; ++q) {
+        for (int k = 0; k < S; ++k) {
+            const int64_t a = lstart[k * NL + q], n = lcnt[k * NL + q];
+            for (int64_t o = 0; o < n; o += kLongChunk) {
+                const int64_t c = (int64_t)crow.size();
+                const int64_t cnt = std::min<int64_t>(kLongChunk, n - o);
+                lists[k].push_back({(int32_t)(-1 - c), 0, (int32_t)(a + o), (int32_t)cnt | (k << 16)});
+                crow.push_back((int32_t)q);
+            }
+        }
+        cptr.push_back((int64_t)crow.size());
+    }
+    // streamed blocks of the short rows
     for (int k = 0; k < S; ++k) {
         const int32_t *l = lrp.data() + k * R1;
         auto close = [&](int64_t a, int64_t b) {
@@ -279,6 +323,22 @@ static void add_slabs(DevMem &mem, SpmvPlan &P, const std::vector<int64_t> &rp,
     h2d(P.slab_ci, sci.data(), total, s);
     h2d(P.slab_perm, sperm.data(), total, s);
     h2d(P.slab_blk, blk.data(), P.n_slab_blocks, s);
+    // the long rows as the finishing steps see them (chunk sums in list order)
+    P.n_long = NL;
+    P.n_chunks = (int64_t)crow.size();
+    P.long_rows = mem.alloc<int32_t>(NL);
+    P.long_chunk_ptr = mem.alloc<int64_t>(NL + 1);
+    P.chunk_row = mem.alloc<int32_t>(P.n_chunks);
+    P.chunk_part = mem.alloc<double>(P.n_chunks);
+    h2d(P.long_rows, lr.data(), NL, s);
+    h2d(P.long_chunk_ptr, cptr.data(), NL + 1, s);
+    h2d(P.chunk_row, crow.data(), P.n_chunks, s);
+    if (NL > 0) {
+        std::vector<int32_t> lof(rows, -1);
+        for (int64_t q = 0; q < NL; ++q) lof[lr[q]] = (int32_t)q;
+        P.long_of = mem.alloc<int32_t>(rows);
+        h2d(P.long_of, lof.data(), rows, s);
+    }
     PDCS_HIP(hipStreamSynchronize(s));
 }
 
@@ -299,6 +359,10 @@ static SpmvPlan build_spmv_plan(DevMem &mem, const std::vector<int64_t> &rp, hip
     // rows one thread adds up in a streamed block stay short: longer rows go
     // to the chunks
     if (P.stream || slabs) P.long_thr = std::min<int64_t>(P.long_thr, kStreamNnz);
+    if (slabs) {   // its long rows are chunked inside the slabs
+        add_slabs(mem, P, rp, src, slabs, s);
+        return P;
+    }
     // rows longer than long_thr: chunks of kLongChunk entries
     std::vector<int32_t> lr, crow;
     std::vector<int64_t> cptr{0}, cbeg, cend;
@@ -331,7 +395,6 @@ static SpmvPlan build_spmv_plan(DevMem &mem, const std::vector<int64_t> &rp, hip
         }
         if (rows > start) sb.push_back(start), sb.push_back(rows);
     }
-    if (slabs) add_slabs(mem, P, rp, src, slabs, s);
     P.n_long = (int64_t)lr.size();
     P.n_chunks = (int64_t)cbeg.size();
     P.n_sblocks = (int64_t)sb.size() / 2;

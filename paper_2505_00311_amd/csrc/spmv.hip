@@ -50,19 +50,16 @@ __device__ __forceinline__ bool chunk_skipped(const SpmvSkip &k, const SpmvPlan 
     return k.row_inst && row_skipped(k, p.long_rows[p.chunk_row[c]]);
 }
 
-// One chunk of a long row: its sum goes to chunk_part[c]; a second kernel (or
-// the product's consumer) adds each row's chunk sums in chunk order.  Each
-// thread takes its entries kChunkRound at a time with all loads issued first
-// and adds them in entry order, then the workgroup sum is formed in a fixed
-// order.
+// The workgroup's sum of v[k] x[ci[k]] over k in [b, e) (a chunk of a long
+// row), identical in every thread: each thread takes its entries
+// kChunkRound at a time with all loads issued first and adds them in entry
+// order, then the workgroup sum is formed in a fixed order.  A second kernel
+// (or the product's consumer) adds each row's chunk sums in chunk order.
 constexpr int kChunkRound = 8;
 template <class T>
-__device__ __forceinline__ void long_chunk(int64_t c, const int64_t *__restrict__,
-                                           const int32_t *__restrict__ ci,
-                                           const T *__restrict__ v,
-                                           const T *__restrict__ x, const SpmvPlan &p) {
+__device__ __forceinline__ double chunk_sum(int64_t b, int64_t e, const int32_t *__restrict__ ci,
+                                            const T *__restrict__ v, const T *__restrict__ x) {
     constexpr int U = kChunkRound;
-    const int64_t b = p.chunk_begin[c], e = p.chunk_end[c];
     double acc[1] = {0.0};
     for (int64_t k0 = b + threadIdx.x; k0 < e; k0 += U * kBlock) {
         int32_t cc[U];
@@ -80,7 +77,17 @@ __device__ __forceinline__ void long_chunk(int64_t c, const int64_t *__restrict_
             if (k0 + (int64_t)u * kBlock < e) acc[0] += (double)w[u] * (double)xv[u];
     }
     block_sum_all<1>(acc);
-    if (threadIdx.x == 0) p.chunk_part[c] = acc[0];
+    return acc[0];
+}
+
+// Chunk c of a long row of the CSR matrix itself (the layouts without slabs).
+template <class T>
+__device__ __forceinline__ void long_chunk(int64_t c, const int64_t *__restrict__,
+                                           const int32_t *__restrict__ ci,
+                                           const T *__restrict__ v,
+                                           const T *__restrict__ x, const SpmvPlan &p) {
+    const double sum = chunk_sum(p.chunk_begin[c], p.chunk_end[c], ci, v, x);
+    if (threadIdx.x == 0) p.chunk_part[c] = sum;
 }
 
 __global__ void spmv_chunks_finish(SpmvPlan p, double *__restrict__ y, SpmvSkip skip) {
@@ -220,9 +227,10 @@ static void launch_rows(const Csr &A, const SpmvPlan &p, const T *v, const T *x,
                        A.rp, A.ci, v, x, y, p, skip, dec);
 }
 
-// Column-slab blocks [0, n_slab_blocks), then the long-row chunks.  A block
-// streams its slab's entries of rows [r0, r1) like a CSR-stream block and
-// writes the slab sums of those rows (0 for an empty segment).
+// Column-slab blocks (after the decision's): a streamed block of a slab's
+// short rows [r0, r1) writes their slab sums (0 for an empty segment); a
+// chunk block (r0 < 0) writes the sum of a piece of a long row's entries in
+// that slab.
 template <class T>
 __global__ __launch_bounds__(kBlock) void spmv_slab_kernel(int64_t rows,
                                                            const int64_t *__restrict__ rp,
@@ -234,12 +242,14 @@ __global__ __launch_bounds__(kBlock) void spmv_slab_kernel(int64_t rows,
     int64_t bid = blockIdx.x;
     if (decide_blocks(dec, bid)) return;
     if (!skip.row_inst && row_skipped(skip, 0)) return;   // one problem: one flag
-    if (bid >= p.n_slab_blocks) {
-        const int64_t c = bid - p.n_slab_blocks;
-        if (!chunk_skipped(skip, p, c)) long_chunk(c, rp, ci, v, x, p);
+    const SlabBlock d = p.slab_blk[bid];
+    if (d.r0 < 0) {   // a chunk of a long row, on its slab's XCDs
+        const int64_t c = -1 - (int64_t)d.r0;
+        if (chunk_skipped(skip, p, c)) return;
+        const double sum = chunk_sum(d.k0, (int64_t)d.k0 + (d.cs & 0xffff), p.slab_ci, sv, x);
+        if (threadIdx.x == 0) p.chunk_part[c] = sum;
         return;
     }
-    const SlabBlock d = p.slab_blk[bid];
     if (d.r1 <= d.r0) return;   // padding that keeps the slab-to-XCD assignment
     if (skip.row_inst && inst_of(skip.row_inst, d.r0) == inst_of(skip.row_inst, d.r1 - 1) &&
         row_skipped(skip, d.r0))
@@ -302,7 +312,7 @@ static void spmv_impl(const Csr &A, const SpmvPlan &p, const T *v, const T *sv, 
     }
     if (p.n_slabs > 0) {
         if (!sv) throw_hip(hipErrorInvalidValue, "column-slab plan without slab values", __FILE__, __LINE__);
-        const int64_t blocks = dec.nblk + p.n_slab_blocks + p.n_chunks;
+        const int64_t blocks = dec.nblk + p.n_slab_blocks;   // chunks are slab blocks here
         if (blocks > 0)
             hipLaunchKernelGGL((spmv_slab_kernel<T>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
                                A.rows, A.rp, A.ci, v, sv, x, p, skip, dec);
