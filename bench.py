@@ -27,6 +27,8 @@ METRIC = "time-to-1e-6 rel. KKT & PDHG iter/s (plain FP64 vs chosen form), HBM G
 SEED_LARGE = 20250502
 SEED_BATCH = 20250504
 SEED_FAMILY = 20250505
+SEED_FISHER = 20250506
+SEED_LASSO = 20250507
 HBM_PEAK_GBS = 8000.0
 CHECK = 64
 
@@ -154,6 +156,37 @@ def batched_form(pdcs, instances, torch, count):
             "speedup_iter_throughput": round(tp_b / tp_s, 3)}
 
 
+def paper_workloads(pdcs, instances, torch):
+    """The paper's two synthetic families at its smallest sizes: the Fisher
+    market (100 buyers, 5000 goods, U density 0.2) and the Lasso (1e4 x 1e5, A
+    density 1e-4), each solved from cold to 1e-3 and 1e-6 (the Lasso's 1e-6
+    run capped at 30 s).  The paper's H100 times are context, not a target."""
+    cases = [("fisher_market", instances.fisher_market(SEED_FISHER, buyers=100, goods=5000),
+              {"1e-3": 15.0, "1e-6": 37.0}, 300.0),
+             ("lasso", instances.lasso(SEED_LASSO, rows=10_000, cols=100_000),
+              {"1e-3": 0.071, "1e-6": 0.11}, 30.0)]
+    res = {}
+    for name, inst, paper, cap in cases:
+        prob = pdcs.Problem(inst)
+        prob.solve(pdcs.settings_default(max_iter=64))   # scaling and graph
+        torch.cuda.synchronize()
+        rec = {"n": inst.n, "m": inst.m, "nnz": inst.nnz, "paper_h100_s": paper}
+        for tol in (1e-3, 1e-6):
+            t0 = time.perf_counter()
+            r = prob.solve(pdcs.settings_default(tol=tol, time_limit=cap if tol < 1e-3 else 300.0))
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            status = {0: "optimal", 1: "iteration limit", 2: "time limit"}.get(r["status"], str(r["status"]))
+            key = f"{tol:.0e}".replace("e-0", "e-")
+            rec[key] = {"status": status, "solve_s": round(r["solve_s"], 3), "wall_s": round(wall, 3),
+                        "iterations": r["iterations"], "objective": r["pobj"],
+                        "kkt": max(r["err_p"], r["err_d"], r["err_gap"])}
+            log(f"{name} to {tol:g}: {status}, {r['solve_s']:.2f}s, {r['iterations']} iterations")
+        prob.close()
+        res[name] = rec
+    return res
+
+
 def warm_start_form(pdcs, instances, torch, n_assets, n_train, n_test):
     """Learned warm start on the parametric SOC portfolio family (k = 50 factors,
     theta in R^64): batched solves of n_train parameters give the targets, the
@@ -226,6 +259,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-time-to-tol", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-paper-workloads", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=64)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--m", type=int, default=500_000)
@@ -377,6 +411,8 @@ def main():
     if args.family_assets > 0:
         out["warm_start"] = warm_start_form(pdcs, instances, torch, args.family_assets,
                                             args.family_train, args.family_test)
+    if not args.no_paper_workloads:
+        out["paper_workloads"] = paper_workloads(pdcs, instances, torch)
 
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample ...")

@@ -436,3 +436,108 @@ class PortfolioFamily:
 
     def thetas(self, seed, count):
         return np.random.default_rng(seed).standard_normal((count, self.dim_theta))
+
+
+# ------------------------------------------------ the paper's workload families
+def _sparse_uniform(rng, m, n, density):
+    """m x n pattern with about density m n entries (flat positions drawn
+    uniformly, repeats merged), values U[0, 1]; CSR."""
+    k = int(rng.binomial(m * n, density)) if m * n > 0 else 0
+    flat = np.unique(rng.integers(0, m * n, size=k, dtype=np.int64))
+    return csr_from_coo(m, n, flat // n, flat % n, rng.random(flat.size))
+
+
+def fisher_market(seed, buyers=100, goods=5000, density=0.2, supply=0.25):
+    """Fisher market equilibrium in the conic form of the paper's appendix:
+    variables [X (buyers x goods, row by row), (p_i, t_i) per buyer],
+    min -sum_i w_i p_i  s.t.  sum_i X_ij = b_j,  t_i = sum_j U_ij X_ij,
+    (p_i, 1, t_i) in K_exp (p_i <= log t_i),  X >= 0.
+    U has the given density with U[0,1] entries (a buyer left without any good
+    gets one, else t_i = 0 and the problem is infeasible), w ~ U[0,1],
+    b_j = supply.
+    Rows: goods clearing and buyer utilities (ZERO), then one EXP block of
+    three rows per buyer (its middle row has no entries and h = -1).  No
+    planted optimum: the oracle's solution is the reference."""
+    rng = np.random.default_rng(seed)
+    m, n = buyers, goods
+    urp, uci, uval = _sparse_uniform(rng, m, n, density)
+    empty = np.flatnonzero(np.diff(urp) == 0)
+    if empty.size:   # a buyer with no good of positive utility makes t_i = 0 (infeasible)
+        ur = np.repeat(np.arange(m, dtype=np.int64), np.diff(urp))
+        urp, uci, uval = csr_from_coo(m, n, np.concatenate([ur, empty]),
+                                      np.concatenate([uci, rng.integers(0, n, empty.size)]),
+                                      np.concatenate([uval, rng.uniform(0.5, 1.0, empty.size)]))
+    w = rng.random(m)
+    nx = m * n
+    N = nx + 2 * m
+    rows, cols, vals = [], [], []
+    # goods j: sum_i X_ij = b_j
+    i_idx = np.repeat(np.arange(m, dtype=np.int64), n)
+    j_idx = np.tile(np.arange(n, dtype=np.int64), m)
+    rows.append(j_idx), cols.append(i_idx * n + j_idx), vals.append(np.ones(nx))
+    # buyer i: sum_j U_ij X_ij - t_i = 0
+    ur = np.repeat(np.arange(m, dtype=np.int64), np.diff(urp))
+    rows.append(n + ur), cols.append(ur * n + uci), vals.append(uval)
+    rows.append(n + np.arange(m)), cols.append(nx + 2 * np.arange(m) + 1), vals.append(-np.ones(m))
+    # exp block of buyer i: rows (p_i, [none], t_i)
+    base = n + m + 3 * np.arange(m)
+    rows.append(base), cols.append(nx + 2 * np.arange(m)), vals.append(np.ones(m))
+    rows.append(base + 2), cols.append(nx + 2 * np.arange(m) + 1), vals.append(np.ones(m))
+    M = n + 4 * m
+    rp, ci, v = csr_from_coo(M, N, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+    h = np.zeros(M)
+    h[:n] = supply
+    h[base + 1] = -1.0
+    c = np.zeros(N)
+    c[nx + 2 * np.arange(m)] = -w
+    return Instance(n=N, m=M, n_box=0, row_ptr=rp, col=ci, val=v, c=c, h=h,
+                    l=np.zeros(0), u=np.zeros(0),
+                    xcone_type=np.array([NONNEG, FREE], np.int32),
+                    xcone_dim=np.array([nx, 2 * m], np.int64),
+                    rcone_type=np.array([ZERO] + [EXP] * m, np.int32),
+                    rcone_dim=np.array([n + m] + [3] * m, np.int64),
+                    name=f"fisher_m{m}_n{n}",
+                    meta=dict(buyers=m, goods=n, u_nnz=int(uval.size), w=w, supply=supply,
+                              u_row_ptr=urp, u_col=uci, u_val=uval))
+
+
+def lasso(seed, rows=10_000, cols=100_000, density=1e-4):
+    """Lasso min ||A x - b||^2 + lambda ||x||_1 in the SOCP form of the paper's
+    appendix: variables [w, r, y (rows), x1 (cols), x2 (cols)],
+    min 2 r + lambda 1^T (x1 + x2)  s.t.  w = 1,  y - A x1 + A x2 = -b,
+    ((w + r)/sqrt 2, (w - r)/sqrt 2, y) in SOC(rows + 2),  x1, x2 >= 0.
+    A has the given density with U[0,1] entries; b = A x~ + 1e-6, x~ ~ N(0,1)
+    with half of its entries set to zero; lambda = ||A^T b||_inf.  No planted
+    optimum."""
+    rng = np.random.default_rng(seed)
+    m, n = rows, cols
+    arp, aci, aval = _sparse_uniform(rng, m, n, density)
+    xt = rng.standard_normal(n)
+    xt[rng.permutation(n)[: n // 2]] = 0.0
+    b = csr_matvec(arp, aci, aval, xt) + 1e-6
+    lam = float(np.abs(csr_rmatvec(arp, aci, aval, b, n)).max()) if n else 0.0
+    N = 2 + m + 2 * n
+    ar = np.repeat(np.arange(m, dtype=np.int64), np.diff(arp))
+    s2 = 1.0 / np.sqrt(2.0)
+    R = [np.array([0]), 1 + np.arange(m), 1 + ar, 1 + ar,
+         np.array([1 + m, 1 + m, 2 + m, 2 + m]), 3 + m + np.arange(m)]
+    C = [np.array([0]), 2 + np.arange(m), 2 + m + aci.astype(np.int64), 2 + m + n + aci.astype(np.int64),
+         np.array([0, 1, 0, 1]), 2 + np.arange(m)]
+    V = [np.ones(1), np.ones(m), -aval, aval, np.array([s2, s2, s2, -s2]), np.ones(m)]
+    M = 1 + m + m + 2
+    rp, ci, v = csr_from_coo(M, N, np.concatenate(R), np.concatenate(C), np.concatenate(V))
+    h = np.zeros(M)
+    h[0] = 1.0
+    h[1:1 + m] = -b
+    c = np.zeros(N)
+    c[1] = 2.0
+    c[2 + m:] = lam
+    return Instance(n=N, m=M, n_box=0, row_ptr=rp, col=ci, val=v, c=c, h=h,
+                    l=np.zeros(0), u=np.zeros(0),
+                    xcone_type=np.array([FREE, NONNEG], np.int32),
+                    xcone_dim=np.array([2 + m, 2 * n], np.int64),
+                    rcone_type=np.array([ZERO, SOC], np.int32),
+                    rcone_dim=np.array([1 + m, m + 2], np.int64),
+                    name=f"lasso_m{m}_n{n}",
+                    meta=dict(rows=m, cols=n, a_nnz=int(aval.size), lam=lam, b=b,
+                              a_row_ptr=arp, a_col=aci, a_val=aval))

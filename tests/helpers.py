@@ -69,3 +69,58 @@ def random_scaled_soc_point(rng, k, scale_range=1.0):
     v = rng.standard_normal(k) * 10 ** rng.uniform(-scale_range, scale_range)
     d = 10 ** rng.uniform(-scale_range, scale_range, k)
     return v, d
+
+
+# ------------------------------------------------ the paper's workload families
+def fisher_equilibrium_errors(inst, x):
+    """Relative violations, at the solution x of the Fisher market's conic form,
+    of the Eisenberg-Gale equilibrium conditions: clearing, t_i = u_i (the
+    buyer's utility), p_i = log u_i, a buyer holds only goods of the best
+    utility per price w_i U_ij / u_i (price q_j = max_i of it), and every
+    budget is spent at those prices."""
+    m, n = inst.meta["buyers"], inst.meta["goods"]
+    X = x[: m * n].reshape(m, n)
+    p, t = x[m * n::2], x[m * n + 1::2]
+    urp, uci, uval = inst.meta["u_row_ptr"], inst.meta["u_col"], inst.meta["u_val"]
+    U = np.zeros((m, n))
+    for i in range(m):
+        U[i, uci[urp[i]:urp[i + 1]]] = uval[urp[i]:urp[i + 1]]
+    w = inst.meta["w"]
+    u = (U * X).sum(axis=1)
+    bpb = w[:, None] * U / u[:, None]
+    q = bpb.max(axis=0)
+    held = (X > 1e-4 * X.max()) & (U.max(axis=0) > 0)[None, :]
+    return {
+        "clearing": float(np.abs(X.sum(axis=0) - inst.meta["supply"]).max() / inst.meta["supply"]),
+        "negative": float(max(0.0, -X.min()) / inst.meta["supply"]),
+        "utility": float(np.abs(t - u).max() / max(1.0, u.max())),
+        "log": float(np.abs(p - np.log(u)).max()),
+        "bang_per_buck": float(np.abs(bpb - q[None, :])[held].max() / q.max()) if held.any() else 0.0,
+        "budget": float(np.abs((X * q[None, :]).sum(axis=1) - w).max() / w.max()),
+    }
+
+
+def lasso_optimality_errors(inst, z):
+    """Relative violations, at the solution z of the Lasso's SOCP form, of
+    w = 1, y = A x - b, 2 r = ||y||^2, and the subgradient condition of
+    min ||A x - b||^2 + lambda ||x||_1 (x = x1 - x2), plus its objective."""
+    m, n = inst.meta["rows"], inst.meta["cols"]
+    arp, aci, aval = inst.meta["a_row_ptr"], inst.meta["a_col"], inst.meta["a_val"]
+    b, lam = inst.meta["b"], inst.meta["lam"]
+    x = z[2 + m:2 + m + n] - z[2 + m + n:]
+    rows = np.repeat(np.arange(m), np.diff(arp))
+    ax = np.zeros(m)
+    np.add.at(ax, rows, aval * x[aci])
+    res = ax - b
+    g = np.zeros(n)
+    np.add.at(g, aci, 2.0 * aval * res[rows])
+    on = np.abs(x) > 1e-6 * max(1.0, np.abs(x).max())
+    yv = z[2:2 + m]
+    return {
+        "w": float(abs(z[0] - 1.0)),
+        "y": float(np.abs(yv - res).max() / max(1.0, np.abs(b).max())),
+        "cone": float(abs(z[1] - 0.5 * yv @ yv) / max(1.0, z[1])),
+        "stationary_on": float(np.abs(g[on] + lam * np.sign(x[on])).max() / lam) if on.any() else 0.0,
+        "stationary_off": float(max(0.0, (np.abs(g[~on]).max() - lam) / lam)) if (~on).any() else 0.0,
+        "objective": float(res @ res + lam * np.abs(x).sum()),
+    }
