@@ -308,6 +308,8 @@ __device__ __forceinline__ void store_ld(const Op &op, int64_t j, const Ld &l, d
 }
 
 // ------------------------------------------------- workgroup-per-SOC block
+// The reductions over the block (read-only loops) are unrolled by 4 so that a
+// thread's loads of the scratch and scale vectors are issued together.
 template <class Op>
 __device__ void soc_block(Op &op, int64_t off, int dim, Acc &acc, double *root) {
     double *buf = op.scratch();
@@ -317,6 +319,7 @@ __device__ void soc_block(Op &op, int64_t off, int dim, Acc &acc, double *root) 
     const double t = buf[off];
     const double d0 = op.scale(off);
     double sums[3] = {0.0, 0.0, 0.0};
+#pragma unroll 4
     for (int e = 1 + tid; e < dim; e += kBlock) {
         const double x = buf[off + e], dh = op.scale(off + e) / d0;
         sums[0] += (dh * x) * (dh * x);
@@ -334,7 +337,8 @@ __device__ void soc_block(Op &op, int64_t off, int dim, Acc &acc, double *root) 
     } else if (t == 0.0) {
         cs = 3;
         double q2[1] = {0.0};
-        for (int e = 1 + tid; e < dim; e += kBlock) {
+    #pragma unroll 4
+    for (int e = 1 + tid; e < dim; e += kBlock) {
             const double x = buf[off + e], dh = op.scale(off + e) / d0;
             const double q = x / (dh + 1.0 / dh);
             q2[0] += q * q;
@@ -355,7 +359,8 @@ __device__ void soc_block(Op &op, int64_t off, int dim, Acc &acc, double *root) 
         auto eval = [&](double ss, double &f, double &df) {
             const double a = 1.0 - t / ss;
             double g[2] = {0.0, 0.0};
-            for (int e = 1 + tid; e < dim; e += kBlock) {
+        #pragma unroll 4
+    for (int e = 1 + tid; e < dim; e += kBlock) {
                 const double x = buf[off + e], dh = op.scale(off + e) / d0;
                 const double xd = x * dh;
                 const double iq = 1.0 / (dh * dh + a);
