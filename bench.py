@@ -187,6 +187,57 @@ def paper_workloads(pdcs, instances, torch):
     return res
 
 
+def projection_sweeps(pdcs, torch, total=1_200_000_000, soc_counts=None, exp_counts=None):
+    """The projection benchmarks of the paper's Section 4: a random vector
+    projected onto m SOC blocks of dimension ceil(total/m) + 1 (D = I), and
+    onto a growing number of exponential cones.  Each point: median of 5 HIP-
+    event-timed projections on a reused plan, each from a fresh copy of the
+    same input; bytes = one read and one write of the vector."""
+    # below 100 cones (dimensions above 1.2e7) each cone is one workgroup's
+    # serial work for seconds: the grid-wide class that would serve it is not
+    # built, so the default sweep starts at 100
+    soc_counts = soc_counts or [100, 1000, 10_000, 100_000, 1_000_000, 10_000_000]
+    exp_counts = exp_counts or [10 ** k for k in range(2, 8)]
+
+    def timed(types, dims):
+        n = int(np.sum(dims))
+        src = torch.randn(n, dtype=torch.float64, device="cuda")
+        v = torch.empty_like(src)
+        cones = pdcs.Cones(types, dims)
+        ms = []
+        for r in range(6):
+            v.copy_(src)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            cones.project(v)
+            b.record()
+            torch.cuda.synchronize()
+            if r:
+                ms.append(a.elapsed_time(b))
+        cones.close()
+        del src, v
+        torch.cuda.empty_cache()
+        t = float(np.median(ms))
+        gbs = 16.0 * n / (t * 1e-3) / 1e9
+        return {"entries": n, "ms": round(t, 3), "gb_s": round(gbs, 1),
+                "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+    soc = []
+    for m in soc_counts:
+        d = -(-total // m)
+        rec = timed(np.full(m, 3, np.int32), np.full(m, d + 1, np.int64))
+        rec.update(cones=m, dim=d + 1)
+        soc.append(rec)
+        log(f"SOC sweep: {m} cones of dim {d + 1}: {rec['ms']} ms, {rec['gb_s']} GB/s")
+    ex = []
+    for k in exp_counts:
+        rec = timed(np.full(k, 4, np.int32), np.full(k, 3, np.int64))
+        rec.update(cones=k)
+        ex.append(rec)
+        log(f"exp sweep: {k} cones: {rec['ms']} ms, {rec['gb_s']} GB/s")
+    return {"soc": soc, "exp": ex, "roofline_ms_soc": round(16.0 * total / (HBM_PEAK_GBS * 1e9) * 1e3, 3)}
+
+
 def warm_start_form(pdcs, instances, torch, n_assets, n_train, n_test):
     """Learned warm start on the parametric SOC portfolio family (k = 50 factors,
     theta in R^64): batched solves of n_train parameters give the targets, the
@@ -260,6 +311,7 @@ def main():
     ap.add_argument("--no-time-to-tol", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-paper-workloads", action="store_true")
+    ap.add_argument("--no-projection-sweeps", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=64)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--m", type=int, default=500_000)
@@ -413,6 +465,8 @@ def main():
                                             args.family_train, args.family_test)
     if not args.no_paper_workloads:
         out["paper_workloads"] = paper_workloads(pdcs, instances, torch)
+    if not args.no_projection_sweeps:
+        out["projection_sweeps"] = projection_sweeps(pdcs, torch)
 
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample ...")

@@ -280,6 +280,21 @@ pdcs_status pdcs_kkt(pdcs_problem *p, const double *x_dev, const double *y_dev, 
 pdcs_status pdcs_project(int64_t nblocks, const int32_t *types, const int64_t *dims, int dual,
                          const double *d_dev, double *v_dev, void *hip_stream);
 
+/* A projection plan for one product of cones, built once and reused: the
+ * dispatch of pdcs_project (the thread-, wavefront- and workgroup-level
+ * classes of Section 4) kept on the device.  pdcs_cones_create takes host
+ * arrays types/dims (copied); pdcs_cones_project enqueues the projection of
+ * v_dev (device, length sum(dims)) in place on hip_stream without waiting,
+ * with d_dev (device, nullable = identity) the diagonal of D and dual != 0
+ * for the dual cones.  Calls on one plan must not overlap (they share its
+ * scratch).  Errors: INVALID_ARG, DIMENSION, OOM, HIP. */
+typedef struct pdcs_cones pdcs_cones;
+pdcs_status pdcs_cones_create(int64_t nblocks, const int32_t *types, const int64_t *dims,
+                              void *hip_stream, pdcs_cones **out);
+pdcs_status pdcs_cones_project(pdcs_cones *c, int dual, const double *d_dev, double *v_dev,
+                               void *hip_stream);
+void pdcs_cones_destroy(pdcs_cones *c);
+
 /* ---------------------------------------------------------------------------
  * Batches (not in the paper): `count` independent problems solved together.
  * Their data are laid out block-diagonally on the device and every kernel of a

@@ -1796,6 +1796,45 @@ pdcs_status pdcs_project(int64_t nblocks, const int32_t *types, const int64_t *d
     });
 }
 
+struct pdcs_cones {
+    DevMem mem;
+    ConePlan plan;
+    double *part = nullptr;
+    int64_t len = 0;
+};
+
+pdcs_status pdcs_cones_create(int64_t nblocks, const int32_t *types, const int64_t *dims,
+                              void *hip_stream, pdcs_cones **out) {
+    if (!out) {
+        g_last_error = "out is NULL";
+        return PDCS_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    return guarded([&] {
+        if (nblocks < 0 || (nblocks > 0 && (!types || !dims))) fail(PDCS_ERR_INVALID_ARG, "NULL argument");
+        int64_t len = 0;
+        for (int64_t b = 0; b < nblocks; ++b) len += dims[b];
+        std::vector<int32_t> t;
+        std::vector<int64_t> d;
+        validate_cones(nblocks, types, dims, len, "cones", t, d);
+        auto c = std::make_unique<pdcs_cones>();
+        c->plan = upload_plan(c->mem, build_plan(0, 0, t, d), (hipStream_t)hip_stream);
+        c->part = c->mem.alloc<double>(c->plan.ntiles * kPartials);
+        c->len = len;
+        *out = c.release();
+    });
+}
+
+pdcs_status pdcs_cones_project(pdcs_cones *c, int dual, const double *d_dev, double *v_dev,
+                               void *hip_stream) {
+    return guarded([&] {
+        if (!c || (c->len > 0 && !v_dev)) fail(PDCS_ERR_INVALID_ARG, "NULL argument");
+        pass_project(c->plan, dual != 0, ProjArgs{v_dev, d_dev}, c->part, (hipStream_t)hip_stream);
+    });
+}
+
+void pdcs_cones_destroy(pdcs_cones *c) { delete c; }
+
 pdcs_status pdcs_batch_create(const pdcs_problem_desc *descs, int64_t count, void *hip_stream,
                               pdcs_batch **out) {
     if (!out) {

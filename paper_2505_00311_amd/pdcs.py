@@ -68,7 +68,8 @@ _lib = None
 
 SYMBOLS = ["pdcs_settings_default", "pdcs_problem_create", "pdcs_problem_create_device",
            "pdcs_problem_destroy", "pdcs_solve", "pdcs_scaling", "pdcs_spmv", "pdcs_spmv32",
-           "pdcs_set_layout", "pdcs_get_layout", "pdcs_kkt", "pdcs_project", "pdcs_batch_create", "pdcs_batch_solve", "pdcs_batch_size",
+           "pdcs_set_layout", "pdcs_get_layout", "pdcs_kkt", "pdcs_cones_create", "pdcs_cones_project",
+           "pdcs_cones_destroy", "pdcs_project", "pdcs_batch_create", "pdcs_batch_solve", "pdcs_batch_size",
            "pdcs_batch_destroy", "pdcs_mlp_create", "pdcs_mlp_num_params", "pdcs_mlp_forward",
            "pdcs_mlp_gradient", "pdcs_mlp_train_step", "pdcs_mlp_get_params", "pdcs_mlp_destroy",
            "pdcs_gemm_bf16", "pdcs_status_string", "pdcs_last_error"]
@@ -102,6 +103,10 @@ def load():
     L.pdcs_set_layout.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
     L.pdcs_get_layout.argtypes = [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     L.pdcs_kkt.argtypes = [_vp, _vp, _vp, _vp]
+    L.pdcs_cones_create.argtypes = [_i64, _pi32, _pi64, _vp, ctypes.POINTER(_vp)]
+    L.pdcs_cones_project.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
+    L.pdcs_cones_destroy.argtypes = [_vp]
+    L.pdcs_cones_destroy.restype = None
     L.pdcs_project.argtypes = [_i64, _pi32, _pi64, ctypes.c_int, _vp, _vp, _vp]
     L.pdcs_batch_create.argtypes = [ctypes.POINTER(ProblemDesc), _i64, _vp, ctypes.POINTER(_vp)]
     L.pdcs_batch_solve.argtypes = [_vp, ctypes.POINTER(Settings), _vp, _vp, _vp,
@@ -376,6 +381,37 @@ def project(types, dims, v_dev, d_dev=None, dual=False, stream=None):
     _check(load().pdcs_project(int(t.size), t.ctypes.data_as(_pi32), k.ctypes.data_as(_pi64),
                                1 if dual else 0, None if d_dev is None else _dptr(d_dev),
                                _dptr(v_dev), _stream(stream)))
+
+
+class Cones:
+    """A reusable projection plan (pdcs_cones_*): project() enqueues the
+    projection of a device tensor in place on the stream without waiting."""
+
+    def __init__(self, types, dims, stream=None):
+        L = load()
+        t = np.ascontiguousarray(types, np.int32)
+        k = np.ascontiguousarray(dims, np.int64)
+        self.size = int(k.sum())
+        h = _vp()
+        _check(L.pdcs_cones_create(int(t.size), t.ctypes.data_as(_pi32), k.ctypes.data_as(_pi64),
+                                   _stream(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def project(self, v_dev, d_dev=None, dual=False, stream=None):
+        _check(load().pdcs_cones_project(self.handle, 1 if dual else 0,
+                                         None if d_dev is None else _dptr(d_dev), _dptr(v_dev),
+                                         _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            load().pdcs_cones_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class MLP:

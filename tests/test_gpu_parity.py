@@ -369,3 +369,30 @@ def test_empty_rows_and_columns(pd, orc):
                   snap_iters=[64, 128])
     assert np.allclose(g["log"]["snap_x"], o["log"]["snap_x"], rtol=1e-10, atol=1e-12)
     prob.close()
+
+
+def test_reusable_projection_plan_matches_one_shot(pd, orc):
+    """pdcs_cones_project on a plan built once gives the bits of pdcs_project,
+    call after call (the plan's partials scratch is reused)."""
+    rng = np.random.default_rng(12)
+    types, dims = [], []
+    for _ in range(300):
+        t = int(rng.choice([1, 2, 3, 3, 4, 5]))
+        k = 3 if t in (4, 5) else int(rng.choice([1, 5, 17, 70, 200, 300, 1000]))
+        types.append(t), dims.append(k)
+    cones = pd.Cones(types, dims)
+    for dual in (False, True):
+        for call in range(3):
+            v, d = random_cone_vector(rng, types, dims)
+            a, b = dev(v), dev(v)
+            pd.project(types, dims, a, dev(d), dual=dual)
+            cones.project(b, dev(d), dual=dual)
+            torch.cuda.synchronize()
+            assert torch.equal(a, b), (dual, call)
+    ref = orc.proj_blocks(types, dims, v, d, dual=True)
+    o = 0
+    got = b.cpu().numpy()
+    for k in dims:
+        assert np.abs(got[o:o + k] - ref[o:o + k]).max() <= 1e-12 * max(1.0, np.linalg.norm(v[o:o + k]))
+        o += k
+    cones.close()
