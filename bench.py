@@ -187,6 +187,37 @@ def paper_workloads(pdcs, instances, torch):
     return res
 
 
+def pdhg_ablation(pdcs, instances, torch, cap_s=30.0):
+    """The paper's PDHG-versus-PDCS comparison on synthetic stand-ins for its
+    SOC and exponential-cone sets: time and iterations to 1e-6 of Algorithm 1
+    and of the baseline PDHG (fixed step 0.9/||G~||_2 on both sides, no
+    Halpern step, no restarts; the same rescaling), the baseline capped at
+    cap_s seconds."""
+    cases = [("lp_soc n=1000", instances.lp_soc_small(20250501)),
+             ("large_mixed n=20000 (SOC + exp)", instances.large_mixed(7, n=20000, m=10000)),
+             ("fisher_market 100x5000 (exp)", instances.fisher_market(SEED_FISHER, buyers=100, goods=5000))]
+    res = []
+    for name, inst in cases:
+        prob = pdcs.Problem(inst)
+        prob.solve(pdcs.settings_default(max_iter=64))
+        rec = {"workload": name, "n": inst.n, "m": inst.m, "nnz": inst.nnz}
+        for key, kw in (("pdcs", {}), ("pdhg", {"plain_pdhg": 1})):
+            torch.cuda.synchronize()
+            r = prob.solve(pdcs.settings_default(tol=1e-6, time_limit=cap_s, **kw))
+            torch.cuda.synchronize()
+            rec[key] = {"status": pdcs.SOLVE_STATUS[r["status"]], "solve_s": round(r["solve_s"], 3),
+                        "iterations": r["iterations"],
+                        "kkt": max(r["err_p"], r["err_d"], r["err_gap"])}
+            log(f"ablation {name} {key}: {rec[key]['status']}, {r['solve_s']:.2f}s, {r['iterations']} iterations")
+        if rec["pdhg"]["status"] == "optimal":
+            rec["speedup_time"] = round(rec["pdhg"]["solve_s"] / rec["pdcs"]["solve_s"], 2)
+        else:
+            rec["speedup_time_at_least"] = round(cap_s / rec["pdcs"]["solve_s"], 2)
+        prob.close()
+        res.append(rec)
+    return res
+
+
 def projection_sweeps(pdcs, torch, total=1_200_000_000, soc_counts=None, exp_counts=None):
     """The projection benchmarks of the paper's Section 4: a random vector
     projected onto m SOC blocks of dimension ceil(total/m) + 1 (D = I), and
@@ -312,6 +343,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-paper-workloads", action="store_true")
     ap.add_argument("--no-projection-sweeps", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=64)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--m", type=int, default=500_000)
@@ -467,6 +499,8 @@ def main():
         out["paper_workloads"] = paper_workloads(pdcs, instances, torch)
     if not args.no_projection_sweeps:
         out["projection_sweeps"] = projection_sweeps(pdcs, torch)
+    if not args.no_ablation:
+        out["pdhg_ablation"] = pdhg_ablation(pdcs, instances, torch)
 
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample ...")

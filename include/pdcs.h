@@ -133,6 +133,12 @@ typedef struct {
      * (restarted at their chosen candidate with their primal weight) once they
      * hold at most 1/8 of the batch's nonzeros (not in the paper). */
     int32_t batch_dropout;
+    /* 1: the baseline PDHG the paper compares PDCS with (its appendix on PDHG
+     * versus PDCS): step step_fixed / ||G~||_2 on both sides (omega = 1 unless
+     * omega0 is given), z = z^ (no reflection, no Halpern anchor), no
+     * restarts, termination measured at the current iterate; the rescaling
+     * still applies.  0: Algorithm 1. */
+    int32_t plain_pdhg;
 } pdcs_settings;
 
 /* Kernels of one step attempt, in launch order (indices of pdcs_info.kernel_ms). */

@@ -60,7 +60,7 @@ class Settings(ctypes.Structure):
                 ("step_reduce_exp", _dbl), ("step_grow_exp", _dbl),
                 ("restart_sufficient", _dbl), ("restart_necessary", _dbl),
                 ("restart_artificial", _dbl), ("max_attempts", _i32), ("step_mode", _i32),
-                ("step_fixed", _dbl), ("power_iters", _i32)]
+                ("step_fixed", _dbl), ("power_iters", _i32), ("plain_pdhg", _i32)]
 
 
 class _Info(ctypes.Structure):

@@ -570,6 +570,7 @@ void orc_settings_default(orc_settings *s) {
     s->step_mode = 0;
     s->step_fixed = 0.9;
     s->power_iters = 100;
+    s->plain_pdhg = 0;
 }
 
 typedef struct {
@@ -621,7 +622,8 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
 
     /* --- initial step size and primal weight (readings) --- */
     double eta = gmax > 0.0 ? 1.0 / gmax : 1.0;
-    if (s->step_mode == 1) {
+    const int plain = s->plain_pdhg == 1;
+    if (s->step_mode == 1 || plain) {
         /* fixed step step_fixed / ||G~||_2, the norm by power iteration on
          * G~^T G~ from the normalised all-ones vector */
         double *pv = ALLOC(double, n), *pu = ALLOC(double, m), *pw = ALLOC(double, n);
@@ -641,6 +643,7 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
     {
         double nc = sqrt(nrm2sq(n, cs)), nh = sqrt(nrm2sq(m, hs));
         omega = (nc > 1e-10 && nh > 1e-10) ? nc / nh : 1.0;
+        if (plain) omega = 1.0;   /* the baseline takes the same step on both sides */
         if (omega0 > 0.0) omega = omega0;
     }
 
@@ -712,7 +715,7 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
             double e1 = (1.0 - pow(nn, -s->step_reduce_exp)) * ebar;
             double e2 = (1.0 + pow(nn, -s->step_grow_exp)) * eta;
             double enew = e1 < e2 ? e1 : e2;
-            if (s->step_mode == 1) { /* fixed step: every attempt is accepted */
+            if (s->step_mode == 1 || plain) { /* fixed step: every attempt is accepted */
                 eta_used = eta;
                 break;
             }
@@ -734,7 +737,9 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
         /* ---- AdaptiveReflectionParameter (reading) ---- */
         double beta;
         double r = sqrt(omega * nx2 + ny2 / omega);
-        if (s->beta_mode == 1) {
+        if (plain) {
+            beta = 0.0;
+        } else if (s->beta_mode == 1) {
             beta = s->beta_const;
         } else {
             beta = r <= r_prev ? fmin(1.0, s->beta_grow * beta_prev) : s->beta_shrink * beta_prev;
@@ -743,8 +748,9 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
         beta_prev = beta;
 
         /* ---- ReflectedHalpern (Algorithm 1) ---- */
-        double a = (double)(kin + 1) / (double)(kin + 2);
-        double b = 1.0 / (double)(kin + 2);
+        /* the baseline PDHG keeps z = z^: weights 1 and 0 */
+        double a = plain ? 1.0 : (double)(kin + 1) / (double)(kin + 2);
+        double b = plain ? 0.0 : 1.0 / (double)(kin + 2);
         for (int64_t j = 0; j < n; ++j) x[j] = a * ((1.0 + beta) * xh[j] - beta * x[j]) + b * xa[j];
         for (int64_t i = 0; i < m; ++i) y[i] = a * ((1.0 + beta) * yh[i] - beta * y[i]) + b * ya[i];
         /* ---- weighted average (Algorithm 1) ---- */
@@ -782,7 +788,7 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
         proj_x(p, ls, us, dx, xc2);
         proj_y(p, dy, yc2);
         kkt_scaled(p, e, f, xc2, yc2, xu, yu, &k2);
-        int chosen = kkt_avg(&k2) < kkt_avg(&k1) ? 1 : 0;
+        int chosen = !plain && kkt_avg(&k2) < kkt_avg(&k1) ? 1 : 0;
         const double *xc = chosen ? xc2 : xc1, *yc = chosen ? yc2 : yc1;
         kkt_t kc = chosen ? k2 : k1;
         double kcv = kkt_avg(&kc), kav = kkt_avg(&k_anchor);
@@ -797,7 +803,7 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
             status = ORC_ITER_LIMIT;
             stop = 1;
         }
-        if (!stop) {
+        if (!stop && !plain) {
             if (kcv <= s->restart_sufficient * kav)
                 reason = 1;
             else if (kcv <= s->restart_necessary * kav && kcv > kprev_avg)

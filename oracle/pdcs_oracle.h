@@ -73,6 +73,10 @@ typedef struct {
     int32_t step_mode;          /* 0: adaptive step (Algorithm 1), 1: fixed step          */
     double step_fixed;          /* fixed step = step_fixed / ||G~||_2                      */
     int32_t power_iters;        /* power iterations estimating ||G~||_2                    */
+    int32_t plain_pdhg;         /* 1: the baseline PDHG of the paper's PDHG-vs-PDCS
+                                 * comparison: fixed step step_fixed/||G~||_2 for both
+                                 * sides (omega = 1), z = z^ (no reflection or Halpern),
+                                 * no restarts, termination at the current iterate   */
 } orc_settings;
 
 typedef struct {

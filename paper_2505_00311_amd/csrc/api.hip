@@ -1224,7 +1224,8 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
         if (!xo[b] || !yo[b]) fail(PDCS_ERR_INVALID_ARG, "settings, x_out and y_out are required");
     if (S->check_every < 1 || S->ruiz_iters < 0 || S->max_attempts < 1 || !(S->tol >= 0.0) ||
         S->step_mode < 0 || S->step_mode > 1 || (S->step_mode == 1 && !(S->step_fixed > 0.0)) ||
-        S->precision < 0 || S->precision > 1 || !(S->polish_tol >= 0.0) || S->polish_stall < 1)
+        S->precision < 0 || S->precision > 1 || !(S->polish_tol >= 0.0) || S->polish_stall < 1 ||
+        S->plain_pdhg < 0 || S->plain_pdhg > 1 || (S->plain_pdhg == 1 && !(S->step_fixed > 0.0)))
         fail(PDCS_ERR_INVALID_ARG, "bad settings");
     if (tr && B != 1) fail(PDCS_ERR_INVALID_ARG, "a trace is for a single problem");
     if (tr && (tr->cap < 0 || tr->n_snap < 0 || (tr->n_snap > 0 && (!tr->snap_iter || !tr->snap_x || !tr->snap_y)) ||
@@ -1283,7 +1284,8 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
     d2h(raw.data() + 2 * B, P->kraw + 2 * B, B, s);
 
     std::vector<double> eta0(B);
-    if (S->step_mode == 1) eta0 = fixed_step(P, S);
+    const bool plain = S->plain_pdhg == 1;
+    if (S->step_mode == 1 || plain) eta0 = fixed_step(P, S);
     std::vector<DevState> hs(B);
     std::vector<Kkt> k_anchor(B), kout(B);
     std::vector<int> status(B, -1), out_src(B, -2);   // -2: not written yet
@@ -1312,14 +1314,17 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
     for (int64_t b = 0; b < B; ++b) {
         DevState &h = hs[b];
         h = DevState{};
-        h.eta = S->step_mode == 1 ? eta0[b] : (P->gmax[b] > 0.0 ? 1.0 / P->gmax[b] : 1.0);
+        h.eta = S->step_mode == 1 || plain ? eta0[b] : (P->gmax[b] > 0.0 ? 1.0 / P->gmax[b] : 1.0);
         h.omega = (P->cs_norm[b] > 1e-10 && P->hs_norm[b] > 1e-10) ? P->cs_norm[b] / P->hs_norm[b] : 1.0;
+        if (plain) h.omega = 1.0;   // the baseline takes the same step on both sides
         if (omega0 && omega0[b] > 0.0) h.omega = omega0[b];
         h.tau = h.eta / h.omega, h.sigma = h.eta * h.omega;
         h.beta_prev = 1.0, h.r_prev = INFINITY;
         h.max_iter = S->max_iter, h.check_every = S->check_every, h.max_attempts = S->max_attempts;
         h.beta_mode = S->beta_mode, h.beta_const = S->beta_const, h.beta_grow = S->beta_grow;
-        h.step_mode = S->step_mode;
+        h.step_mode = plain ? 1 : S->step_mode;
+        h.plain = plain ? 1 : 0;
+        if (plain) h.beta_mode = 1, h.beta_const = 0.0;
         h.beta_shrink = S->beta_shrink, h.step_reduce_exp = S->step_reduce_exp;
         h.step_grow_exp = S->step_grow_exp;
         h.log_cap = cap, h.log_attempts = log_att, h.log_eta = log_eta, h.log_beta = log_beta,
@@ -1432,7 +1437,7 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
             DevState &h = hs[b];
             ++checks[b];
             const Kkt k1 = kkt_from_raw(P, b, raw[b]), k2 = kkt_from_raw(P, b, raw[B + b]);
-            const int chosen = k2.avg() < k1.avg() ? 1 : 0;
+            const int chosen = !plain && k2.avg() < k1.avg() ? 1 : 0;
             last_src[b] = chosen;
             const Kkt kc = chosen ? k2 : k1;
             const double kcv = kc.avg(), kav = k_anchor[b].avg();
@@ -1446,7 +1451,7 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
             } else if (S->time_limit > 0.0 && elapsed >= S->time_limit) {
                 status[b] = PDCS_SOLVE_TIME_LIMIT, stop = 1;
             }
-            if (!stop) {
+            if (!stop && !plain) {
                 if (kcv <= S->restart_sufficient * kav)
                     reason = 1;
                 else if (kcv <= S->restart_necessary * kav && kcv > kprev_avg[b])
@@ -1648,6 +1653,7 @@ pdcs_status pdcs_settings_default(pdcs_settings *s) {
     s->polish_stall = 8;
     s->autotune = 0;
     s->batch_dropout = 1;
+    s->plain_pdhg = 0;
     return PDCS_OK;
 }
 

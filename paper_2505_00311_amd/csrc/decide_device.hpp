@@ -65,8 +65,8 @@ __device__ void decide_body(DevState *__restrict__ st, const double *__restrict_
         st->beta_prev = beta;
         st->beta = beta;
         const long long k = st->kin;
-        st->ha = (double)(k + 1) / (double)(k + 2);
-        st->hb = 1.0 / (double)(k + 2);
+        st->ha = st->plain ? 1.0 : (double)(k + 1) / (double)(k + 2);
+        st->hb = st->plain ? 0.0 : 1.0 / (double)(k + 2);
         st->eta_used = eta;
         st->eta_sum += eta;
         st->eta = enew;

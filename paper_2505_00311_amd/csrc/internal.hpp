@@ -181,6 +181,7 @@ struct DevState {
     // change under them); the host writes both
     int halt_next, pad_halt;
     int check_every, max_attempts, beta_mode, step_mode;
+    int plain, pad_plain;             // plain: baseline PDHG, Halpern weights 1 and 0
     double beta_const, beta_grow, beta_shrink, step_reduce_exp, step_grow_exp;
     long long log_cap;
     int *log_attempts;

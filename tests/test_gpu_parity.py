@@ -396,3 +396,27 @@ def test_reusable_projection_plan_matches_one_shot(pd, orc):
         assert np.abs(got[o:o + k] - ref[o:o + k]).max() <= 1e-12 * max(1.0, np.linalg.norm(v[o:o + k]))
         o += k
     cones.close()
+
+
+@pytest.mark.parametrize("name,maker", TRAJ[:3], ids=[t[0] for t in TRAJ[:3]])
+def test_plain_pdhg_trajectory(pd, orc, name, maker):
+    """The baseline PDHG (plain_pdhg = 1): same iterates as the oracle's over
+    200 iterations (its fixed step, no Halpern step, no restarts)."""
+    inst = maker()
+    say("plain pdhg trajectory", name)
+    errs = _trajectory(pd, orc, inst, 200, plain_pdhg=1)
+    say("  worst relative iterate difference", errs.max())
+    assert errs.max() <= TRAJ_BOUND[name], (int(errs.argmax()) + 1, errs.max())
+
+
+def test_plain_pdhg_solves_to_tolerance(pd, orc):
+    inst = I.small_mixed(1)
+    prob = pd.Problem(inst)
+    g = prob.solve(pd.settings_default(plain_pdhg=1, tol=1e-7))
+    prob.close()
+    o = orc.solve(inst, orc.default_settings(plain_pdhg=1, tol=1e-7, max_iter=2_000_000))
+    assert g["status"] == 0 and o["status"] == 0 and g["restarts"] == 0
+    assert g["pobj"] == pytest.approx(inst.opt, rel=1e-5, abs=1e-5)
+    # the two step sizes come from power iterations in different summation
+    # orders, so termination may land one check period (64) apart
+    assert abs(g["iterations"] - o["iterations"]) <= 64

@@ -237,3 +237,42 @@ def test_solve_without_rows(orc):
     r = orc.solve(inst, orc.default_settings(tol=1e-9))
     assert r["status"] == 0 and r["iterations"] > 0
     assert np.allclose(r["x"], inst.x_star, atol=1e-8)
+
+
+# ------------------------------------------------ the baseline PDHG (plain mode)
+def test_plain_pdhg_is_textbook_pdhg(orc):
+    """plain_pdhg = 1 without rescaling: the iterates are those of textbook PDHG
+    with tau = sigma = 0.9 / ||G||_2 (||G||_2 from an SVD here, by power
+    iteration in the oracle), written out below with the box and
+    nonnegative-orthant projections of this LP."""
+    from paper_2505_00311_amd import instances as I
+    inst = I.tiny_lp(7, n=6, m=5)
+    G = inst.dense()
+    eta = 0.9 / np.linalg.svd(G, compute_uv=False)[0]
+    l, u = inst.l, inst.u
+    x = np.clip(np.zeros(inst.n), l, u)
+    y = np.zeros(inst.m)
+    iters = 6
+    ref = []
+    for _ in range(iters):
+        xh = np.clip(x - eta * (inst.c - G.T @ y), l, u)
+        yh = np.maximum(y + eta * (inst.h - G @ (2 * xh - x)), 0.0)
+        x, y = xh, yh
+        ref.append((x.copy(), y.copy()))
+    s = orc.default_settings(ruiz_iters=0, pock_chambolle=0, plain_pdhg=1, max_iter=iters,
+                             power_iters=500)
+    r = orc.solve(inst, s, log_cap=iters, snap_iters=np.arange(1, iters + 1))
+    for k in range(iters):
+        assert np.allclose(r["log"]["snap_x"][k], ref[k][0], rtol=1e-9, atol=1e-12), k
+        assert np.allclose(r["log"]["snap_y"][k], ref[k][1], rtol=1e-9, atol=1e-12), k
+    assert np.all(r["log"]["beta"][:iters] == 0.0)
+    assert np.allclose(r["log"]["omega"][:iters], 1.0)
+
+
+def test_plain_pdhg_reaches_the_planted_optimum(orc):
+    from paper_2505_00311_amd import instances as I
+    inst = I.small_mixed(1)
+    r = orc.solve(inst, orc.default_settings(plain_pdhg=1, tol=1e-7, max_iter=2_000_000))
+    assert r["status"] == 0
+    assert r["pobj"] == pytest.approx(inst.opt, rel=1e-5, abs=1e-5)
+    assert r["restarts"] == 0
