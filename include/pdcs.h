@@ -57,7 +57,23 @@ enum {
     PDCS_CONE_NONNEG = 2,
     PDCS_CONE_SOC = 3,
     PDCS_CONE_EXP = 4,
-    PDCS_CONE_EXP_DUAL = 5
+    PDCS_CONE_EXP_DUAL = 5,
+    /* Rotated SOC, d >= 2: (u, v, w) with 2 u v >= ||w||^2, u, v >= 0 (the
+     * cone of the paper's Lasso form).  The orthogonal, self-inverse map
+     * T(u, v, w) = ((u + v)/sqrt 2, (u - v)/sqrt 2, w) takes it onto SOC of the
+     * same dimension, so at creation a row block of this type is replaced by
+     * T applied to its rows of G and h, and an x block by G T and T c on its
+     * first two entries; both become SOC blocks.  Starting points and
+     * solutions are mapped by T at the boundary (entries of G that the map
+     * makes exactly zero are dropped).  The cone is self-dual.  Supported by
+     * pdcs_problem_create and pdcs_batch_create (host arrays; the device
+     * form returns NOT_SUPPORTED) and by the projections with d_dev = NULL
+     * (NOT_SUPPORTED otherwise).  pdcs_solve, pdcs_spmv, pdcs_spmv32 and
+     * pdcs_kkt take and return points of the caller's problem; the
+     * termination measures and pdcs_scaling are those of the mapped problem
+     * (T keeps 2-norms, the infinity norms of the measures differ by at most
+     * a factor sqrt 2). */
+    PDCS_CONE_RSOC = 6
 };
 
 /* Outcome of a solve (distinct from the call's pdcs_status). */
@@ -279,10 +295,11 @@ pdcs_status pdcs_kkt(pdcs_problem *p, const double *x_dev, const double *y_dev, 
 
 /* Projection of v_dev (device, length sum(dims)) in place onto the product of
  * diagonally rescaled cones D K_1 x ... x D K_nblocks (eq. (6); Theorem 1 for
- * SOC, Theorem 3 for EXP, the Appendix A.2 remark for EXP_DUAL).  types and
- * dims are host arrays; d_dev (device, nullable = identity) is the diagonal of
- * D.  dual != 0 projects onto the product of the dual cones instead.
- * Errors: INVALID_ARG, DIMENSION, HIP. */
+ * SOC, Theorem 3 for EXP, the Appendix A.2 remark for EXP_DUAL; RSOC as
+ * T P_SOC(T v), D = I only).  types and dims are host arrays; d_dev (device,
+ * nullable = identity) is the diagonal of D.  dual != 0 projects onto the
+ * product of the dual cones instead.
+ * Errors: INVALID_ARG, DIMENSION, HIP; NOT_SUPPORTED for RSOC with d_dev. */
 pdcs_status pdcs_project(int64_t nblocks, const int32_t *types, const int64_t *dims, int dual,
                          const double *d_dev, double *v_dev, void *hip_stream);
 
@@ -293,7 +310,8 @@ pdcs_status pdcs_project(int64_t nblocks, const int32_t *types, const int64_t *d
  * v_dev (device, length sum(dims)) in place on hip_stream without waiting,
  * with d_dev (device, nullable = identity) the diagonal of D and dual != 0
  * for the dual cones.  Calls on one plan must not overlap (they share its
- * scratch).  Errors: INVALID_ARG, DIMENSION, OOM, HIP. */
+ * scratch).  Errors: INVALID_ARG, DIMENSION, OOM, HIP; NOT_SUPPORTED for a
+ * plan with RSOC blocks given a d_dev. */
 typedef struct pdcs_cones pdcs_cones;
 pdcs_status pdcs_cones_create(int64_t nblocks, const int32_t *types, const int64_t *dims,
                               void *hip_stream, pdcs_cones **out);

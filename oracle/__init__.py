@@ -10,6 +10,13 @@ thread); this module only compiles it with gcc and marshals numpy arrays
 through ctypes.  An instance is any object with the attributes
 ``n, m, n_box, row_ptr, col, val, c, h, l, u, xcone_type, xcone_dim,
 rcone_type, rcone_dim``.
+
+Rotated second-order cones (type RSOC: 2 u v >= ||w||^2 with u, v >= 0, the
+cone of the appendix's Lasso form) are handled here, in Python: the problem
+is rewritten with the orthogonal symmetric map T that is the identity except
+for the 2x2 block [[1, 1], [1, -1]] / sqrt 2 on the first two entries of each
+rotated block (T maps the rotated cone onto the second-order cone), and
+points are mapped by T on the way in and out.
 """
 from __future__ import annotations
 
@@ -23,7 +30,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pdcs_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-ZERO, FREE, NONNEG, SOC, EXP, EXP_DUAL = range(6)
+ZERO, FREE, NONNEG, SOC, EXP, EXP_DUAL, RSOC = range(7)
 OPTIMAL, ITER_LIMIT, TIME_LIMIT, NUMERICAL = range(4)
 
 _i64 = ctypes.c_int64
@@ -140,6 +147,58 @@ def _problem(inst, keep: _Keep) -> _Problem:
                     int(rt.size), _ptr(rt, ctypes.c_int32), _ptr(rd, ctypes.c_int64))
 
 
+def _rotation(types, dims, start, size):
+    """The map T over a vector of `size` entries whose cone blocks (types,
+    dims) start at entry `start`: a sparse matrix, identity except
+    [[1, 1], [1, -1]] / sqrt 2 on the first two entries of each rotated
+    block.  T is symmetric and orthogonal, so T^-1 = T^T = T."""
+    import scipy.sparse as sp
+    r = 1.0 / np.sqrt(2.0)
+    rows, cols, vals = [], [], []
+    rotated = set()
+    o = start
+    for t, d in zip(np.asarray(types), np.asarray(dims)):
+        if int(t) == RSOC:
+            rotated.update((o, o + 1))
+            rows += [o, o, o + 1, o + 1]
+            cols += [o, o + 1, o, o + 1]
+            vals += [r, r, r, -r]
+        o += int(d)
+    ident = [i for i in range(size) if i not in rotated]
+    rows += ident
+    cols += ident
+    vals += [1.0] * len(ident)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(size, size))
+
+
+def _has_rsoc(inst):
+    return bool(np.any(np.asarray(inst.xcone_type) == RSOC) or
+                np.any(np.asarray(inst.rcone_type) == RSOC))
+
+
+def _as_soc(inst):
+    """The problem with every rotated block replaced by an SOC block:
+    G' = T_r G T_x, c' = T_x c, h' = T_r h (T_r over the rows, T_x over x);
+    x = T_x x', y = T_r y'.  Returns (problem, T_x, T_r)."""
+    import scipy.sparse as sp
+    from types import SimpleNamespace
+    n, m = int(inst.n), int(inst.m)
+    Tx = _rotation(inst.xcone_type, inst.xcone_dim, int(inst.n_box), n)
+    Tr = _rotation(inst.rcone_type, inst.rcone_dim, 0, m)
+    G = sp.csr_matrix((np.asarray(inst.val, np.float64), np.asarray(inst.col, np.int64),
+                       np.asarray(inst.row_ptr, np.int64)), shape=(m, n))
+    G2 = sp.csr_matrix(Tr @ G @ Tx)
+    G2.eliminate_zeros()
+    G2.sort_indices()
+    soc = lambda t: np.where(np.asarray(t) == RSOC, SOC, np.asarray(t)).astype(np.int32)
+    return SimpleNamespace(
+        n=n, m=m, n_box=int(inst.n_box), row_ptr=G2.indptr.astype(np.int64),
+        col=G2.indices.astype(np.int32), val=G2.data.astype(np.float64),
+        c=Tx @ np.asarray(inst.c, np.float64), h=Tr @ np.asarray(inst.h, np.float64),
+        l=inst.l, u=inst.u, xcone_type=soc(inst.xcone_type), xcone_dim=inst.xcone_dim,
+        rcone_type=soc(inst.rcone_type), rcone_dim=inst.rcone_dim), Tx, Tr
+
+
 def default_settings(**overrides) -> Settings:
     s = Settings()
     _lib().orc_settings_default(ctypes.byref(s))
@@ -182,7 +241,14 @@ def proj_exp_dual(v, d=None):
 
 
 def proj_blocks(types, dims, v, d=None, dual=False):
-    """Projection onto a product of (scaled) cones, eq. (6)."""
+    """Projection onto a product of (scaled) cones, eq. (6).  Rotated blocks:
+    T P_SOC(T v), for D = I only (the rotated cone is self-dual)."""
+    if np.any(np.asarray(types) == RSOC):
+        if d is not None:
+            raise ValueError("rotated SOC blocks are projected with D = I")
+        T = _rotation(types, dims, 0, int(np.sum(dims)))
+        st = np.where(np.asarray(types) == RSOC, SOC, np.asarray(types))
+        return T @ proj_blocks(st, dims, T @ np.asarray(v, np.float64), None, dual)
     t = np.ascontiguousarray(types, dtype=np.int32)
     k = np.ascontiguousarray(dims, dtype=np.int64)
     out = np.array(v, dtype=np.float64, copy=True)
@@ -206,6 +272,9 @@ def spmv(row_ptr, col, val, x):
 
 # ---------------------------------------------------------------- problem-level
 def scaling(inst, settings: Settings | None = None):
+    """Rescaling factors (E, F); of the rewritten problem when it has rotated blocks."""
+    if _has_rsoc(inst):
+        inst = _as_soc(inst)[0]
     keep = _Keep()
     P = _problem(inst, keep)
     s = settings or default_settings()
@@ -217,7 +286,11 @@ def scaling(inst, settings: Settings | None = None):
 
 
 def kkt(inst, x, y):
-    """eq. (PDCS_terminate_tolerance) at unscaled (x, y)."""
+    """eq. (PDCS_terminate_tolerance) at unscaled (x, y); with rotated
+    blocks, the measures of the rewritten problem at (T_x x, T_r y)."""
+    if _has_rsoc(inst):
+        inst, Tx, Tr = _as_soc(inst)
+        x, y = Tx @ np.asarray(x, np.float64), Tr @ np.asarray(y, np.float64)
     keep = _Keep()
     P = _problem(inst, keep)
     x = keep.arr(x, np.float64)
@@ -231,6 +304,11 @@ def kkt(inst, x, y):
 
 def onepdhg(inst, x, y, tau, sigma):
     """One PDHG step, eq. (5), on the unscaled problem."""
+    if _has_rsoc(inst):
+        inst2, Tx, Tr = _as_soc(inst)
+        xh, yh = onepdhg(inst2, Tx @ np.asarray(x, np.float64), Tr @ np.asarray(y, np.float64),
+                         tau, sigma)
+        return Tx @ xh, Tr @ yh
     keep = _Keep()
     P = _problem(inst, keep)
     x = keep.arr(x, np.float64)
@@ -246,7 +324,18 @@ def onepdhg(inst, x, y, tau, sigma):
 def solve(inst, settings: Settings | None = None, x0=None, y0=None, omega0: float = 0.0,
           log_cap: int = 0, snap_iters=None):
     """Algorithm 1 with rescaling.  Returns a dict with x, y, info fields and,
-    if requested, the decision log and iterate snapshots."""
+    if requested, the decision log and iterate snapshots.  Rotated blocks:
+    the rewritten problem is solved from (T_x x0, T_r y0) and its iterates
+    are mapped back by T."""
+    if _has_rsoc(inst):
+        inst2, Tx, Tr = _as_soc(inst)
+        fwd = lambda T, v: None if v is None else T @ np.asarray(v, np.float64)
+        res = solve(inst2, settings, fwd(Tx, x0), fwd(Tr, y0), omega0, log_cap, snap_iters)
+        res["x"], res["y"] = Tx @ res["x"], Tr @ res["y"]
+        if "log" in res:
+            res["log"]["snap_x"] = np.array([Tx @ v for v in res["log"]["snap_x"]])
+            res["log"]["snap_y"] = np.array([Tr @ v for v in res["log"]["snap_y"]])
+        return res
     keep = _Keep()
     P = _problem(inst, keep)
     s = settings or default_settings()

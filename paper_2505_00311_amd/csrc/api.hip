@@ -483,6 +483,13 @@ struct pdcs_problem {
     // and of the products' inputs x^, y^, allocated on first use
     float *xh32 = nullptr, *yh32 = nullptr;
     float *x32 = nullptr;   // input of pdcs_spmv32
+    // rotated SOC blocks of the caller's problem (mapped to SOC at creation):
+    // the caller's index of each block's first entry, in x and in the rows,
+    // [B+1] bounds per instance, device copies and an (n + m) work buffer
+    std::vector<int64_t> rx, ry, rx_b, ry_b;
+    int64_t *rx_dev = nullptr, *ry_dev = nullptr;
+    double *rtmp = nullptr;
+    int64_t snaps_written = 0;         // snapshots of the last solve's trace
     ~pdcs_problem() {
         for (hipEvent_t e : tev) (void)hipEventDestroy(e);
         for (hipGraphExec_t g : gexec)
@@ -524,8 +531,9 @@ static void validate_cones(int64_t nblk, const int32_t *t, const int64_t *d, int
     if (nblk < 0 || (nblk > 0 && (!t || !d))) fail(PDCS_ERR_INVALID_ARG, std::string(what) + ": bad cone list");
     int64_t sum = 0;
     for (int64_t b = 0; b < nblk; ++b) {
-        if (t[b] < kZero || t[b] > kExpDual) fail(PDCS_ERR_INVALID_ARG, std::string(what) + ": unknown cone type");
+        if (t[b] < kZero || t[b] > kRsoc) fail(PDCS_ERR_INVALID_ARG, std::string(what) + ": unknown cone type");
         if (d[b] < 1) fail(PDCS_ERR_DIMENSION, std::string(what) + ": cone of dimension < 1");
+        if (t[b] == kRsoc && d[b] < 2) fail(PDCS_ERR_DIMENSION, std::string(what) + ": rotated SOC of dimension < 2");
         if ((t[b] == kExp || t[b] == kExpDual) && d[b] != 3)
             fail(PDCS_ERR_DIMENSION, std::string(what) + ": exponential cone of dimension != 3");
         if (d[b] > INT32_MAX) fail(PDCS_ERR_NOT_SUPPORTED, std::string(what) + ": cone too large");
@@ -581,6 +589,152 @@ static void sync_slab_values(pdcs_problem *P) {
 
 static void set_plan(pdcs_problem *P, int side, int code);
 
+// ------------------------------------------------------------ rotated SOC
+// A rotated SOC block (2 u v >= ||w||^2, u, v >= 0) is an SOC block under the
+// orthogonal, self-inverse map T(u, v, w) = ((u + v)/sqrt 2, (u - v)/sqrt 2, w):
+//   row block: (G x - h) in RSOC  <=>  T (G x - h) in SOC, so the block's first
+//              two rows of G and entries of h become their sum and difference
+//              over sqrt 2, and the caller's dual variable is y = T y';
+//   x block:   x in RSOC  <=>  x = T x' with x' in SOC, so the block's first
+//              two columns of G and entries of c are combined the same way.
+// The objective is unchanged; starting points and solutions are mapped by T.
+struct RsocMap {
+    std::vector<pdcs_problem_desc> d;
+    std::vector<std::vector<int64_t>> rp, xd, rd;
+    std::vector<std::vector<int32_t>> ci, xt, rt;
+    std::vector<std::vector<double>> val, c, h;
+    // caller's index of the first entry of each rotated block, over the whole
+    // batch (instance b's x block at x0_b + offset), and [B+1] bounds per instance
+    std::vector<int64_t> xpair, ypair, xpair_b, ypair_b;
+};
+
+static bool has_rsoc(int64_t nblk, const int32_t *t) {
+    for (int64_t b = 0; t && b < nblk; ++b)
+        if (t[b] == kRsoc) return true;
+    return false;
+}
+
+// Host CSR checks needed before the arrays are read on the host.
+static void check_csr_host(const pdcs_problem_desc *D) {
+    if (D->row_ptr[0] != 0 || D->row_ptr[D->m] != D->nnz)
+        fail(PDCS_ERR_INVALID_ARG, "malformed CSR (row_ptr or column index)");
+    for (int64_t r = 0; r < D->m; ++r)
+        if (D->row_ptr[r] > D->row_ptr[r + 1]) fail(PDCS_ERR_INVALID_ARG, "malformed CSR (row_ptr or column index)");
+    for (int64_t k = 0; k < D->nnz; ++k)
+        if (D->col[k] < 0 || D->col[k] >= D->n) fail(PDCS_ERR_INVALID_ARG, "malformed CSR (row_ptr or column index)");
+}
+
+// Fills R with the descriptors of Ds[0, count) with every rotated block
+// mapped to SOC; false (R untouched) when there is none.
+static bool map_rsoc(const pdcs_problem_desc *Ds, int64_t count, RsocMap &R) {
+    bool any = false;
+    for (int64_t b = 0; b < count; ++b) {
+        check_desc(Ds + b);
+        any = any || has_rsoc(Ds[b].n_xcones, Ds[b].xcone_type) || has_rsoc(Ds[b].n_rcones, Ds[b].rcone_type);
+    }
+    if (!any) return false;
+    const double r2 = 1.0 / std::sqrt(2.0);
+    R.d.assign(Ds, Ds + count);
+    R.rp.resize(count), R.xd.resize(count), R.rd.resize(count), R.ci.resize(count);
+    R.xt.resize(count), R.rt.resize(count), R.val.resize(count), R.c.resize(count), R.h.resize(count);
+    R.xpair_b.assign(1, 0), R.ypair_b.assign(1, 0);
+    int64_t x0 = 0, y0 = 0;
+    for (int64_t b = 0; b < count; ++b) {
+        const pdcs_problem_desc &D = Ds[b];
+        std::vector<int32_t> vt;
+        std::vector<int64_t> vd;
+        validate_cones(D.n_xcones, D.xcone_type, D.xcone_dim, D.n - D.n_box, "x cones", vt, vd);
+        validate_cones(D.n_rcones, D.rcone_type, D.rcone_dim, D.m, "row cones", vt, vd);
+        check_csr_host(&D);
+        // pair[j] = 0: column j untouched, 1: first, 2: second entry of a rotated x block
+        std::vector<int8_t> xpair(D.n, 0);
+        std::vector<int64_t> rows_first;   // first rows of the rotated row blocks
+        R.c[b].assign(D.c, D.c + D.n);
+        R.h[b].assign(D.h, D.h + D.m);
+        R.xt[b].assign(D.xcone_type, D.xcone_type + D.n_xcones);
+        R.xd[b].assign(D.xcone_dim, D.xcone_dim + D.n_xcones);
+        R.rt[b].assign(D.rcone_type, D.rcone_type + D.n_rcones);
+        R.rd[b].assign(D.rcone_dim, D.rcone_dim + D.n_rcones);
+        for (int64_t k = 0, o = D.n_box; k < D.n_xcones; o += D.xcone_dim[k], ++k) {
+            if (D.xcone_type[k] != kRsoc) continue;
+            R.xt[b][k] = kSoc;
+            xpair[o] = 1, xpair[o + 1] = 2;
+            R.xpair.push_back(x0 + o);
+            const double a = D.c[o], e = D.c[o + 1];
+            R.c[b][o] = (a + e) * r2, R.c[b][o + 1] = (a - e) * r2;
+        }
+        for (int64_t k = 0, o = 0; k < D.n_rcones; o += D.rcone_dim[k], ++k) {
+            if (D.rcone_type[k] != kRsoc) continue;
+            R.rt[b][k] = kSoc;
+            rows_first.push_back(o);
+            R.ypair.push_back(y0 + o);
+            const double a = D.h[o], e = D.h[o + 1];
+            R.h[b][o] = (a + e) * r2, R.h[b][o + 1] = (a - e) * r2;
+        }
+        // Merges entries (key, side, value) by key and appends the sums and
+        // differences over sqrt 2 of sides 0 and 1 (exact zeros dropped).
+        struct Ent { int32_t key; int side; double v; };
+        auto merge = [&](std::vector<Ent> &ents, std::vector<std::pair<int32_t, double>> &o0,
+                         std::vector<std::pair<int32_t, double>> &o1, int32_t key1_shift) {
+            std::stable_sort(ents.begin(), ents.end(), [](const Ent &p, const Ent &q) { return p.key < q.key; });
+            for (size_t i = 0; i < ents.size();) {
+                double s0 = 0.0, s1 = 0.0;
+                size_t j = i;
+                for (; j < ents.size() && ents[j].key == ents[i].key; ++j) (ents[j].side ? s1 : s0) += ents[j].v;
+                const double p = (s0 + s1) * r2, q = (s0 - s1) * r2;
+                if (p != 0.0) o0.push_back({ents[i].key, p});
+                if (q != 0.0) o1.push_back({ents[i].key + key1_shift, q});
+                i = j;
+            }
+        };
+        // columns: in each row, the entries of a rotated pair of columns
+        std::vector<std::vector<std::pair<int32_t, double>>> rows(D.m);
+        std::vector<Ent> ents;
+        for (int64_t r = 0; r < D.m; ++r) {
+            auto &out = rows[r];
+            ents.clear();
+            for (int64_t k = D.row_ptr[r]; k < D.row_ptr[r + 1]; ++k) {
+                const int32_t j = D.col[k];
+                if (!xpair[j]) out.push_back({j, D.val[k]});
+                else ents.push_back({xpair[j] == 1 ? j : j - 1, xpair[j] - 1, D.val[k]});
+            }
+            merge(ents, out, out, 1);
+        }
+        // rows: the first two rows of each rotated row block, merged by column
+        for (int64_t o : rows_first) {
+            ents.clear();
+            for (int w = 0; w < 2; ++w)
+                for (const auto &e : rows[o + w]) ents.push_back({e.first, w, e.second});
+            rows[o].clear(), rows[o + 1].clear();
+            merge(ents, rows[o], rows[o + 1], 0);
+        }
+        auto &rp = R.rp[b];
+        rp.assign(D.m + 1, 0);
+        for (int64_t r = 0; r < D.m; ++r) rp[r + 1] = rp[r] + (int64_t)rows[r].size();
+        R.ci[b].reserve(rp[D.m]), R.val[b].reserve(rp[D.m]);
+        for (const auto &row : rows)
+            for (const auto &e : row) R.ci[b].push_back(e.first), R.val[b].push_back(e.second);
+        pdcs_problem_desc &M = R.d[b];
+        M.nnz = rp[D.m];
+        M.row_ptr = rp.data(), M.col = R.ci[b].data(), M.val = R.val[b].data();
+        M.c = R.c[b].data(), M.h = R.h[b].data();
+        M.xcone_type = R.xt[b].data(), M.xcone_dim = R.xd[b].data();
+        M.rcone_type = R.rt[b].data(), M.rcone_dim = R.rd[b].data();
+        R.xpair_b.push_back((int64_t)R.xpair.size()), R.ypair_b.push_back((int64_t)R.ypair.size());
+        x0 += D.n, y0 += D.m;
+    }
+    return true;
+}
+
+static void rotate_host(double *v, const int64_t *offs, int64_t count, int64_t base) {
+    const double r2 = 1.0 / std::sqrt(2.0);
+    for (int64_t t = 0; t < count; ++t) {
+        double *p = v + (offs[t] - base);
+        const double a = p[0], e = p[1];
+        p[0] = (a + e) * r2, p[1] = (a - e) * r2;
+    }
+}
+
 // A problem, or a batch of `count` independent problems laid out block-
 // diagonally: instance b owns entries [x0, x0 + n) of x, rows [y0, y0 + m) and
 // nonzeros [k0, k0 + nnz); its columns are shifted by x0.  A batch needs host
@@ -590,6 +744,14 @@ static pdcs_problem *create_impl(const pdcs_problem_desc *Ds, int64_t count, voi
     if (!Ds) fail(PDCS_ERR_INVALID_ARG, "desc is NULL");
     if (count < 1) fail(PDCS_ERR_INVALID_ARG, "no problem in the batch");
     if (on_device && count != 1) fail(PDCS_ERR_NOT_SUPPORTED, "a batch takes host arrays");
+    RsocMap R;
+    if (on_device) {
+        check_desc(Ds);
+        if (has_rsoc(Ds->n_xcones, Ds->xcone_type) || has_rsoc(Ds->n_rcones, Ds->rcone_type))
+            fail(PDCS_ERR_NOT_SUPPORTED, "rotated SOC blocks need host arrays");
+    } else if (map_rsoc(Ds, count, R)) {
+        Ds = R.d.data();
+    }
     auto P = std::make_unique<pdcs_problem>();
     P->B = count;
     P->stream = (hipStream_t)stream;
@@ -701,6 +863,16 @@ static pdcs_problem *create_impl(const pdcs_problem_desc *Ds, int64_t count, voi
     if (flag & 4) fail(PDCS_ERR_INVALID_ARG, "bounds: NaN, l > u, l = +inf or u = -inf");
     if (flag & 1) fail(PDCS_ERR_NONFINITE, "non-finite value in G, c or h");
 
+    if (!R.d.empty()) {
+        P->rx = std::move(R.xpair), P->ry = std::move(R.ypair);
+        P->rx_b = std::move(R.xpair_b), P->ry_b = std::move(R.ypair_b);
+        P->rx_dev = M.alloc<int64_t>((int64_t)P->rx.size());
+        P->ry_dev = M.alloc<int64_t>((int64_t)P->ry.size());
+        P->rtmp = M.alloc<double>(n + m);
+        h2d(P->rx_dev, P->rx.data(), (int64_t)P->rx.size(), s);
+        h2d(P->ry_dev, P->ry.data(), (int64_t)P->ry.size(), s);
+        PDCS_HIP(hipStreamSynchronize(s));
+    }
     transpose_csr(P->G, P->Gt, s);
     std::vector<int64_t> hrp(m + 1), hrpt(n + 1);
     d2h(hrp.data(), P->G.rp, m + 1, s);
@@ -1576,6 +1748,7 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
         tr->count = cnt;
     }
     PDCS_HIP(hipStreamSynchronize(s));
+    P->snaps_written = snap;
     const double solve_s = std::chrono::duration<double>(clk::now() - t_iter).count();
     for (int64_t b = 0; b < B; ++b) {
         if (!infos) break;
@@ -1591,6 +1764,69 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
         for (int j = 0; j < PDCS_K_COUNT; ++j)
             infos[b].kernel_ms[j] = kms[j], infos[b].kernel_launches[j] = klaunch[j];
         infos[b].polish_iter = polish_iter;
+    }
+}
+
+// The caller's point (x [n] or y [m], device) in the solver's formulation: a
+// copy with each rotated pair mapped by T, or v itself when there is none.
+static const double *to_solver(pdcs_problem *P, bool is_y, const double *v, hipStream_t s) {
+    const std::vector<int64_t> &o = is_y ? P->ry : P->rx;
+    if (o.empty()) return v;
+    double *t = is_y ? P->rtmp + P->n : P->rtmp;
+    d2d(t, v, is_y ? P->m : P->n, s);
+    rotate_pairs(t, is_y ? P->ry_dev : P->rx_dev, (int64_t)o.size(), 0, s);
+    return t;
+}
+// Maps a result of the solver's formulation (device) back to the caller's.
+static void to_caller(pdcs_problem *P, bool is_y, double *v, hipStream_t s) {
+    const std::vector<int64_t> &o = is_y ? P->ry : P->rx;
+    if (!o.empty()) rotate_pairs(v, is_y ? P->ry_dev : P->rx_dev, (int64_t)o.size(), 0, s);
+}
+
+// solve_batch in the caller's formulation: the rotated pairs of the starting
+// points, the solutions and the snapshots are mapped by T.
+static void solve_caller(pdcs_problem *P, const pdcs_settings *S, const double *const *x0,
+                         const double *const *y0, const double *omega0, double *const *xo,
+                         double *const *yo, pdcs_info *infos, pdcs_trace *tr) {
+    if (P->rx.empty() && P->ry.empty()) return solve_batch(P, S, x0, y0, omega0, xo, yo, infos, tr);
+    const int64_t B = P->B;
+    auto span = [&](bool is_y, int64_t b) {
+        const std::vector<int64_t> &o = is_y ? P->ry : P->rx, &ob = is_y ? P->ry_b : P->rx_b;
+        return std::make_pair(o.data() + ob[b], ob[b + 1] - ob[b]);
+    };
+    std::vector<std::vector<double>> hx(B), hy(B);
+    std::vector<const double *> px(B, nullptr), py(B, nullptr);
+    for (int64_t b = 0; b < B; ++b) {
+        const InstDims &I = P->inst[b];
+        if (x0 && x0[b]) {
+            hx[b].assign(x0[b], x0[b] + I.n);
+            const auto o = span(false, b);
+            rotate_host(hx[b].data(), o.first, o.second, I.x0);
+            px[b] = hx[b].data();
+        }
+        if (y0 && y0[b]) {
+            hy[b].assign(y0[b], y0[b] + I.m);
+            const auto o = span(true, b);
+            rotate_host(hy[b].data(), o.first, o.second, I.y0);
+            py[b] = hy[b].data();
+        }
+    }
+    solve_batch(P, S, px.data(), py.data(), omega0, xo, yo, infos, tr);
+    for (int64_t b = 0; b < B; ++b) {
+        const InstDims &I = P->inst[b];
+        const auto ox = span(false, b), oy = span(true, b);
+        if (S->out_on_device) {
+            rotate_pairs(xo[b], P->rx_dev + P->rx_b[b], ox.second, I.x0, P->stream);
+            rotate_pairs(yo[b], P->ry_dev + P->ry_b[b], oy.second, I.y0, P->stream);
+        } else {
+            rotate_host(xo[b], ox.first, ox.second, I.x0);
+            rotate_host(yo[b], oy.first, oy.second, I.y0);
+        }
+    }
+    if (S->out_on_device) PDCS_HIP(hipStreamSynchronize(P->stream));
+    for (int64_t i = 0; tr && i < P->snaps_written; ++i) {
+        rotate_host(tr->snap_x + i * P->n, P->rx.data(), (int64_t)P->rx.size(), 0);
+        rotate_host(tr->snap_y + i * P->m, P->ry.data(), (int64_t)P->ry.size(), 0);
     }
 }
 
@@ -1687,7 +1923,7 @@ pdcs_status pdcs_solve(pdcs_problem *p, const pdcs_settings *settings, const dou
                        pdcs_info *info, pdcs_trace *trace) {
     return guarded([&] {
         if (!p) fail(PDCS_ERR_INVALID_ARG, "problem is NULL");
-        solve_batch(p, settings, &x0, &y0, &omega0, &x_out, &y_out, info, trace);
+        solve_caller(p, settings, &x0, &y0, &omega0, &x_out, &y_out, info, trace);
     });
 }
 
@@ -1708,6 +1944,7 @@ pdcs_status pdcs_spmv(pdcs_problem *p, int transpose, const double *x_dev, doubl
     return guarded([&] {
         if (!p || !x_dev || !y_dev) fail(PDCS_ERR_INVALID_ARG, "NULL argument");
         hipStream_t s = hip_stream ? (hipStream_t)hip_stream : p->stream;
+        x_dev = to_solver(p, transpose != 0, x_dev, s);
         // columns are held in the internal order of x
         if (transpose) {
             spmv(p->Gt, p->pGt, x_dev, p->tmp_n, SpmvSkip{}, s);
@@ -1716,6 +1953,7 @@ pdcs_status pdcs_spmv(pdcs_problem *p, int transpose, const double *x_dev, doubl
             gather(p->tmp_n, x_dev, p->xperm, p->n, s);
             spmv(p->G, p->pG, p->tmp_n, y_dev, SpmvSkip{}, s);
         }
+        to_caller(p, transpose == 0, y_dev, s);
     });
 }
 
@@ -1732,6 +1970,7 @@ pdcs_status pdcs_spmv32(pdcs_problem *p, int transpose, const double *x_dev, dou
             p->G.v32 = g32, p->Gt.v32 = gt32;
             sync_slab_values(p);
         }
+        x_dev = to_solver(p, transpose != 0, x_dev, s);
         // columns are held in the internal order of x
         if (transpose) {
             to_float(x_dev, p->x32, p->m, s);
@@ -1742,6 +1981,7 @@ pdcs_status pdcs_spmv32(pdcs_problem *p, int transpose, const double *x_dev, dou
             to_float(p->tmp_n, p->x32, p->n, s);
             spmv32(p->G, p->pG, p->x32, y_dev, SpmvSkip{}, s);
         }
+        to_caller(p, transpose == 0, y_dev, s);
     });
 }
 
@@ -1770,6 +2010,8 @@ pdcs_status pdcs_kkt(pdcs_problem *p, const double *x_dev, const double *y_dev, 
     return guarded([&] {
         if (!p || !x_dev || !y_dev || !out) fail(PDCS_ERR_INVALID_ARG, "NULL argument");
         hipStream_t s = p->stream;
+        x_dev = to_solver(p, false, x_dev, s);
+        y_dev = to_solver(p, true, y_dev, s);
         double *xi = p->xc[1];   // x in the internal order
         gather(xi, x_dev, p->xperm, p->n, s);
         spmv(p->G, p->pG, xi, p->gxc[0], SpmvSkip{}, s);
@@ -1783,6 +2025,18 @@ pdcs_status pdcs_kkt(pdcs_problem *p, const double *x_dev, const double *y_dev, 
     });
 }
 
+// Rotated SOC blocks of a cone list become SOC blocks; returns their first
+// entries.  T maps the rotated cone onto the SOC, so the projection onto the
+// rotated cone is T P_SOC(T v); under a scaling D != I this no longer holds.
+static std::vector<int64_t> rsoc_to_soc(std::vector<int32_t> &t, const std::vector<int64_t> &d,
+                                        const double *d_dev) {
+    std::vector<int64_t> rot;
+    for (size_t b = 0, o = 0; b < t.size(); o += d[b], ++b)
+        if (t[b] == kRsoc) t[b] = kSoc, rot.push_back((int64_t)o);
+    if (!rot.empty() && d_dev) fail(PDCS_ERR_NOT_SUPPORTED, "rotated SOC blocks are projected with D = I");
+    return rot;
+}
+
 pdcs_status pdcs_project(int64_t nblocks, const int32_t *types, const int64_t *dims, int dual,
                          const double *d_dev, double *v_dev, void *hip_stream) {
     return guarded([&] {
@@ -1793,11 +2047,16 @@ pdcs_status pdcs_project(int64_t nblocks, const int32_t *types, const int64_t *d
         std::vector<int32_t> t;
         std::vector<int64_t> d;
         validate_cones(nblocks, types, dims, len, "cones", t, d);
+        const std::vector<int64_t> rot = rsoc_to_soc(t, d, d_dev);
         hipStream_t s = (hipStream_t)hip_stream;
         DevMem mem;
         ConePlan plan = upload_plan(mem, build_plan(0, 0, t, d), s);
         double *part = mem.alloc<double>(plan.ntiles * kPartials);
+        int64_t *rot_dev = mem.alloc<int64_t>((int64_t)rot.size());
+        h2d(rot_dev, rot.data(), (int64_t)rot.size(), s);
+        rotate_pairs(v_dev, rot_dev, (int64_t)rot.size(), 0, s);
         pass_project(plan, dual != 0, ProjArgs{v_dev, d_dev}, part, s);
+        rotate_pairs(v_dev, rot_dev, (int64_t)rot.size(), 0, s);
         PDCS_HIP(hipStreamSynchronize(s));
     });
 }
@@ -1807,6 +2066,8 @@ struct pdcs_cones {
     ConePlan plan;
     double *part = nullptr;
     int64_t len = 0;
+    int64_t n_rot = 0;          // rotated SOC blocks, projected as T P_SOC(T v)
+    int64_t *rot = nullptr;     // [n_rot] their first entries
 };
 
 pdcs_status pdcs_cones_create(int64_t nblocks, const int32_t *types, const int64_t *dims,
@@ -1823,10 +2084,16 @@ pdcs_status pdcs_cones_create(int64_t nblocks, const int32_t *types, const int64
         std::vector<int32_t> t;
         std::vector<int64_t> d;
         validate_cones(nblocks, types, dims, len, "cones", t, d);
+        const std::vector<int64_t> rot = rsoc_to_soc(t, d, nullptr);
         auto c = std::make_unique<pdcs_cones>();
-        c->plan = upload_plan(c->mem, build_plan(0, 0, t, d), (hipStream_t)hip_stream);
+        hipStream_t s = (hipStream_t)hip_stream;
+        c->plan = upload_plan(c->mem, build_plan(0, 0, t, d), s);
         c->part = c->mem.alloc<double>(c->plan.ntiles * kPartials);
         c->len = len;
+        c->n_rot = (int64_t)rot.size();
+        c->rot = c->mem.alloc<int64_t>(c->n_rot);
+        h2d(c->rot, rot.data(), c->n_rot, s);
+        PDCS_HIP(hipStreamSynchronize(s));
         *out = c.release();
     });
 }
@@ -1835,7 +2102,11 @@ pdcs_status pdcs_cones_project(pdcs_cones *c, int dual, const double *d_dev, dou
                                void *hip_stream) {
     return guarded([&] {
         if (!c || (c->len > 0 && !v_dev)) fail(PDCS_ERR_INVALID_ARG, "NULL argument");
-        pass_project(c->plan, dual != 0, ProjArgs{v_dev, d_dev}, c->part, (hipStream_t)hip_stream);
+        if (c->n_rot > 0 && d_dev) fail(PDCS_ERR_NOT_SUPPORTED, "rotated SOC blocks are projected with D = I");
+        hipStream_t s = (hipStream_t)hip_stream;
+        rotate_pairs(v_dev, c->rot, c->n_rot, 0, s);
+        pass_project(c->plan, dual != 0, ProjArgs{v_dev, d_dev}, c->part, s);
+        rotate_pairs(v_dev, c->rot, c->n_rot, 0, s);
     });
 }
 
@@ -1859,7 +2130,7 @@ pdcs_status pdcs_batch_solve(pdcs_batch *b, const pdcs_settings *settings, const
                              double *const *y_out, pdcs_info *infos) {
     return guarded([&] {
         if (!b || !b->p) fail(PDCS_ERR_INVALID_ARG, "batch is NULL");
-        solve_batch(b->p, settings, x0, y0, omega0, x_out, y_out, infos, nullptr);
+        solve_caller(b->p, settings, x0, y0, omega0, x_out, y_out, infos, nullptr);
     });
 }
 

@@ -22,7 +22,8 @@ constexpr int kExpPerTile = 64;      // exponential cones per tile (one thread e
 constexpr int kPartials = 6;         // per-tile partial slots: 3 sums, 3 maxima
 
 // cone type codes of the C ABI
-enum ConeType : int32_t { kZero = 0, kFree = 1, kNonneg = 2, kSoc = 3, kExp = 4, kExpDual = 5 };
+enum ConeType : int32_t { kZero = 0, kFree = 1, kNonneg = 2, kSoc = 3, kExp = 4, kExpDual = 5,
+                          kRsoc = 6 };   // rotated SOC: mapped to kSoc at the boundary
 
 // tile kinds of a cone plan
 enum TileKind : int32_t {
@@ -275,6 +276,9 @@ void gather(double *out, const double *in, const int32_t *idx, int64_t n, hipStr
 void scatter(double *out, const double *in, const int32_t *idx, int64_t n, int64_t base,
              hipStream_t s);
 void relabel(int32_t *ci, int64_t nnz, const int32_t *pos, hipStream_t s);
+// (v[o], v[o+1]) <- ((v[o] + v[o+1])/sqrt 2, (v[o] - v[o+1])/sqrt 2) for each
+// o = offs[t] - base, t < count: the map between a rotated SOC and an SOC.
+void rotate_pairs(double *v, const int64_t *offs, int64_t count, int64_t base, hipStream_t s);
 // A.sv (and A.sv32 when both A.v32 and A.sv32 are set) <- the values in the
 // slab order of p (the caller allocates them).  No-op for a plan without slabs.
 void slab_values(const Csr &A, const SpmvPlan &p, hipStream_t s);

@@ -2,6 +2,8 @@
 // diagonal rescaling of Section 3 (reading: Ruiz infinity-norm passes, then one
 // Pock-Chambolle pass with alpha = 1), the scaled problem vectors, input
 // validation and small deterministic reductions.
+#include <cmath>
+
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include "device_common.hpp"
@@ -378,6 +380,24 @@ __global__ void relabel_kernel(int32_t *ci, int64_t nnz, const int32_t *pos) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < nnz) ci[k] = pos[ci[k]];
 }
+// r = 1 / fl(sqrt 2), the constant the host side of the map uses, so both
+// sides round the same way
+__global__ void rotate_pairs_kernel(double *v, const int64_t *offs, int64_t count, int64_t base,
+                                    double r) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const int64_t o = offs[t] - base;
+    const double a = v[o], b = v[o + 1];
+    v[o] = (a + b) * r;
+    v[o + 1] = (a - b) * r;
+}
+void rotate_pairs(double *v, const int64_t *offs, int64_t count, int64_t base, hipStream_t s) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(rotate_pairs_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+                       v, offs, count, base, 1.0 / std::sqrt(2.0));
+    PDCS_HIP(hipGetLastError());
+}
+
 void relabel(int32_t *ci, int64_t nnz, const int32_t *pos, hipStream_t s) {
     if (nnz == 0) return;
     hipLaunchKernelGGL(relabel_kernel, dim3(grid_for(nnz)), dim3(kBlock), 0, s, ci, nnz, pos);

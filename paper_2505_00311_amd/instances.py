@@ -11,7 +11,7 @@ the dual of X, a slack s* in K_d^* and y* in K_d with <x*,lambda*> = 0 and
 <s*,y*> = 0 blockwise, then sets h = G x* - s* and c = G^T y* + lambda*.  The
 planted objective <c, x*> is then the optimal value.
 
-Cone type codes: ZERO 0, FREE 1, NONNEG 2, SOC 3, EXP 4, EXP_DUAL 5.
+Cone type codes: ZERO 0, FREE 1, NONNEG 2, SOC 3, EXP 4, EXP_DUAL 5, RSOC 6 (rotated SOC).
 A row block of type T states G x - h in T.
 """
 from __future__ import annotations
@@ -20,7 +20,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-ZERO, FREE, NONNEG, SOC, EXP, EXP_DUAL = range(6)
+ZERO, FREE, NONNEG, SOC, EXP, EXP_DUAL, RSOC = range(7)
 
 
 @dataclass
@@ -501,11 +501,13 @@ def fisher_market(seed, buyers=100, goods=5000, density=0.2, supply=0.25):
                               u_row_ptr=urp, u_col=uci, u_val=uval))
 
 
-def lasso(seed, rows=10_000, cols=100_000, density=1e-4):
+def lasso(seed, rows=10_000, cols=100_000, density=1e-4, rotated=False):
     """Lasso min ||A x - b||^2 + lambda ||x||_1 in the SOCP form of the paper's
     appendix: variables [w, r, y (rows), x1 (cols), x2 (cols)],
     min 2 r + lambda 1^T (x1 + x2)  s.t.  w = 1,  y - A x1 + A x2 = -b,
-    ((w + r)/sqrt 2, (w - r)/sqrt 2, y) in SOC(rows + 2),  x1, x2 >= 0.
+    ((w + r)/sqrt 2, (w - r)/sqrt 2, y) in SOC(rows + 2),  x1, x2 >= 0;
+    with rotated=True the last block is written as (w, r, y) in the rotated
+    cone (RSOC: 2 w r >= ||y||^2), the same set.
     A has the given density with U[0,1] entries; b = A x~ + 1e-6, x~ ~ N(0,1)
     with half of its entries set to zero; lambda = ||A^T b||_inf.  No planted
     optimum."""
@@ -524,6 +526,8 @@ def lasso(seed, rows=10_000, cols=100_000, density=1e-4):
     C = [np.array([0]), 2 + np.arange(m), 2 + m + aci.astype(np.int64), 2 + m + n + aci.astype(np.int64),
          np.array([0, 1, 0, 1]), 2 + np.arange(m)]
     V = [np.ones(1), np.ones(m), -aval, aval, np.array([s2, s2, s2, -s2]), np.ones(m)]
+    if rotated:
+        R[4], C[4], V[4] = np.array([1 + m, 2 + m]), np.array([0, 1]), np.ones(2)
     M = 1 + m + m + 2
     rp, ci, v = csr_from_coo(M, N, np.concatenate(R), np.concatenate(C), np.concatenate(V))
     h = np.zeros(M)
@@ -536,8 +540,39 @@ def lasso(seed, rows=10_000, cols=100_000, density=1e-4):
                     l=np.zeros(0), u=np.zeros(0),
                     xcone_type=np.array([FREE, NONNEG], np.int32),
                     xcone_dim=np.array([2 + m, 2 * n], np.int64),
-                    rcone_type=np.array([ZERO, SOC], np.int32),
+                    rcone_type=np.array([ZERO, RSOC if rotated else SOC], np.int32),
                     rcone_dim=np.array([1 + m, m + 2], np.int64),
-                    name=f"lasso_m{m}_n{n}",
+                    name=f"lasso_m{m}_n{n}" + ("_rsoc" if rotated else ""),
                     meta=dict(rows=m, cols=n, a_nnz=int(aval.size), lam=lam, b=b,
                               a_row_ptr=arp, a_col=aci, a_val=aval))
+
+
+def rsoc_min_sum(seed, k=5, form="x"):
+    """min u + v over the rotated cone 2 u v >= ||w||^2 (u, v >= 0) with w
+    fixed to a seeded w0 ~ N(0, 1)^k.  form "x": x = (u, v, w) is a rotated x
+    block and k equality rows fix w; form "rows": x is free, the rows
+    (u, v, w) of the identity form a rotated row block and k more rows fix w.
+    Optimum u = v = ||w0|| / sqrt 2, objective sqrt 2 ||w0||; meta holds w0."""
+    rng = np.random.default_rng(seed)
+    w0 = rng.standard_normal(k)
+    n = k + 2
+    c = np.zeros(n)
+    c[:2] = 1.0
+    fix_r = np.arange(k, dtype=np.int64)
+    fix_c = 2 + np.arange(k, dtype=np.int64)
+    if form == "x":
+        rp, ci, v = csr_from_coo(k, n, fix_r, fix_c, np.ones(k))
+        return Instance(n=n, m=k, n_box=0, row_ptr=rp, col=ci, val=v, c=c, h=w0.copy(),
+                        l=np.zeros(0), u=np.zeros(0),
+                        xcone_type=np.array([RSOC], np.int32), xcone_dim=np.array([n], np.int64),
+                        rcone_type=np.array([ZERO], np.int32), rcone_dim=np.array([k], np.int64),
+                        name=f"rsoc_x_{k}", meta=dict(w0=w0))
+    rows = np.concatenate([np.arange(n), n + fix_r])
+    cols = np.concatenate([np.arange(n), fix_c])
+    rp, ci, v = csr_from_coo(n + k, n, rows, cols, np.ones(n + k))
+    h = np.concatenate([np.zeros(n), w0])
+    return Instance(n=n, m=n + k, n_box=0, row_ptr=rp, col=ci, val=v, c=c, h=h,
+                    l=np.zeros(0), u=np.zeros(0),
+                    xcone_type=np.array([FREE], np.int32), xcone_dim=np.array([n], np.int64),
+                    rcone_type=np.array([RSOC, ZERO], np.int32), rcone_dim=np.array([n, k], np.int64),
+                    name=f"rsoc_rows_{k}", meta=dict(w0=w0))
