@@ -501,13 +501,20 @@ def fisher_market(seed, buyers=100, goods=5000, density=0.2, supply=0.25):
                               u_row_ptr=urp, u_col=uci, u_val=uval))
 
 
-def lasso(seed, rows=10_000, cols=100_000, density=1e-4, rotated=False):
+def lasso(seed, rows=10_000, cols=100_000, density=1e-4, form="soc_rows", balance=False):
     """Lasso min ||A x - b||^2 + lambda ||x||_1 in the SOCP form of the paper's
     appendix: variables [w, r, y (rows), x1 (cols), x2 (cols)],
     min 2 r + lambda 1^T (x1 + x2)  s.t.  w = 1,  y - A x1 + A x2 = -b,
-    ((w + r)/sqrt 2, (w - r)/sqrt 2, y) in SOC(rows + 2),  x1, x2 >= 0;
-    with rotated=True the last block is written as (w, r, y) in the rotated
-    cone (RSOC: 2 w r >= ||y||^2), the same set.
+    ((w + r)/sqrt 2, (w - r)/sqrt 2, y) in SOC(rows + 2),  x1, x2 >= 0.
+    form "soc_rows": the cone constraint as rows+2 rows of G (the appendix's
+    form); "rsoc_rows": the same rows written as (w, r, y) in the rotated cone
+    (RSOC: 2 w r >= ||y||^2), the same set; "rsoc_x": (w, r, y) is a rotated
+    x block, so the rows are only the 1 + rows equalities.
+    balance=True fixes w to alpha = ||b|| / sqrt 2 instead of 1 and puts 2 alpha
+    on r in the objective: (alpha w, r / alpha, y) is in the rotated cone
+    exactly when (w, r, y) is, so the problem and its x1, x2, y are unchanged,
+    while w and r (about ||y||^2 / 2 at the optimum) are brought to the same
+    scale; meta["alpha"] holds the factor (1 without balancing).
     A has the given density with U[0,1] entries; b = A x~ + 1e-6, x~ ~ N(0,1)
     with half of its entries set to zero; lambda = ||A^T b||_inf.  No planted
     optimum."""
@@ -526,24 +533,31 @@ def lasso(seed, rows=10_000, cols=100_000, density=1e-4, rotated=False):
     C = [np.array([0]), 2 + np.arange(m), 2 + m + aci.astype(np.int64), 2 + m + n + aci.astype(np.int64),
          np.array([0, 1, 0, 1]), 2 + np.arange(m)]
     V = [np.ones(1), np.ones(m), -aval, aval, np.array([s2, s2, s2, -s2]), np.ones(m)]
-    if rotated:
+    if form not in ("soc_rows", "rsoc_rows", "rsoc_x"):
+        raise ValueError(form)
+    if form == "rsoc_rows":
         R[4], C[4], V[4] = np.array([1 + m, 2 + m]), np.array([0, 1]), np.ones(2)
-    M = 1 + m + m + 2
+    if form == "rsoc_x":
+        R, C, V = R[:4], C[:4], V[:4]
+    M = 1 + m + (0 if form == "rsoc_x" else m + 2)
     rp, ci, v = csr_from_coo(M, N, np.concatenate(R), np.concatenate(C), np.concatenate(V))
+    alpha = float(np.linalg.norm(b) / np.sqrt(2.0)) if balance and m else 1.0
     h = np.zeros(M)
-    h[0] = 1.0
+    h[0] = alpha
     h[1:1 + m] = -b
     c = np.zeros(N)
-    c[1] = 2.0
+    c[1] = 2.0 * alpha
     c[2 + m:] = lam
     return Instance(n=N, m=M, n_box=0, row_ptr=rp, col=ci, val=v, c=c, h=h,
                     l=np.zeros(0), u=np.zeros(0),
-                    xcone_type=np.array([FREE, NONNEG], np.int32),
+                    xcone_type=np.array([RSOC if form == "rsoc_x" else FREE, NONNEG], np.int32),
                     xcone_dim=np.array([2 + m, 2 * n], np.int64),
-                    rcone_type=np.array([ZERO, RSOC if rotated else SOC], np.int32),
-                    rcone_dim=np.array([1 + m, m + 2], np.int64),
-                    name=f"lasso_m{m}_n{n}" + ("_rsoc" if rotated else ""),
-                    meta=dict(rows=m, cols=n, a_nnz=int(aval.size), lam=lam, b=b,
+                    rcone_type=np.array([ZERO] if form == "rsoc_x" else
+                                        [ZERO, RSOC if form == "rsoc_rows" else SOC], np.int32),
+                    rcone_dim=np.array([1 + m] if form == "rsoc_x" else [1 + m, m + 2], np.int64),
+                    name=f"lasso_m{m}_n{n}" + ("" if form == "soc_rows" else "_" + form)
+                    + ("_balanced" if balance else ""),
+                    meta=dict(rows=m, cols=n, a_nnz=int(aval.size), lam=lam, b=b, alpha=alpha,
                               a_row_ptr=arp, a_col=aci, a_val=aval))
 
 

@@ -107,6 +107,9 @@ def lasso_optimality_errors(inst, z):
     m, n = inst.meta["rows"], inst.meta["cols"]
     arp, aci, aval = inst.meta["a_row_ptr"], inst.meta["a_col"], inst.meta["a_val"]
     b, lam = inst.meta["b"], inst.meta["lam"]
+    al = inst.meta.get("alpha", 1.0)   # balanced form: w = alpha w', r = r' / alpha
+    z = np.array(z, dtype=np.float64, copy=True)
+    z[0], z[1] = z[0] / al, z[1] * al
     x = z[2 + m:2 + m + n] - z[2 + m + n:]
     rows = np.repeat(np.arange(m), np.diff(arp))
     ax = np.zeros(m)

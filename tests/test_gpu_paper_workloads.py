@@ -1,7 +1,8 @@
 """GPU solves of the paper's two synthetic workload families (the appendix's
 conic forms of the Fisher market and of the Lasso) against the oracle at
-sizes it finishes quickly, and at the paper's smallest Fisher size against
-the equilibrium conditions, which hold at any size (see helpers).
+sizes it finishes quickly, and at the paper's smallest Fisher and Lasso
+sizes against the equilibrium and optimality conditions, which hold at any
+size (see helpers).
 
 Tolerances: both sides stop at a relative KKT error of 1e-8 (the oracle at
 1e-9), so objectives agree to 1e-7 relative; the equilibrium and optimality
@@ -27,7 +28,13 @@ def say(*a):
 SMALL = [("fisher_8x30", lambda: I.fisher_market(3, buyers=8, goods=30), fisher_equilibrium_errors),
          ("fisher_20x100", lambda: I.fisher_market(5, buyers=20, goods=100), fisher_equilibrium_errors),
          ("lasso_12x60", lambda: I.lasso(4, rows=12, cols=60, density=0.15), lasso_optimality_errors),
-         ("lasso_50x2000", lambda: I.lasso(6, rows=50, cols=2000, density=0.01), lasso_optimality_errors)]
+         ("lasso_50x2000", lambda: I.lasso(6, rows=50, cols=2000, density=0.01), lasso_optimality_errors),
+         # the same Lasso with (w, r, y) as a rotated x block: only the equality rows
+         ("lasso_50x2000_rsoc_x", lambda: I.lasso(6, rows=50, cols=2000, density=0.01, form="rsoc_x"),
+          lasso_optimality_errors),
+         ("lasso_50x2000_rsoc_x_balanced",
+          lambda: I.lasso(6, rows=50, cols=2000, density=0.01, form="rsoc_x", balance=True),
+          lasso_optimality_errors)]
 
 
 @pytest.mark.parametrize("name,maker,check", SMALL, ids=[s[0] for s in SMALL])
@@ -60,3 +67,20 @@ def test_fisher_market_paper_size_equilibrium(pd):
     assert e["clearing"] <= 1e-3 and e["log"] <= 1e-3
     assert e["negative"] <= 1e-6 and e["utility"] <= 1e-4
     assert e["bang_per_buck"] <= 1e-4 and e["budget"] <= 1e-4
+
+
+def test_lasso_paper_size_optimality(pd):
+    """The paper's smallest Lasso (1e4 x 1e5, A density 1e-4), balanced
+    rotated-x form, solved to 1e-6: the subgradient condition of the original
+    problem holds at the returned x = x1 - x2."""
+    inst = I.lasso(2025, rows=10_000, cols=100_000, form="rsoc_x", balance=True)
+    say("lasso paper size", inst.n, inst.m, inst.nnz)
+    prob = pd.Problem(inst)
+    g = prob.solve(pd.settings_default(tol=1e-6, time_limit=60.0))
+    prob.close()
+    assert g["status"] == 0, g["status"]
+    e = lasso_optimality_errors(inst, g["x"])
+    say("  iterations", g["iterations"], e)
+    assert e["w"] <= 1e-5 and e["y"] <= 1e-5 and e["cone"] <= 1e-4, e
+    assert e["stationary_on"] <= 1e-3 and e["stationary_off"] <= 1e-3, e
+

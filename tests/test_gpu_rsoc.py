@@ -84,7 +84,7 @@ def test_project_rejects_scaling(pd):
 def test_products_are_the_callers_matrix(pd, orc):
     """pdcs_spmv of a problem with rotated blocks is the product with the
     caller's G: both maps are undone at the boundary."""
-    inst = I.lasso(3, rows=40, cols=300, density=0.05, rotated=True)
+    inst = I.lasso(3, rows=40, cols=300, density=0.05, form="rsoc_rows")
     # rotated x blocks as well: the Lasso's x with its free part as one block
     # (w, r) rotated and the rest free
     inst.xcone_type = np.array([RSOC, FREE, NONNEG], np.int32)
@@ -149,7 +149,7 @@ def test_rotated_lasso_runs_the_soc_lasso(pd):
     SOC form (same rows, same entries, same bits): same iterations, the same
     x, and y equal up to T on the two rotated rows."""
     a = I.lasso(6, rows=50, cols=2000, density=0.01)
-    b = I.lasso(6, rows=50, cols=2000, density=0.01, rotated=True)
+    b = I.lasso(6, rows=50, cols=2000, density=0.01, form="rsoc_rows")
     s = pd.settings_default(tol=1e-8)
     pa, pb = pd.Problem(a), pd.Problem(b)
     ra, rb = pa.solve(s), pb.solve(s)
@@ -169,7 +169,7 @@ def test_rotated_lasso_runs_the_soc_lasso(pd):
 def test_rotated_lasso_trajectory(pd, orc):
     """Fixed step, 150 iterations with snapshots, starting from a point: the
     starting point, the snapshots and the output all pass through the map."""
-    inst = I.lasso(4, rows=12, cols=60, density=0.15, rotated=True)
+    inst = I.lasso(4, rows=12, cols=60, density=0.15, form="rsoc_rows")
     iters = 150
     rng = np.random.default_rng(9)
     x0, y0 = rng.standard_normal(inst.n), rng.standard_normal(inst.m)
@@ -194,7 +194,7 @@ def test_rotated_lasso_trajectory(pd, orc):
 def test_batch_with_rotated_instances(pd, orc):
     insts = [I.rsoc_min_sum(2, k=5, form="x"), I.lasso(1, rows=5, cols=40, density=0.2),
              I.rsoc_min_sum(5, k=3, form="rows"),
-             I.lasso(4, rows=12, cols=60, density=0.15, rotated=True)]
+             I.lasso(4, rows=12, cols=60, density=0.15, form="rsoc_rows")]
     bt = pd.Batch(insts)
     rs = bt.solve(pd.settings_default(tol=1e-8))
     bt.close()

@@ -91,10 +91,15 @@ def test_min_sum_closed_form(orc, form, seed, k):
         assert rsoc_violation(yb) <= 1e-8 * max(1.0, float(yb @ yb))
 
 
+@pytest.mark.parametrize("form,balance", [("rsoc_rows", False), ("rsoc_x", False), ("rsoc_x", True),
+                                          ("soc_rows", True)])
 @pytest.mark.parametrize("seed,rows,cols,density", [(1, 5, 40, 0.2), (4, 12, 60, 0.15)])
-def test_rotated_lasso_is_the_soc_lasso(orc, seed, rows, cols, density):
+def test_rotated_lasso_is_the_soc_lasso(orc, form, balance, seed, rows, cols, density):
+    """The other forms (and the balanced ones, w fixed to alpha) are the same
+    problem: same optimal value, same optimality conditions."""
     a = I.lasso(seed, rows=rows, cols=cols, density=density)
-    b = I.lasso(seed, rows=rows, cols=cols, density=density, rotated=True)
+    b = I.lasso(seed, rows=rows, cols=cols, density=density, form=form, balance=balance)
+    assert (b.meta["alpha"] != 1.0) == balance
     s = orc.default_settings(tol=1e-9, max_iter=400_000)
     ra, rb = orc.solve(a, s), orc.solve(b, s)
     assert ra["status"] == 0 and rb["status"] == 0
@@ -102,6 +107,10 @@ def test_rotated_lasso_is_the_soc_lasso(orc, seed, rows, cols, density):
     e = lasso_optimality_errors(b, rb["x"])
     assert e["w"] <= 1e-7 and e["y"] <= 1e-6 and e["cone"] <= 1e-6, e
     assert e["stationary_on"] <= 1e-4 and e["stationary_off"] <= 1e-4, e
+    if balance or form == "rsoc_x":
+        # the multipliers of y - A x1 + A x2 = -b are the same in every form
+        assert np.allclose(rb["y"][1:1 + rows], ra["y"][1:1 + rows], rtol=1e-5, atol=1e-7)
+        return
     # the rotated rows' multiplier is that of the SOC form, mapped back:
     # (y_u, y_v) = T (y_a, y_b) with T [[1, 1], [1, -1]] / sqrt 2
     ya = ra["y"][1 + rows:3 + rows]
