@@ -222,8 +222,10 @@ typedef struct pdcs_problem pdcs_problem;
 pdcs_status pdcs_settings_default(pdcs_settings *s);
 
 /* Validates the problem of eq. (1), copies it to the device, builds the CSR
- * of G^T and the cone dispatch plans (the thread-, wavefront- and
- * workgroup-level projection strategies of Section 4, Table 3).
+ * of G^T and the cone dispatch plans (the thread-, wavefront-, workgroup- and
+ * grid-level projection strategies of Section 4, Table 3; an SOC block of at
+ * least 8192 entries is spread over one workgroup per 4096 entries, at most
+ * 64, while the plan holds at most 256 such blocks).
  * Errors: INVALID_ARG, DIMENSION, NONFINITE, OOM, HIP.  On error *out = NULL. */
 pdcs_status pdcs_problem_create(const pdcs_problem_desc *desc, void *hip_stream,
                                 pdcs_problem **out);
@@ -299,7 +301,8 @@ pdcs_status pdcs_kkt(pdcs_problem *p, const double *x_dev, const double *y_dev, 
  * T P_SOC(T v), D = I only).  types and dims are host arrays; d_dev (device,
  * nullable = identity) is the diagonal of D.  dual != 0 projects onto the
  * product of the dual cones instead.
- * Errors: INVALID_ARG, DIMENSION, HIP; NOT_SUPPORTED for RSOC with d_dev. */
+ * Errors: INVALID_ARG, DIMENSION, HIP (also when a grid-level block timed out
+ * waiting for its workgroups); NOT_SUPPORTED for RSOC with d_dev. */
 pdcs_status pdcs_project(int64_t nblocks, const int32_t *types, const int64_t *dims, int dual,
                          const double *d_dev, double *v_dev, void *hip_stream);
 
@@ -310,8 +313,9 @@ pdcs_status pdcs_project(int64_t nblocks, const int32_t *types, const int64_t *d
  * v_dev (device, length sum(dims)) in place on hip_stream without waiting,
  * with d_dev (device, nullable = identity) the diagonal of D and dual != 0
  * for the dual cones.  Calls on one plan must not overlap (they share its
- * scratch).  Errors: INVALID_ARG, DIMENSION, OOM, HIP; NOT_SUPPORTED for a
- * plan with RSOC blocks given a d_dev. */
+ * scratch and the barrier state of its grid-level SOC blocks).  Errors:
+ * INVALID_ARG, DIMENSION, OOM, HIP; NOT_SUPPORTED for a plan with RSOC blocks
+ * given a d_dev. */
 typedef struct pdcs_cones pdcs_cones;
 pdcs_status pdcs_cones_create(int64_t nblocks, const int32_t *types, const int64_t *dims,
                               void *hip_stream, pdcs_cones **out);

@@ -76,6 +76,7 @@ struct HostPlan {
     std::vector<int64_t> soc_off, exp_off;
     std::vector<int32_t> soc_dim;
     std::vector<int64_t> inst_tiles{0};   // tiles of instance b: [inst_tiles[b], inst_tiles[b+1])
+    int64_t n_grid = 0;                    // grid-level SOC blocks
 };
 
 static int elem_kind(int32_t t) {
@@ -98,13 +99,21 @@ static void append_plan(HostPlan &P, int32_t inst, int64_t box0, int64_t n_box, 
     };
     push_run(kTileBox, box0, n_box);
     // SOC size classes: lanes per block 8, 16, 32, 64 (1 entry per lane), then
-    // one wavefront with 2 or 4 entries per lane, then a workgroup per block
-    constexpr int kClasses = 7;
+    // one wavefront with 2 or 4 entries per lane, then a workgroup per block,
+    // then several workgroups per block (grid level)
+    constexpr int kClasses = 8;
     const int class_kind[kClasses] = {kTileSoc8, kTileSoc16, kTileSoc32, kTileSoc64,
-                                      kTileSoc128, kTileSoc256, kTileSocBlock};
-    const int class_per_tile[kClasses] = {32, 16, 8, 4, 4, 4, 1};
-    auto soc_class = [](int64_t d) {
-        return d <= 8 ? 0 : d <= 16 ? 1 : d <= 32 ? 2 : d <= 64 ? 3 : d <= 128 ? 4 : d <= 256 ? 5 : 6;
+                                      kTileSoc128, kTileSoc256, kTileSocBlock, kTileSocGrid};
+    const int class_per_tile[kClasses] = {32, 16, 8, 4, 4, 4, 1, 1};
+    // The grid level pays for its barriers only while the large blocks alone
+    // cannot fill the chip: with more than kSocGridMaxBlocks of them (one
+    // workgroup each already covers every CU) they stay at the workgroup level.
+    int64_t n_large = 0;
+    for (int64_t b = 0; b < nblk; ++b) n_large += types[b] == kSoc && dims[b] >= kSocGridMin;
+    const bool grid = n_large <= kSocGridMaxBlocks;
+    auto soc_class = [grid](int64_t d) {
+        return d <= 8 ? 0 : d <= 16 ? 1 : d <= 32 ? 2 : d <= 64 ? 3 : d <= 128 ? 4 : d <= 256 ? 5
+               : (d < kSocGridMin || !grid) ? 6 : 7;
     };
     std::vector<std::pair<int64_t, int64_t>> soc[kClasses];
     std::vector<int64_t> ep, ed;
@@ -131,11 +140,22 @@ static void append_plan(HostPlan &P, int32_t inst, int64_t box0, int64_t n_box, 
         off += d;
     }
     if (run_len) push_run(run_kind, run_start, run_len);
-    // largest classes first: they run longest
+    // largest classes first: they run longest.  A grid-level block becomes G
+    // consecutive tiles, one per part, so its workgroups are dispatched together.
     for (int c = kClasses - 1; c >= 0; --c) {
         const int64_t first = (int64_t)P.soc_off.size();
         for (auto &p : soc[c]) P.soc_off.push_back(p.first), P.soc_dim.push_back((int32_t)p.second);
         const int64_t cnt = (int64_t)soc[c].size();
+        if (class_kind[c] == kTileSocGrid) {
+            for (int64_t i = 0; i < cnt; ++i) {
+                const int64_t d = soc[c][i].second;
+                const int G = (int)std::min<int64_t>(kSocGridMaxParts, (d + kSocGridChunk - 1) / kSocGridChunk);
+                for (int p = 0; p < G; ++p)
+                    P.tiles.push_back(Tile{kTileSocGrid, p + 256 * G, first + i, inst, (int32_t)P.n_grid});
+                ++P.n_grid;
+            }
+            continue;
+        }
         for (int64_t i = 0; i < cnt; i += class_per_tile[c])
             P.tiles.push_back(tile(class_kind[c], std::min<int64_t>(class_per_tile[c], cnt - i), first + i));
     }
@@ -171,12 +191,28 @@ static ConePlan upload_plan(DevMem &mem, const HostPlan &H, hipStream_t s) {
     h2d(P.exp_off, H.exp_off.data(), (int64_t)H.exp_off.size(), s);
     P.n_soc = (int64_t)H.soc_off.size();
     P.n_exp = (int64_t)H.exp_off.size();
+    P.n_grid = H.n_grid;
+    P.grid_ctr = mem.alloc<unsigned long long>(P.n_grid);
+    P.grid_part = mem.alloc<double>(P.n_grid * 2 * kSocGridMaxParts * 3);
+    P.grid_err = mem.alloc<int>(1);
+    PDCS_HIP(hipMemsetAsync(P.grid_ctr, 0, sizeof(unsigned long long) * (size_t)std::max<int64_t>(P.n_grid, 1), s));
+    PDCS_HIP(hipMemsetAsync(P.grid_err, 0, sizeof(int), s));
     if (H.inst_tiles.size() > 2) {   // a batch: per-instance tile ranges
         P.inst_tiles = mem.alloc<int64_t>((int64_t)H.inst_tiles.size());
         h2d(P.inst_tiles, H.inst_tiles.data(), (int64_t)H.inst_tiles.size(), s);
     }
     PDCS_HIP(hipStreamSynchronize(s));  // the host vectors die with the caller's frame
     return P;
+}
+
+// A barrier of a grid-level SOC block that timed out leaves the plan's flag
+// set (the projections of that launch are then not valid): report it.
+static void check_grid(const ConePlan &pl, hipStream_t s) {
+    if (pl.n_grid == 0) return;
+    int e = 0;
+    d2h(&e, pl.grid_err, 1, s);
+    PDCS_HIP(hipStreamSynchronize(s));
+    if (e) fail(PDCS_ERR_HIP, "a grid-level SOC projection timed out waiting for its workgroups");
 }
 
 // Product layouts by code: 0 = default, -1 = CSR-stream, L > 0 = row-split
@@ -1748,6 +1784,8 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
         tr->count = cnt;
     }
     PDCS_HIP(hipStreamSynchronize(s));
+    check_grid(P->planX, s);
+    check_grid(P->planY, s);
     P->snaps_written = snap;
     const double solve_s = std::chrono::duration<double>(clk::now() - t_iter).count();
     for (int64_t b = 0; b < B; ++b) {
@@ -2058,6 +2096,7 @@ pdcs_status pdcs_project(int64_t nblocks, const int32_t *types, const int64_t *d
         pass_project(plan, dual != 0, ProjArgs{v_dev, d_dev}, part, s);
         rotate_pairs(v_dev, rot_dev, (int64_t)rot.size(), 0, s);
         PDCS_HIP(hipStreamSynchronize(s));
+        check_grid(plan, s);
     });
 }
 

@@ -308,25 +308,31 @@ __device__ __forceinline__ void store_ld(const Op &op, int64_t j, const Ld &l, d
 }
 
 // ------------------------------------------------- workgroup-per-SOC block
-// The reductions over the block (read-only loops) are unrolled by 4 so that a
-// thread's loads of the scratch and scale vectors are issued together.
-template <class Op>
-__device__ void soc_block(Op &op, int64_t off, int dim, Acc &acc, double *root) {
+// The workgroup projects entries [lo, hi) of the block at `off` (the whole
+// block for the workgroup class, one part for the grid class); every sum over
+// the block goes through red.sum, which returns the block total to every
+// thread.  The reductions over the block (read-only loops) are unrolled by 4
+// so that a thread's loads of the scratch and scale vectors are issued
+// together.
+template <class Op, class Red>
+__device__ void soc_block_range(Op &op, int64_t off, int dim, int lo, int hi, Acc &acc,
+                                double *root, Red &red) {
     double *buf = op.scratch();
     const int tid = threadIdx.x;
-    for (int e = tid; e < dim; e += kBlock) buf[off + e] = op.load(off + e);
+    for (int e = lo + tid; e < hi; e += kBlock) buf[off + e] = op.load(off + e);
     __syncthreads();
-    const double t = buf[off];
+    const double t = lo == 0 ? buf[off] : op.load(off);
     const double d0 = op.scale(off);
+    const int e0 = (lo == 0 ? 1 : lo) + tid;
     double sums[3] = {0.0, 0.0, 0.0};
 #pragma unroll 4
-    for (int e = 1 + tid; e < dim; e += kBlock) {
+    for (int e = e0; e < hi; e += kBlock) {
         const double x = buf[off + e], dh = op.scale(off + e) / d0;
         sums[0] += (dh * x) * (dh * x);
         sums[1] += (x / dh) * (x / dh);
         sums[2] += x * x;
     }
-    block_sum_all<3>(sums);
+    red.sum(sums);
     const double nd = sqrt(sums[0]), ndi = sqrt(sums[1]), nx2 = sums[2];
     int cs;
     double s = 0.0;
@@ -337,30 +343,30 @@ __device__ void soc_block(Op &op, int64_t off, int dim, Acc &acc, double *root) 
     } else if (t == 0.0) {
         cs = 3;
         double q2[1] = {0.0};
-    #pragma unroll 4
-    for (int e = 1 + tid; e < dim; e += kBlock) {
+#pragma unroll 4
+        for (int e = e0; e < hi; e += kBlock) {
             const double x = buf[off + e], dh = op.scale(off + e) / d0;
             const double q = x / (dh + 1.0 / dh);
             q2[0] += q * q;
         }
-        block_sum_all<1>(q2);
+        red.sum(q2);
         s = sqrt(q2[0]);
     } else {
         cs = 4;
-        const double lo = t > 0.0 ? t : 0.0, hi = sqrt(t * t + nx2);
-        double xpos = lo, xneg = hi;
+        const double lo_s = t > 0.0 ? t : 0.0, hi_s = sqrt(t * t + nx2);
+        double xpos = lo_s, xneg = hi_s;
         s = 0.5 * (t + sqrt(nx2));
-        if (!(s > lo && s < hi)) s = 0.5 * (lo + hi);
+        if (!(s > lo_s && s < hi_s)) s = 0.5 * (lo_s + hi_s);
         if (root) {
             const double g = *root;   // root of an earlier, nearby input
-            if (g > lo && g < hi) s = g;
+            if (g > lo_s && g < hi_s) s = g;
         }
-        double dxold = hi - lo, dx = dxold;
+        double dxold = hi_s - lo_s, dx = dxold;
         auto eval = [&](double ss, double &f, double &df) {
             const double a = 1.0 - t / ss;
             double g[2] = {0.0, 0.0};
-        #pragma unroll 4
-    for (int e = 1 + tid; e < dim; e += kBlock) {
+#pragma unroll 4
+            for (int e = e0; e < hi; e += kBlock) {
                 const double x = buf[off + e], dh = op.scale(off + e) / d0;
                 const double xd = x * dh;
                 const double iq = 1.0 / (dh * dh + a);
@@ -368,7 +374,7 @@ __device__ void soc_block(Op &op, int64_t off, int dim, Acc &acc, double *root) 
                 g[0] += u;
                 g[1] += u * iq;
             }
-            block_sum_all<2>(g);
+            red.sum(g);
             f = g[0] - ss * ss;
             df = -2.0 * (t / (ss * ss)) * g[1] - 2.0 * ss;
         };
@@ -395,10 +401,13 @@ __device__ void soc_block(Op &op, int64_t off, int dim, Acc &acc, double *root) 
             eval(s, f, df);
         }
     }
-    __syncthreads();  // every thread has read buf[off] (t) and *root before they change
-    if (root && cs == 4 && tid == 0) *root = s;
+    // every thread of every part has read buf[off] (t) and *root before they
+    // change: the workgroup barrier here, and for the grid class the barrier
+    // of the first reduction, which the other parts pass only after reading
+    __syncthreads();
+    if (root && cs == 4 && tid == 0 && lo == 0) *root = s;
     const double a = 1.0 - t / s;
-    for (int e = tid; e < dim; e += kBlock) {
+    for (int e = lo + tid; e < hi; e += kBlock) {
         const int64_t j = off + e;
         const double v = buf[j];
         double p;
@@ -414,6 +423,107 @@ __device__ void soc_block(Op &op, int64_t off, int dim, Acc &acc, double *root) 
         }
         op.store(j, v, p, acc);
     }
+}
+
+struct BlockRed {
+    template <int K>
+    __device__ void sum(double (&v)[K]) { block_sum_all<K>(v); }
+};
+
+template <class Op>
+__device__ void soc_block(Op &op, int64_t off, int dim, Acc &acc, double *root) {
+    BlockRed red;
+    soc_block_range(op, off, dim, 0, dim, acc, root, red);
+}
+
+// ------------------------------------ grid level: several workgroups per block
+// A block of dim >= kSocGridMin is cut into G parts of consecutive entries,
+// one workgroup each.  Each sum over the block becomes: block sums per part,
+// written to the part's slot; a barrier of the G workgroups; then every part
+// adds the G slots in part order, so all parts hold the same bits and take
+// the same decisions.  The slots alternate between two rounds: a part writes
+// round r + 2 only after the barrier of round r + 1, which every part passes
+// only after reading round r.
+struct GridSync {
+    unsigned long long *ctr;
+    double *part;
+    int *err;
+};
+
+// about one second of the 100 MHz wall clock
+constexpr long long kGridWaitTicks = 100000000;
+
+// Barrier of the G workgroups of one block.  The counter only grows: the
+// arrivals of a round are the next G values, so the round is complete when
+// the counter reaches the next multiple of G.  A wait past kGridWaitTicks (a
+// part that never arrives) sets the error flag and returns false; the caller
+// then stops waiting.
+__device__ bool grid_barrier(unsigned long long *ctr, int G, int *err) {
+    __shared__ int ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();   // this part's slot before its arrival
+        const unsigned long long a = atomicAdd(ctr, 1ull);
+        const unsigned long long target = (a / (unsigned long long)G + 1ull) * (unsigned long long)G;
+        const long long t0 = wall_clock64();
+        int good = 1;
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (wall_clock64() - t0 > kGridWaitTicks) {
+                atomicOr(err, 1);
+                good = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();   // the other parts' slots after their arrivals
+        ok = good;
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+struct GridRed {
+    GridSync g;
+    int slot, part, parts, round;
+    bool ok;
+    template <int K>
+    __device__ void sum(double (&v)[K]) {
+        __shared__ double sh[kSocGridMaxParts * 3];
+        block_sum_all<K>(v);
+        double *buf = g.part + ((int64_t)slot * 2 + (round & 1)) * (kSocGridMaxParts * 3);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                __hip_atomic_store(buf + part * 3 + k, v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (ok) ok = grid_barrier(g.ctr + slot, parts, g.err);
+        if (threadIdx.x < parts * 3)
+            sh[threadIdx.x] = __hip_atomic_load(buf + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
+            for (int q = 0; q < parts; ++q) s += sh[q * 3 + k];
+            v[k] = s;
+        }
+        __syncthreads();
+        ++round;
+    }
+};
+
+template <class Op>
+__device__ void soc_grid_part(Op &op, const Tile &tl, const int64_t *__restrict__ soc_off,
+                              const int32_t *__restrict__ soc_dim, double *soc_root,
+                              const GridSync &gs, Acc &acc) {
+    const int part = tl.count % 256, parts = tl.count / 256;
+    const int64_t b = tl.start;
+    const int dim = soc_dim[b];
+    const int chunk = (dim + parts - 1) / parts;
+    const int lo = part * chunk, hi = lo + chunk < dim ? lo + chunk : dim;
+    // after a timed-out barrier anywhere, no part waits again
+    const bool ok = __hip_atomic_load(gs.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    GridRed red{gs, tl.pad, part, parts, 0, ok};
+    soc_block_range(op, soc_off[b], dim, lo, hi, acc, soc_root ? soc_root + b : nullptr, red);
 }
 
 // --------------------------------------- lane-group-per-SOC block (dim <= 256)
@@ -461,7 +571,8 @@ __global__ __launch_bounds__(kBlock) void cone_pass_kernel(Op op, const Tile *__
                                                            const int64_t *__restrict__ exp_off,
                                                            double *__restrict__ partials,
                                                            double *__restrict__ soc_root,
-                                                           double *__restrict__ exp_root) {
+                                                           double *__restrict__ exp_root,
+                                                           GridSync gs) {
     const Tile tl = tiles[blockIdx.x];
     op.begin(tl.inst);
     if (op.skip()) return;
@@ -519,6 +630,9 @@ __global__ __launch_bounds__(kBlock) void cone_pass_kernel(Op op, const Tile *__
         soc_block(op, soc_off[tl.start], soc_dim[tl.start], acc,
                   soc_root ? soc_root + tl.start : nullptr);
         break;
+    case kTileSocGrid:
+        soc_grid_part(op, tl, soc_off, soc_dim, soc_root, gs, acc);
+        break;
     case kTileExp:
     case kTileExpDual:
         if (tid < tl.count) {
@@ -547,7 +661,8 @@ static void launch(const ConePlan &p, const Op &op, double *partials, hipStream_
     if (p.ntiles == 0) return;
     hipLaunchKernelGGL((cone_pass_kernel<Op, DUAL>), dim3((unsigned)p.ntiles), dim3(kBlock), 0, s,
                        op, p.tiles, p.soc_off, p.soc_dim, p.exp_off, partials,
-                       Op::kWarm ? p.soc_root : nullptr, Op::kWarm ? p.exp_root : nullptr);
+                       Op::kWarm ? p.soc_root : nullptr, Op::kWarm ? p.exp_root : nullptr,
+                       GridSync{p.grid_ctr, p.grid_part, p.grid_err});
     PDCS_HIP(hipGetLastError());
 }
 

@@ -20,6 +20,12 @@ constexpr int kSocWaveMax = 256;     // SOC blocks up to this dim: a lane group 
 constexpr int kElemPerTile = 2048;   // entries per elementwise tile
 constexpr int kExpPerTile = 64;      // exponential cones per tile (one thread each)
 constexpr int kPartials = 6;         // per-tile partial slots: 3 sums, 3 maxima
+// SOC blocks of at least kSocGridMin entries are spread over several
+// workgroups (one per kSocGridChunk entries, at most kSocGridMaxParts)
+constexpr int kSocGridMin = 8192;
+constexpr int kSocGridChunk = 4096;
+constexpr int kSocGridMaxParts = 64;
+constexpr int kSocGridMaxBlocks = 256;   // more large blocks than this: one workgroup each
 
 // cone type codes of the C ABI
 enum ConeType : int32_t { kZero = 0, kFree = 1, kNonneg = 2, kSoc = 3, kExp = 4, kExpDual = 5,
@@ -39,7 +45,9 @@ enum TileKind : int32_t {
     kTileSoc32 = 10,     // dim <= 32
     kTileSoc64 = 11,     // dim <= 64, one wavefront each
     kTileSoc128 = 12,    // dim <= 128, one wavefront, 2 entries per lane
-    kTileSoc256 = 13     // dim <= 256, one wavefront, 4 entries per lane
+    kTileSoc256 = 13,    // dim <= 256, one wavefront, 4 entries per lane
+    kTileSocGrid = 14    // one part of an SOC block of dim >= kSocGridMin (start = block,
+                         // count = part + 256 * parts, pad = grid slot)
 };
 
 struct Tile {
@@ -61,6 +69,13 @@ struct ConePlan {
     double *soc_root = nullptr;   // last case-4 root per SOC block (s), NaN = none
     double *exp_root = nullptr;   // last case-4 root per exp block (rho), NaN = none
     int64_t *inst_tiles = nullptr;  // [B+1]: tiles of instance b are [inst_tiles[b], inst_tiles[b+1])
+    // grid-level SOC blocks (slots): a barrier counter each (it only grows),
+    // two rounds of per-part partial sums [slot][round][part][3], and a
+    // sticky flag set when a barrier wait timed out
+    int64_t n_grid = 0;
+    unsigned long long *grid_ctr = nullptr;
+    double *grid_part = nullptr;
+    int *grid_err = nullptr;
 };
 
 // Instance of each entry of a batch (null for a single problem: instance 0).

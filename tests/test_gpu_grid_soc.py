@@ -1,0 +1,159 @@
+"""GPU parity of the grid-level SOC class (Section 4: blocks of at least 8192
+entries are projected by several workgroups, one per 4096 entries, that
+exchange their partial sums) against the oracle.
+
+Tolerances: projections as the other projection tests (1e-12 of the block's
+norm; the parts add the block's sums in another order than one workgroup);
+solves against closed forms and the oracle as the other solve tests;
+trajectories within 1e-8 of the iterate norm (two summation orders)."""
+import numpy as np
+import pytest
+
+from paper_2505_00311_amd import instances as I
+
+from helpers import lasso_optimality_errors
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SOC = 3
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def big_cones(rng):
+    """Grid-class blocks (3 to 64 parts, the largest capped at 64) between smaller
+    blocks, with the four cases of Theorem 1 planted: inside, polar, t = 0,
+    and the root-finding case."""
+    dims = [8192, 40000, 70001, 300000, 700000, 12, 33000, 5000, 65536, 9000]
+    types = [SOC] * len(dims)
+    v = np.concatenate([rng.standard_normal(k) * 10 ** rng.uniform(-2, 2) for k in dims])
+    d = 10 ** rng.uniform(-1, 1, v.size)
+    o = 0
+    for i, k in enumerate(dims):
+        nx = np.linalg.norm(v[o + 1:o + k])
+        if i == 1:
+            v[o] = 2.0 * nx * 10.0          # inside (case 2, with the scaling)
+        elif i == 2:
+            v[o] = -2.0 * nx * 10.0         # polar (case 1)
+        elif i == 3:
+            v[o] = 0.0                      # t = 0 (case 3)
+        o += k
+    return types, dims, v, d
+
+
+@pytest.mark.parametrize("dual", [False, True])
+@pytest.mark.parametrize("scaled", [False, True])
+def test_grid_projection_matches_oracle(pd, orc, dual, scaled):
+    rng = np.random.default_rng(3 + dual + 2 * scaled)
+    types, dims, v, d = big_cones(rng)
+    say("grid projection", dual, scaled, v.size)
+    ref = orc.proj_blocks(types, dims, v, d if scaled else None, dual=dual)
+    vd = dev(v)
+    pd.project(types, dims, vd, dev(d) if scaled else None, dual=dual)
+    got = vd.cpu().numpy()
+    o = 0
+    for k in dims:
+        sc = max(1.0, np.linalg.norm(v[o:o + k]))
+        err = np.abs(got[o:o + k] - ref[o:o + k]).max() / sc
+        assert err <= 1e-12, (k, err)
+        o += k
+
+
+def test_grid_projection_repeats_bit_for_bit(pd):
+    """One plan, five projections in a row (the barrier counters keep
+    growing across launches): the same bits each time, and the same as a
+    fresh one-shot projection."""
+    rng = np.random.default_rng(8)
+    types, dims, v, d = big_cones(rng)
+    cones = pd.Cones(types, dims)
+    dd = dev(d)
+    outs = []
+    for _ in range(5):
+        vd = dev(v)
+        cones.project(vd, dd)
+        torch.cuda.synchronize()
+        outs.append(vd.cpu().numpy())
+    cones.close()
+    one = dev(v)
+    pd.project(types, dims, one, dd)
+    for o in outs[1:] + [one.cpu().numpy()]:
+        assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("form", ["x", "rows"])
+def test_grid_block_solve_closed_form(pd, orc, form):
+    """min u + v over 2 u v >= ||w0||^2 with a 50002-entry rotated block (a
+    13-part grid-level SOC after the map): closed form and the oracle."""
+    inst = I.rsoc_min_sum(21, k=50000, form=form)
+    say("grid closed form", form, inst.n, inst.m)
+    prob = pd.Problem(inst)
+    g = prob.solve(pd.settings_default(tol=1e-9))
+    prob.close()
+    o = orc.solve(inst, orc.default_settings(tol=1e-9, max_iter=200_000))
+    assert g["status"] == 0 and o["status"] == 0
+    w0 = inst.meta["w0"]
+    assert g["pobj"] == pytest.approx(np.sqrt(2.0) * np.linalg.norm(w0), rel=1e-7)
+    assert g["pobj"] == pytest.approx(o["pobj"], rel=1e-7)
+    assert np.allclose(g["x"], o["x"], rtol=1e-5, atol=1e-7)
+
+
+def test_grid_block_trajectory(pd, orc):
+    """Fixed step, 100 iterations with snapshots on the rows form with a
+    40002-entry block: iterates against the oracle's."""
+    inst = I.rsoc_min_sum(22, k=40000, form="rows")
+    iters = 100
+    s = pd.settings_default(max_iter=iters, step_mode=1)
+    so = orc.default_settings(max_iter=iters, step_mode=1)
+    snaps = np.arange(1, iters + 1)
+    prob = pd.Problem(inst)
+    r = prob.solve(s, log_cap=iters, snap_iters=snaps)
+    prob.close()
+    o = orc.solve(inst, so, log_cap=iters, snap_iters=snaps)
+    gl, ol = r["log"], o["log"]
+    assert np.array_equal(gl["check_code"], ol["check_code"])
+    errs = [np.linalg.norm(np.concatenate([gl["snap_x"][i] - ol["snap_x"][i],
+                                           gl["snap_y"][i] - ol["snap_y"][i]]))
+            / max(1.0, np.linalg.norm(np.concatenate([ol["snap_x"][i], ol["snap_y"][i]])))
+            for i in range(iters)]
+    say("  worst relative iterate difference", max(errs))
+    assert max(errs) <= 1e-8
+
+
+def test_lasso_7e4_optimality(pd):
+    """The paper's 7e4 x 7e5 Lasso (balanced, rotated x block of 70002
+    entries: an 18-part grid block) solved to 1e-6 meets the optimality
+    conditions of the original problem."""
+    inst = I.lasso(2026, rows=70_000, cols=700_000, form="rsoc_x", balance=True)
+    say("lasso 7e4", inst.n, inst.m, inst.nnz)
+    prob = pd.Problem(inst)
+    g = prob.solve(pd.settings_default(tol=1e-6, time_limit=60.0))
+    prob.close()
+    assert g["status"] == 0, g["status"]
+    e = lasso_optimality_errors(inst, g["x"])
+    say("  iterations", g["iterations"], e)
+    assert e["w"] <= 1e-5 and e["y"] <= 1e-5 and e["cone"] <= 1e-4, e
+    assert e["stationary_on"] <= 1e-3 and e["stationary_off"] <= 1e-3, e
+
+
+def test_many_large_blocks_match_oracle(pd, orc):
+    """300 blocks of 9000 entries: more large blocks than the grid level
+    takes (they stay at one workgroup each), against the oracle."""
+    rng = np.random.default_rng(12)
+    dims = [9000] * 300
+    v = rng.standard_normal(sum(dims))
+    d = 10 ** rng.uniform(-1, 1, v.size)
+    ref = orc.proj_blocks([SOC] * 300, dims, v, d)
+    vd = dev(v)
+    pd.project([SOC] * 300, dims, vd, dev(d))
+    got = vd.cpu().numpy()
+    for o in range(0, v.size, 9000):
+        sc = max(1.0, np.linalg.norm(v[o:o + 9000]))
+        assert np.abs(got[o:o + 9000] - ref[o:o + 9000]).max() / sc <= 1e-12
