@@ -156,7 +156,13 @@ def batched_form(pdcs, instances, torch, count):
             "speedup_iter_throughput": round(tp_b / tp_s, 3)}
 
 
-def paper_workloads(pdcs, instances, torch):
+# the paper's H100 times for its larger Lasso sizes (rows, cols): 1e-3, 1e-6
+PAPER_LASSO_S = {(400_000, 7_000_000): {"1e-3": 120.0, "1e-6": 260.0},
+                 (700_000, 7_000_000): {"1e-3": 320.0, "1e-6": 520.0},
+                 (750_000, 7_500_000): {"1e-3": 470.0, "1e-6": 600.0}}
+
+
+def paper_workloads(pdcs, instances, torch, extra_lasso=()):
     """The paper's two synthetic families: the Fisher market (100 buyers, 5000
     goods, U density 0.2) and the Lasso at its two smaller sizes (1e4 x 1e5 and
     7e4 x 7e5, A density 1e-4), solved from cold to 1e-3 and 1e-6.  The Lasso
@@ -164,15 +170,22 @@ def paper_workloads(pdcs, instances, torch):
     w fixed to alpha = ||b|| / sqrt 2 (the same problem: the block is in the
     cone for any alpha); the appendix's w = 1 is also solved at the smaller
     size, to 1e-3 (capped at 30 s).  The paper's H100 times are context, not a
-    target."""
+    target.  extra_lasso: further (rows, cols) sizes, balanced, to both
+    tolerances (capped at 300 s each)."""
     lasso = lambda rows, bal: instances.lasso(SEED_LASSO, rows=rows, cols=10 * rows, form="rsoc_x", balance=bal)
     cases = [("fisher_market", instances.fisher_market(SEED_FISHER, buyers=100, goods=5000),
               {"1e-3": 15.0, "1e-6": 37.0}, (1e-3, 1e-6), 300.0),
              ("lasso 1e4x1e5", lasso(10_000, True), {"1e-3": 0.071, "1e-6": 0.11}, (1e-3, 1e-6), 60.0),
              ("lasso 7e4x7e5", lasso(70_000, True), {"1e-3": 0.29, "1e-6": 0.84}, (1e-3, 1e-6), 60.0),
              ("lasso 1e4x1e5, w = 1", lasso(10_000, False), {"1e-3": 0.071}, (1e-3,), 30.0)]
+    cases += [(f"lasso {r:.0e}x{c:.0e}", (r, c), PAPER_LASSO_S.get((r, c), {}), (1e-3, 1e-6), 300.0)
+              for r, c in extra_lasso]
     res = {}
     for name, inst, paper, tols, cap in cases:
+        if isinstance(inst, tuple):   # generated only when its turn comes (tens of GB)
+            t0 = time.perf_counter()
+            inst = instances.lasso(SEED_LASSO, rows=inst[0], cols=inst[1], form="rsoc_x", balance=True)
+            log(f"{name}: generated in {time.perf_counter() - t0:.1f}s, G nnz {inst.nnz}")
         prob = pdcs.Problem(inst)
         prob.solve(pdcs.settings_default(max_iter=64))   # scaling and graph
         torch.cuda.synchronize()
@@ -189,6 +202,7 @@ def paper_workloads(pdcs, instances, torch):
                         "kkt": max(r["err_p"], r["err_d"], r["err_gap"])}
             log(f"{name} to {tol:g}: {status}, {r['solve_s']:.2f}s, {r['iterations']} iterations")
         prob.close()
+        del inst
         res[name] = rec
     return res
 
@@ -350,6 +364,10 @@ def main():
     ap.add_argument("--no-paper-workloads", action="store_true")
     ap.add_argument("--no-projection-sweeps", action="store_true")
     ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--lasso-sizes", default="",
+                    help="extra Lasso sizes 'ROWSxCOLS,...' for the paper workloads (the paper's "
+                         "larger ones: 400000x7000000,700000x7000000,750000x7500000; each takes "
+                         "a minute or more)")
     ap.add_argument("--cpu-iters", type=int, default=64)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--m", type=int, default=500_000)
@@ -502,7 +520,8 @@ def main():
         out["warm_start"] = warm_start_form(pdcs, instances, torch, args.family_assets,
                                             args.family_train, args.family_test)
     if not args.no_paper_workloads:
-        out["paper_workloads"] = paper_workloads(pdcs, instances, torch)
+        extra = [tuple(int(v) for v in t.split("x")) for t in args.lasso_sizes.split(",") if t]
+        out["paper_workloads"] = paper_workloads(pdcs, instances, torch, extra)
     if not args.no_projection_sweeps:
         out["projection_sweeps"] = projection_sweeps(pdcs, torch)
     if not args.no_ablation:

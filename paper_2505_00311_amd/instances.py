@@ -104,17 +104,15 @@ def powerlaw_csr(rng, m, n, mean_row_nnz=20, alpha=0.8):
 
 
 def csr_matvec(rp, col, val, x):
+    """A x, each row summed in entry order (bincount adds in input order)."""
     rows = np.repeat(np.arange(rp.size - 1), np.diff(rp))
-    out = np.zeros(rp.size - 1)
-    np.add.at(out, rows, val * x[col])
-    return out
+    return np.bincount(rows, weights=val * x[col], minlength=rp.size - 1).astype(np.float64)
 
 
 def csr_rmatvec(rp, col, val, y, n):
+    """A^T y, each column summed in entry order."""
     rows = np.repeat(np.arange(rp.size - 1), np.diff(rp))
-    out = np.zeros(n)
-    np.add.at(out, col, val * y[rows])
-    return out
+    return np.bincount(col, weights=val * y[rows], minlength=n).astype(np.float64)
 
 
 # ----------------------------------------------------------- planted pairs
@@ -443,8 +441,11 @@ def _sparse_uniform(rng, m, n, density):
     """m x n pattern with about density m n entries (flat positions drawn
     uniformly, repeats merged), values U[0, 1]; CSR."""
     k = int(rng.binomial(m * n, density)) if m * n > 0 else 0
-    flat = np.unique(rng.integers(0, m * n, size=k, dtype=np.int64))
-    return csr_from_coo(m, n, flat // n, flat % n, rng.random(flat.size))
+    flat = np.unique(rng.integers(0, m * n, size=k, dtype=np.int64))   # sorted, no repeats
+    rows = flat // n
+    rp = np.zeros(m + 1, dtype=np.int64)
+    rp[1:] = np.cumsum(np.bincount(rows, minlength=m))
+    return rp, (flat % n).astype(np.int32), rng.random(flat.size)
 
 
 def fisher_market(seed, buyers=100, goods=5000, density=0.2, supply=0.25):
@@ -525,22 +526,40 @@ def lasso(seed, rows=10_000, cols=100_000, density=1e-4, form="soc_rows", balanc
     xt[rng.permutation(n)[: n // 2]] = 0.0
     b = csr_matvec(arp, aci, aval, xt) + 1e-6
     lam = float(np.abs(csr_rmatvec(arp, aci, aval, b, n)).max()) if n else 0.0
-    N = 2 + m + 2 * n
-    ar = np.repeat(np.arange(m, dtype=np.int64), np.diff(arp))
-    s2 = 1.0 / np.sqrt(2.0)
-    R = [np.array([0]), 1 + np.arange(m), 1 + ar, 1 + ar,
-         np.array([1 + m, 1 + m, 2 + m, 2 + m]), 3 + m + np.arange(m)]
-    C = [np.array([0]), 2 + np.arange(m), 2 + m + aci.astype(np.int64), 2 + m + n + aci.astype(np.int64),
-         np.array([0, 1, 0, 1]), 2 + np.arange(m)]
-    V = [np.ones(1), np.ones(m), -aval, aval, np.array([s2, s2, s2, -s2]), np.ones(m)]
     if form not in ("soc_rows", "rsoc_rows", "rsoc_x"):
         raise ValueError(form)
-    if form == "rsoc_rows":
-        R[4], C[4], V[4] = np.array([1 + m, 2 + m]), np.array([0, 1]), np.ones(2)
-    if form == "rsoc_x":
-        R, C, V = R[:4], C[:4], V[:4]
+    N = 2 + m + 2 * n
     M = 1 + m + (0 if form == "rsoc_x" else m + 2)
-    rp, ci, v = csr_from_coo(M, N, np.concatenate(R), np.concatenate(C), np.concatenate(V))
+    # rows in order, columns ascending within each row: w = 1; then per row i
+    # of A: y_i, -A_i on x1, +A_i on x2; then the cone rows
+    s2 = 1.0 / np.sqrt(2.0)
+    alen = np.diff(arp)
+    if form == "soc_rows":
+        cone_c, cone_v, cone_len = [0, 1, 0, 1], [s2, s2, s2, -s2], [2, 2]
+    elif form == "rsoc_rows":
+        cone_c, cone_v, cone_len = [0, 1], [1.0, 1.0], [1, 1]
+    else:
+        cone_c, cone_v, cone_len = [], [], []
+    row_len = np.concatenate([[1], 1 + 2 * alen, cone_len,
+                              np.ones(m if form != "rsoc_x" else 0, np.int64)]).astype(np.int64)
+    rp = np.zeros(M + 1, dtype=np.int64)
+    rp[1:] = np.cumsum(row_len)
+    ci = np.empty(rp[-1], dtype=np.int32)
+    v = np.empty(rp[-1])
+    ci[0], v[0] = 0, 1.0
+    ys = rp[1:1 + m]                                    # first entry of row 1 + i
+    ci[ys], v[ys] = 2 + np.arange(m), 1.0
+    ar = np.repeat(np.arange(m, dtype=np.int64), alen)
+    pos1 = ys[ar] + 1 + (np.arange(arp[-1], dtype=np.int64) - arp[:-1][ar])
+    ci[pos1], v[pos1] = 2 + m + aci, -aval
+    pos2 = pos1 + alen[ar]
+    ci[pos2], v[pos2] = 2 + m + n + aci, aval
+    del ar, pos1, pos2
+    if form != "rsoc_x":
+        c0 = rp[1 + m]
+        ci[c0:c0 + len(cone_c)], v[c0:c0 + len(cone_c)] = cone_c, cone_v
+        tail = rp[3 + m:3 + 2 * m]
+        ci[tail], v[tail] = 2 + np.arange(m), 1.0
     alpha = float(np.linalg.norm(b) / np.sqrt(2.0)) if balance and m else 1.0
     h = np.zeros(M)
     h[0] = alpha
