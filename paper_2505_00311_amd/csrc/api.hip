@@ -922,10 +922,17 @@ static pdcs_problem *create_impl(const pdcs_problem_desc *Ds, int64_t count, voi
     // all held as bounds [l, u]), then the SOC and exponential blocks, each
     // kept whole and rated by its largest degree.  Hot columns then share cache
     // lines.
+    //   Columns with the same rows (the parts x1 - x2 of a split free
+    // variable, say) are gathered by the same rows of G~: placed side by side
+    // they share cache lines in G~x^, and their rows of G~^T read the same
+    // entries of y^.  Outside the hottest units, columns of degree >= 2 are
+    // grouped by a hash of their row lists (a collision only costs locality).
     {
         std::vector<double> ul(n), uu(n);   // the caller's bounds, caller's order
         d2h(ul.data(), P->l, n, s);
         d2h(uu.data(), P->u, n, s);
+        std::vector<int32_t> hci(nnz);      // rows of each column, ascending
+        d2h(hci.data(), P->Gt.ci, nnz, s);
         PDCS_HIP(hipStreamSynchronize(s));
         std::vector<int32_t> perm(n), pos(n);
         std::vector<double> il(n), iu(n);
@@ -953,8 +960,8 @@ static pdcs_problem *create_impl(const pdcs_problem_desc *Ds, int64_t count, voi
 // the hottest 1% of units move to the front, by degree; the others keep
             // their order (sorting them all clusters the long rows of G~^T, which
             // cost the transposed product more than the gathers gained: measured)
-            auto front = [&](std::vector<Unit> &v) {
-                if (v.empty()) return;
+            auto front = [&](std::vector<Unit> &v) -> size_t {
+                if (v.empty()) return 0;
                 std::vector<int64_t> hs;
                 for (auto &u : v) hs.push_back(u.heat);
                 const size_t k = hs.size() / 100;
@@ -963,8 +970,40 @@ static pdcs_problem *create_impl(const pdcs_problem_desc *Ds, int64_t count, voi
                 auto mid = std::stable_partition(v.begin(), v.end(),
                                                  [&](const Unit &u) { return u.heat > thr; });
                 std::stable_sort(v.begin(), mid, hotter);
+                return (size_t)(mid - v.begin());
             };
-            front(elem);
+            auto twins = [&](std::vector<Unit> &v, size_t from) {
+                const size_t cnt = v.size() - from;
+                std::vector<std::pair<uint64_t, uint32_t>> hv;
+                for (size_t i = 0; i < cnt; ++i) {
+                    const Unit &u = v[from + i];
+                    if (u.heat < 2) continue;
+                    const int64_t g = I.x0 + u.start;
+                    uint64_t h = 0x9E3779B97F4A7C15ull ^ (uint64_t)u.heat;
+                    for (int64_t k = hrpt[g]; k < hrpt[g + 1]; ++k) {
+                        h ^= (uint64_t)(uint32_t)hci[k] + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+                        h *= 0xBF58476D1CE4E5B9ull;
+                    }
+                    hv.push_back({h, (uint32_t)i});
+                }
+                if (hv.empty()) return;
+                std::sort(hv.begin(), hv.end());
+                std::vector<int64_t> next(cnt, -1);
+                bool any = false;
+                for (size_t a = 0; a + 1 < hv.size(); ++a)
+                    if (hv[a].first == hv[a + 1].first) next[hv[a].second] = hv[a + 1].second, any = true;
+                if (!any) return;
+                std::vector<Unit> out;
+                out.reserve(cnt);
+                std::vector<char> placed(cnt, 0);
+                for (size_t i = 0; i < cnt; ++i) {
+                    if (placed[i]) continue;
+                    for (int64_t j = (int64_t)i; j >= 0; j = next[j])
+                        if (!placed[j]) out.push_back(v[from + j]), placed[j] = 1;
+                }
+                std::copy(out.begin(), out.end(), v.begin() + from);
+            };
+            twins(elem, front(elem));
             front(blk);
             int64_t q = 0;
             for (const Unit &u : elem) {
