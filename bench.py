@@ -178,7 +178,7 @@ def paper_workloads(pdcs, instances, torch, extra_lasso=()):
              ("lasso 1e4x1e5", lasso(10_000, True), {"1e-3": 0.071, "1e-6": 0.11}, (1e-3, 1e-6), 60.0),
              ("lasso 7e4x7e5", lasso(70_000, True), {"1e-3": 0.29, "1e-6": 0.84}, (1e-3, 1e-6), 60.0),
              ("lasso 1e4x1e5, w = 1", lasso(10_000, False), {"1e-3": 0.071}, (1e-3,), 30.0)]
-    cases += [(f"lasso {r:.0e}x{c:.0e}", (r, c), PAPER_LASSO_S.get((r, c), {}), (1e-3, 1e-6), 300.0)
+    cases += [(f"lasso {r:.2g}x{c:.2g}", (r, c), PAPER_LASSO_S.get((r, c), {}), (1e-3, 1e-6), 300.0)
               for r, c in extra_lasso]
     res = {}
     for name, inst, paper, tols, cap in cases:
