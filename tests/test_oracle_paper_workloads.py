@@ -66,3 +66,45 @@ def test_lasso_optimality(orc, seed, rows, cols, density):
     fi = f(_ista(A, b, lam))
     assert e["objective"] == pytest.approx(fi, rel=1e-7, abs=1e-9)
     assert r["pobj"] == pytest.approx(fi, rel=1e-7, abs=1e-9)
+
+
+@pytest.mark.parametrize("form", ["soc_rows", "rsoc_rows", "rsoc_x"])
+@pytest.mark.parametrize("balance", [False, True])
+def test_lasso_rows_are_the_appendix_constraints(form, balance):
+    """G z - h, for a random z = (w, r, y, x1, x2), written out from the
+    appendix's form: w - alpha; y - A x1 + A x2 + b; then the cone rows
+    ((w + r)/sqrt 2, (w - r)/sqrt 2, y), or (w, r, y) for the rotated rows,
+    or none when the cone is on x.  Also the cone lists, c, and that every
+    row's columns ascend."""
+    inst = I.lasso(5, rows=30, cols=400, density=0.02, form=form, balance=balance)
+    m, n = 30, 400
+    rng = np.random.default_rng(1)
+    z = rng.standard_normal(inst.n)
+    w, r, y, x1, x2 = z[0], z[1], z[2:2 + m], z[2 + m:2 + m + n], z[2 + m + n:]
+    A = np.zeros((m, n))
+    arp, aci, aval = inst.meta["a_row_ptr"], inst.meta["a_col"], inst.meta["a_val"]
+    for i in range(m):
+        A[i, aci[arp[i]:arp[i + 1]]] = aval[arp[i]:arp[i + 1]]
+    al, b = inst.meta["alpha"], inst.meta["b"]
+    want = [[w - al], y - A @ x1 + A @ x2 + b]
+    s2 = 1.0 / np.sqrt(2.0)
+    if form == "soc_rows":
+        want.append([(w + r) * s2, (w - r) * s2])
+        want.append(y)
+    elif form == "rsoc_rows":
+        want.append([w, r])
+        want.append(y)
+    want = np.concatenate(want)
+    G = np.zeros((inst.m, inst.n))
+    for i in range(inst.m):
+        cols = inst.col[inst.row_ptr[i]:inst.row_ptr[i + 1]]
+        assert np.all(np.diff(cols) > 0)
+        G[i, cols] = inst.val[inst.row_ptr[i]:inst.row_ptr[i + 1]]
+    assert np.allclose(G @ z - inst.h, want, rtol=1e-14, atol=1e-12)
+    assert inst.c[1] == 2.0 * al and np.all(inst.c[2 + m:] == inst.meta["lam"]) and inst.c[0] == 0.0
+    assert (al == 1.0) != balance or al == pytest.approx(np.linalg.norm(b) / np.sqrt(2.0))
+    cone = {"soc_rows": I.SOC, "rsoc_rows": I.RSOC}.get(form)
+    if cone is None:
+        assert list(inst.xcone_type) == [I.RSOC, I.NONNEG] and list(inst.rcone_type) == [I.ZERO]
+    else:
+        assert list(inst.xcone_type) == [I.FREE, I.NONNEG] and list(inst.rcone_type) == [I.ZERO, cone]
