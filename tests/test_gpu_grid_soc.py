@@ -157,3 +157,22 @@ def test_many_large_blocks_match_oracle(pd, orc):
     for o in range(0, v.size, 9000):
         sc = max(1.0, np.linalg.norm(v[o:o + 9000]))
         assert np.abs(got[o:o + 9000] - ref[o:o + 9000]).max() / sc <= 1e-12
+
+
+def test_grid_blocks_in_a_batch(pd, orc):
+    """A batch whose instances each hold a grid-level block (one barrier
+    counter per block, the parts of each block consecutive in the plan),
+    beside a plain instance: every instance against its closed form and the
+    oracle."""
+    insts = [I.rsoc_min_sum(31, k=20000, form="x"), I.small_mixed(2),
+             I.rsoc_min_sum(32, k=12000, form="rows"), I.rsoc_min_sum(33, k=30000, form="x")]
+    bt = pd.Batch(insts)
+    rs = bt.solve(pd.settings_default(tol=1e-8))
+    bt.close()
+    for inst, r in zip(insts, rs):
+        say("grid batch", inst.name, r["status"], r["iterations"])
+        assert r["status"] == 0
+        o = orc.solve(inst, orc.default_settings(tol=1e-9, max_iter=200_000))
+        assert r["pobj"] == pytest.approx(o["pobj"], rel=1e-7, abs=1e-8)
+        if "w0" in inst.meta:
+            assert r["pobj"] == pytest.approx(np.sqrt(2.0) * np.linalg.norm(inst.meta["w0"]), rel=1e-7)
