@@ -394,6 +394,7 @@ static int valid_problem(const orc_problem *p) {
     if (p->row_ptr[0] != 0 || p->row_ptr[p->m] != p->nnz) return -1;
     int64_t sx = 0, sr = 0;
     for (int64_t b = 0; b < p->n_xcones; ++b) {
+        if (p->xcone_type[b] < ORC_ZERO || p->xcone_type[b] > ORC_EXP_DUAL) return -3;
         if (p->xcone_dim[b] < 1) return -2;
         if ((p->xcone_type[b] == ORC_EXP || p->xcone_type[b] == ORC_EXP_DUAL) &&
             p->xcone_dim[b] != 3)
@@ -401,6 +402,7 @@ static int valid_problem(const orc_problem *p) {
         sx += p->xcone_dim[b];
     }
     for (int64_t b = 0; b < p->n_rcones; ++b) {
+        if (p->rcone_type[b] < ORC_ZERO || p->rcone_type[b] > ORC_EXP_DUAL) return -3;
         if (p->rcone_dim[b] < 1) return -2;
         if ((p->rcone_type[b] == ORC_EXP || p->rcone_type[b] == ORC_EXP_DUAL) &&
             p->rcone_dim[b] != 3)

@@ -25,7 +25,9 @@
 extern "C" {
 #endif
 
-/* Cone type codes (the disciplined cones of Section 1.2). */
+/* Cone type codes (the disciplined cones of Section 1.2).  Other codes are
+ * rejected (-3).  The rotated second-order cone is rewritten as an SOC by the
+ * Python wrapper before a problem reaches this library. */
 enum {
     ORC_ZERO = 0,     /* {0}^d                                   */
     ORC_FREE = 1,     /* R^d                                     */

@@ -135,3 +135,21 @@ def test_kkt_in_the_callers_form(orc):
     # c - G^T y = (1, 1, -y) must lie in the rotated cone: 2 >= ||y||^2 = 2
     assert rsoc_violation(np.concatenate(lam)) <= 1e-14
     assert k["err_d"] <= 1e-14, k
+
+
+def test_oracle_library_rejects_unknown_cone_types(orc):
+    """The C library rejects cone codes it does not know (the rotated cone
+    only reaches it rewritten as an SOC by the wrapper)."""
+    import ctypes
+    inst = I.rsoc_min_sum(1, k=3, form="x")
+    keep = orc._Keep()
+    P = orc._problem(inst, keep)         # the raw description: one type-6 block
+    x, y = np.empty(inst.n), np.empty(inst.m)
+    info = orc._Info()
+    s = orc.default_settings()
+    rc = orc._lib().orc_solve(ctypes.byref(P), ctypes.byref(s), None, None, 0.0,
+                              x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              y.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              ctypes.byref(info), None)
+    assert rc == -3
+    assert orc.solve(inst)["status"] == 0     # through the wrapper's map
