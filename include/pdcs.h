@@ -147,7 +147,9 @@ typedef struct {
     int32_t autotune;
     /* Batches: 1 hands the instances still running to problems of their own
      * (restarted at their chosen candidate with their primal weight) once they
-     * hold at most 1/8 of the batch's nonzeros (not in the paper). */
+     * hold at most 1/8 of the batch's nonzeros (not in the paper).  Default 0:
+     * the restart at the hand-over can cost a straggler more iterations than
+     * the batch-wide launches cost it. */
     int32_t batch_dropout;
     /* 1: the baseline PDHG the paper compares PDCS with (its appendix on PDHG
      * versus PDCS): step step_fixed / ||G~||_2 on both sides (omega = 1 unless

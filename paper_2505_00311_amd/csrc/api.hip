@@ -1965,7 +1965,7 @@ pdcs_status pdcs_settings_default(pdcs_settings *s) {
     s->polish_tol = 1e-5;
     s->polish_stall = 8;
     s->autotune = 0;
-    s->batch_dropout = 1;
+    s->batch_dropout = 0;
     s->plain_pdhg = 0;
     return PDCS_OK;
 }

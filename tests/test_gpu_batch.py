@@ -23,11 +23,11 @@ def mix():
 OBJ_REL = 3e-5
 
 
-@pytest.mark.parametrize("autotune", [0, 1])
-def test_batch_solves_each_instance_to_tolerance(pd, orc, autotune):
+@pytest.mark.parametrize("autotune,dropout", [(0, 0), (1, 0), (1, 1)])
+def test_batch_solves_each_instance_to_tolerance(pd, orc, autotune, dropout):
     insts = mix()
     batch = pd.Batch(insts)
-    res = batch.solve(pd.settings_default(autotune=autotune))
+    res = batch.solve(pd.settings_default(autotune=autotune, batch_dropout=dropout))
     for inst, r in zip(insts, res):
         assert r["status"] == 0, (inst.name, r["status"])
         k = orc.kkt(inst, r["x"], r["y"])
