@@ -382,8 +382,8 @@ def main():
                          "for scaling HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "design is described in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the sharded "
+              "multi-GPU path is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -1,7 +1,7 @@
 """The learned warm start end to end on a small member of the parametric
 portfolio family: batched solves give the training targets, the network is
 trained on the GPU, and on held-out parameters its predicted starting points
-are compared with cold starts (the fallback and the judge)."""
+are compared with cold starts (the fallback and the yardstick)."""
 import numpy as np
 import pytest
 
