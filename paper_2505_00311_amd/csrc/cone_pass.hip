@@ -437,8 +437,9 @@ __device__ void soc_block(Op &op, int64_t off, int dim, Acc &acc, double *root) 
 }
 
 // ------------------------------------ grid level: several workgroups per block
-// A block of dim >= kSocGridMin is cut into G parts of consecutive entries,
-// one workgroup each.  Each sum over the block becomes: block sums per part,
+// The grid-level strategy of Section 4 for the largest SOC blocks, inside the
+// pass launch: a block of dim >= kSocGridMin is cut into G parts of
+// consecutive entries, one workgroup each.  Each sum over the block becomes: block sums per part,
 // written to the part's slot; a barrier of the G workgroups; then every part
 // adds the G slots in part order, so all parts hold the same bits and take
 // the same decisions.  The slots alternate between two rounds: a part writes
