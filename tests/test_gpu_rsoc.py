@@ -191,12 +191,15 @@ def test_rotated_lasso_trajectory(pd, orc):
     assert np.allclose(r["x"], o["x"], rtol=1e-8, atol=1e-10)
 
 
-def test_batch_with_rotated_instances(pd, orc):
+@pytest.mark.parametrize("dropout", [0, 1])
+def test_batch_with_rotated_instances(pd, orc, dropout):
+    """With dropout = 1 the instances still running are handed to problems
+    of their own; their answers must still come back in the caller's form."""
     insts = [I.rsoc_min_sum(2, k=5, form="x"), I.lasso(1, rows=5, cols=40, density=0.2),
              I.rsoc_min_sum(5, k=3, form="rows"),
              I.lasso(4, rows=12, cols=60, density=0.15, form="rsoc_rows")]
     bt = pd.Batch(insts)
-    rs = bt.solve(pd.settings_default(tol=1e-8))
+    rs = bt.solve(pd.settings_default(tol=1e-8, batch_dropout=dropout))
     bt.close()
     for inst, r in zip(insts, rs):
         say("batch", inst.name, r["status"], r["iterations"])
