@@ -193,7 +193,7 @@ static ConePlan upload_plan(DevMem &mem, const HostPlan &H, hipStream_t s) {
     P.n_exp = (int64_t)H.exp_off.size();
     P.n_grid = H.n_grid;
     P.grid_ctr = mem.alloc<unsigned long long>(P.n_grid);
-    P.grid_part = mem.alloc<double>(P.n_grid * 2 * kSocGridMaxParts * 3);
+    P.grid_part = mem.alloc<double>(P.n_grid * 2 * kSocGridMaxParts * kSocGridSlot);
     P.grid_err = mem.alloc<int>(1);
     PDCS_HIP(hipMemsetAsync(P.grid_ctr, 0, sizeof(unsigned long long) * (size_t)std::max<int64_t>(P.n_grid, 1), s));
     PDCS_HIP(hipMemsetAsync(P.grid_err, 0, sizeof(int), s));

@@ -324,13 +324,26 @@ __device__ void soc_block_range(Op &op, int64_t off, int dim, int lo, int hi, Ac
     const double t = lo == 0 ? buf[off] : op.load(off);
     const double d0 = op.scale(off);
     const int e0 = (lo == 0 ? 1 : lo) + tid;
-    double sums[3] = {0.0, 0.0, 0.0};
+    // With the root of an earlier, nearby input, the first root-finding
+    // evaluation at it is summed in this same pass (the arithmetic of eval
+    // below, one reduction fewer); it is used when that root is in bracket.
+    const double g0 = root ? *root : 0.0;
+    const bool fuse = g0 > 0.0 && isfinite(g0);
+    const double a0 = fuse ? 1.0 - t / g0 : 0.0;
+    double sums[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
     for (int e = e0; e < hi; e += kBlock) {
         const double x = buf[off + e], dh = op.scale(off + e) / d0;
         sums[0] += (dh * x) * (dh * x);
         sums[1] += (x / dh) * (x / dh);
         sums[2] += x * x;
+        if (fuse) {
+            const double xd = x * dh;
+            const double iq = 1.0 / (dh * dh + a0);
+            const double u = xd * xd * iq * iq;
+            sums[3] += u;
+            sums[4] += u * iq;
+        }
     }
     red.sum(sums);
     const double nd = sqrt(sums[0]), ndi = sqrt(sums[1]), nx2 = sums[2];
@@ -357,10 +370,8 @@ __device__ void soc_block_range(Op &op, int64_t off, int dim, int lo, int hi, Ac
         double xpos = lo_s, xneg = hi_s;
         s = 0.5 * (t + sqrt(nx2));
         if (!(s > lo_s && s < hi_s)) s = 0.5 * (lo_s + hi_s);
-        if (root) {
-            const double g = *root;   // root of an earlier, nearby input
-            if (g > lo_s && g < hi_s) s = g;
-        }
+        const bool warm = fuse && g0 > lo_s && g0 < hi_s;
+        if (warm) s = g0;
         double dxold = hi_s - lo_s, dx = dxold;
         auto eval = [&](double ss, double &f, double &df) {
             const double a = 1.0 - t / ss;
@@ -379,7 +390,12 @@ __device__ void soc_block_range(Op &op, int64_t off, int dim, int lo, int hi, Ac
             df = -2.0 * (t / (ss * ss)) * g[1] - 2.0 * ss;
         };
         double f, df;
-        eval(s, f, df);
+        if (warm) {
+            f = sums[3] - s * s;
+            df = -2.0 * (t / (s * s)) * sums[4] - 2.0 * s;
+        } else {
+            eval(s, f, df);
+        }
         for (int it = 0; it < 100; ++it) {
             if (f == 0.0) break;
             if (f > 0.0)
@@ -489,22 +505,24 @@ struct GridRed {
     bool ok;
     template <int K>
     __device__ void sum(double (&v)[K]) {
-        __shared__ double sh[kSocGridMaxParts * 3];
+        static_assert(K <= kSocGridSlot, "a reduction round holds kSocGridSlot values per part");
+        __shared__ double sh[kSocGridMaxParts * kSocGridSlot];
         block_sum_all<K>(v);
-        double *buf = g.part + ((int64_t)slot * 2 + (round & 1)) * (kSocGridMaxParts * 3);
+        double *buf = g.part + ((int64_t)slot * 2 + (round & 1)) * (kSocGridMaxParts * kSocGridSlot);
         if (threadIdx.x == 0) {
 #pragma unroll
             for (int k = 0; k < K; ++k)
-                __hip_atomic_store(buf + part * 3 + k, v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(buf + part * kSocGridSlot + k, v[k], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
         if (ok) ok = grid_barrier(g.ctr + slot, parts, g.err);
-        if (threadIdx.x < parts * 3)
-            sh[threadIdx.x] = __hip_atomic_load(buf + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int i = threadIdx.x; i < parts * kSocGridSlot; i += kBlock)
+            sh[i] = __hip_atomic_load(buf + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             double s = 0.0;
-            for (int q = 0; q < parts; ++q) s += sh[q * 3 + k];
+            for (int q = 0; q < parts; ++q) s += sh[q * kSocGridSlot + k];
             v[k] = s;
         }
         __syncthreads();

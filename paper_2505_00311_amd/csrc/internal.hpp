@@ -26,6 +26,7 @@ constexpr int kSocGridMin = 8192;
 constexpr int kSocGridChunk = 4096;
 constexpr int kSocGridMaxParts = 64;
 constexpr int kSocGridMaxBlocks = 256;   // more large blocks than this: one workgroup each
+constexpr int kSocGridSlot = 5;          // values per part in one reduction round
 
 // cone type codes of the C ABI
 enum ConeType : int32_t { kZero = 0, kFree = 1, kNonneg = 2, kSoc = 3, kExp = 4, kExpDual = 5,
@@ -70,7 +71,7 @@ struct ConePlan {
     double *exp_root = nullptr;   // last case-4 root per exp block (rho), NaN = none
     int64_t *inst_tiles = nullptr;  // [B+1]: tiles of instance b are [inst_tiles[b], inst_tiles[b+1])
     // grid-level SOC blocks (slots): a barrier counter each (it only grows),
-    // two rounds of per-part partial sums [slot][round][part][3], and a
+    // two rounds of per-part partial sums [slot][round][part][kSocGridSlot], and a
     // sticky flag set when a barrier wait timed out
     int64_t n_grid = 0;
     unsigned long long *grid_ctr = nullptr;
