@@ -327,22 +327,27 @@ __device__ void soc_block_range(Op &op, int64_t off, int dim, int lo, int hi, Ac
     // With the root of an earlier, nearby input, the first root-finding
     // evaluation at it is summed in this same pass (the arithmetic of eval
     // below, one reduction fewer); it is used when that root is in bracket.
+    // Only passes that keep roots (Op::kWarm) have one; the others reduce the
+    // three norms alone.
+    constexpr int K = Op::kWarm ? 5 : 3;
     const double g0 = root ? *root : 0.0;
-    const bool fuse = g0 > 0.0 && isfinite(g0);
+    const bool fuse = K == 5 && g0 > 0.0 && isfinite(g0);
     const double a0 = fuse ? 1.0 - t / g0 : 0.0;
-    double sums[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double sums[K] = {};
 #pragma unroll 4
     for (int e = e0; e < hi; e += kBlock) {
         const double x = buf[off + e], dh = op.scale(off + e) / d0;
         sums[0] += (dh * x) * (dh * x);
         sums[1] += (x / dh) * (x / dh);
         sums[2] += x * x;
-        if (fuse) {
-            const double xd = x * dh;
-            const double iq = 1.0 / (dh * dh + a0);
-            const double u = xd * xd * iq * iq;
-            sums[3] += u;
-            sums[4] += u * iq;
+        if constexpr (K == 5) {
+            if (fuse) {
+                const double xd = x * dh;
+                const double iq = 1.0 / (dh * dh + a0);
+                const double u = xd * xd * iq * iq;
+                sums[3] += u;
+                sums[4] += u * iq;
+            }
         }
     }
     red.sum(sums);
@@ -390,9 +395,13 @@ __device__ void soc_block_range(Op &op, int64_t off, int dim, int lo, int hi, Ac
             df = -2.0 * (t / (ss * ss)) * g[1] - 2.0 * ss;
         };
         double f, df;
-        if (warm) {
-            f = sums[3] - s * s;
-            df = -2.0 * (t / (s * s)) * sums[4] - 2.0 * s;
+        if constexpr (K == 5) {
+            if (warm) {
+                f = sums[3] - s * s;
+                df = -2.0 * (t / (s * s)) * sums[4] - 2.0 * s;
+            } else {
+                eval(s, f, df);
+            }
         } else {
             eval(s, f, df);
         }
