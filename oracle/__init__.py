@@ -46,7 +46,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+            ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
              "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -79,10 +79,32 @@ class _Info(ctypes.Structure):
 class _Trace(ctypes.Structure):
     _fields_ = [("cap", _i64), ("count", _i64), ("attempts", _pi32), ("eta_used", _pd),
                 ("beta", _pd), ("omega", _pd), ("check_code", _pi32), ("check_kkt", _pd),
-                ("n_snap", _i64), ("snap_iter", _pi64), ("snap_x", _pd), ("snap_y", _pd)]
+                ("n_snap", _i64), ("snap_iter", _pi64), ("snap_x", _pd), ("snap_y", _pd),
+                ("replay_count", _i64), ("replay_attempts", _pi32), ("replay_beta", _pd),
+                ("replay_check_code", _pi32), ("margin", _pd)]
 
 
 _lib_handle = None
+
+
+def _declare(L):
+    L.orc_settings_default.argtypes = [ctypes.POINTER(Settings)]
+    L.orc_set_threads.argtypes = [ctypes.c_int]
+    L.orc_set_threads.restype = None
+    L.orc_get_threads.argtypes = []
+    L.orc_proj_soc.argtypes = [_i64, _pd, _pd, _pd]
+    L.orc_proj_exp.argtypes = [_pd, _pd, _pd]
+    L.orc_proj_exp_dual.argtypes = [_pd, _pd, _pd]
+    L.orc_proj_blocks.argtypes = [_i64, _pi32, _pi64, ctypes.c_int, _pd, _pd]
+    L.orc_proj_blocks.restype = None
+    L.orc_spmv.argtypes = [_i64, _pi64, _pi32, _pd, _pd, _pd]
+    L.orc_spmv.restype = None
+    L.orc_scaling.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(Settings), _pd, _pd]
+    L.orc_kkt.argtypes = [ctypes.POINTER(_Problem), _pd, _pd, _pd, _pd, _pd, _pd, _pd]
+    L.orc_onepdhg.argtypes = [ctypes.POINTER(_Problem), _pd, _pd, _dbl, _dbl, _pd, _pd]
+    L.orc_solve.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(Settings), _pd, _pd,
+                            _dbl, _pd, _pd, ctypes.POINTER(_Info), ctypes.POINTER(_Trace)]
+    return L
 
 
 def _lib():
@@ -90,22 +112,22 @@ def _lib():
     if _lib_handle is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build()
-        L = ctypes.CDLL(_LIB)
-        L.orc_settings_default.argtypes = [ctypes.POINTER(Settings)]
-        L.orc_proj_soc.argtypes = [_i64, _pd, _pd, _pd]
-        L.orc_proj_exp.argtypes = [_pd, _pd, _pd]
-        L.orc_proj_exp_dual.argtypes = [_pd, _pd, _pd]
-        L.orc_proj_blocks.argtypes = [_i64, _pi32, _pi64, ctypes.c_int, _pd, _pd]
-        L.orc_proj_blocks.restype = None
-        L.orc_spmv.argtypes = [_i64, _pi64, _pi32, _pd, _pd, _pd]
-        L.orc_spmv.restype = None
-        L.orc_scaling.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(Settings), _pd, _pd]
-        L.orc_kkt.argtypes = [ctypes.POINTER(_Problem), _pd, _pd, _pd, _pd, _pd, _pd, _pd]
-        L.orc_onepdhg.argtypes = [ctypes.POINTER(_Problem), _pd, _pd, _dbl, _dbl, _pd, _pd]
-        L.orc_solve.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(Settings), _pd, _pd,
-                                _dbl, _pd, _pd, ctypes.POINTER(_Info), ctypes.POINTER(_Trace)]
-        _lib_handle = L
+        _lib_handle = _declare(ctypes.CDLL(_LIB))
     return _lib_handle
+
+
+def build_variant(name: str, flags) -> ctypes.CDLL:
+    """The same oracle source compiled with other floating-point flags (for
+    example FMA contraction on) into liboracle_<name>.so: a second, equally
+    valid rounding of the same arithmetic, for measuring how far two correct
+    FP64 implementations drift apart.  Pass the handle as solve(..., lib=)."""
+    out = os.path.join(_HERE, f"liboracle_{name}.so")
+    if not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", *flags,
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, out)
+    return _declare(ctypes.CDLL(out))
 
 
 def _ptr(a, ct):
@@ -197,6 +219,15 @@ def _as_soc(inst):
         c=Tx @ np.asarray(inst.c, np.float64), h=Tr @ np.asarray(inst.h, np.float64),
         l=inst.l, u=inst.u, xcone_type=soc(inst.xcone_type), xcone_dim=inst.xcone_dim,
         rcone_type=soc(inst.rcone_type), rcone_dim=inst.rcone_dim), Tx, Tr
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's timing mode (1 = the deterministic default)."""
+    _lib().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_lib().orc_get_threads())
 
 
 def default_settings(**overrides) -> Settings:
@@ -322,15 +353,19 @@ def onepdhg(inst, x, y, tau, sigma):
 
 
 def solve(inst, settings: Settings | None = None, x0=None, y0=None, omega0: float = 0.0,
-          log_cap: int = 0, snap_iters=None):
+          log_cap: int = 0, snap_iters=None, replay=None, lib=None):
     """Algorithm 1 with rescaling.  Returns a dict with x, y, info fields and,
-    if requested, the decision log and iterate snapshots.  Rotated blocks:
-    the rewritten problem is solved from (T_x x0, T_r y0) and its iterates
-    are mapped back by T."""
+    if requested, the decision log and iterate snapshots.  `replay` (a decision
+    log: a dict with "attempts", "beta" and "check_code" arrays) forces those
+    decisions for as many iterations as it holds.  `lib` is another build of
+    the same source (build_variant) to run instead.  Rotated blocks: the
+    rewritten problem is solved from (T_x x0, T_r y0) and its iterates are
+    mapped back by T."""
     if _has_rsoc(inst):
         inst2, Tx, Tr = _as_soc(inst)
         fwd = lambda T, v: None if v is None else T @ np.asarray(v, np.float64)
-        res = solve(inst2, settings, fwd(Tx, x0), fwd(Tr, y0), omega0, log_cap, snap_iters)
+        res = solve(inst2, settings, fwd(Tx, x0), fwd(Tr, y0), omega0, log_cap, snap_iters,
+                    replay, lib)
         res["x"], res["y"] = Tx @ res["x"], Tr @ res["y"]
         if "log" in res:
             res["log"]["snap_x"] = np.array([Tx @ v for v in res["log"]["snap_x"]])
@@ -353,6 +388,7 @@ def solve(inst, settings: Settings | None = None, x0=None, y0=None, omega0: floa
         logs = {"attempts": np.zeros(cap, np.int32), "eta_used": np.zeros(cap),
                 "beta": np.zeros(cap), "omega": np.zeros(cap),
                 "check_code": np.zeros(cap, np.int32), "check_kkt": np.zeros(cap),
+                "margin": np.zeros(cap),
                 "snap_iter": snaps, "snap_x": np.zeros((max(snaps.size, 1), n)),
                 "snap_y": np.zeros((max(snaps.size, 1), m))}
         tr = _Trace(cap, 0, _ptr(logs["attempts"], ctypes.c_int32),
@@ -362,7 +398,18 @@ def solve(inst, settings: Settings | None = None, x0=None, y0=None, omega0: floa
                     _ptr(logs["check_kkt"], ctypes.c_double), int(snaps.size),
                     _ptr(snaps, ctypes.c_int64), _ptr(logs["snap_x"], ctypes.c_double),
                     _ptr(logs["snap_y"], ctypes.c_double))
-    rc = _lib().orc_solve(ctypes.byref(P), ctypes.byref(s), _ptr(x0a, ctypes.c_double),
+        tr.margin = _ptr(logs["margin"], ctypes.c_double)
+    if replay is not None:
+        if tr is None:
+            raise ValueError("a replay needs log_cap or snap_iters")
+        ra = keep.arr(replay["attempts"], np.int32)
+        rb = keep.arr(replay["beta"], np.float64)
+        rcc = keep.arr(replay["check_code"], np.int32)
+        tr.replay_count = int(min(ra.size, rb.size, rcc.size))
+        tr.replay_attempts = _ptr(ra, ctypes.c_int32)
+        tr.replay_beta = _ptr(rb, ctypes.c_double)
+        tr.replay_check_code = _ptr(rcc, ctypes.c_int32)
+    rc = (lib or _lib()).orc_solve(ctypes.byref(P), ctypes.byref(s), _ptr(x0a, ctypes.c_double),
                           _ptr(y0a, ctypes.c_double), float(omega0), _ptr(x, ctypes.c_double),
                           _ptr(y, ctypes.c_double), ctypes.byref(info),
                           ctypes.byref(tr) if tr is not None else None)
@@ -372,7 +419,7 @@ def solve(inst, settings: Settings | None = None, x0=None, y0=None, omega0: floa
     res["x"], res["y"] = x, y
     if logs is not None:
         cnt = tr.count
-        for k in ("attempts", "eta_used", "beta", "omega", "check_code", "check_kkt"):
+        for k in ("attempts", "eta_used", "beta", "omega", "check_code", "check_kkt", "margin"):
             logs[k] = logs[k][:cnt]
         res["log"] = logs
     return res

@@ -29,6 +29,17 @@
 
 static double sq(double a) { return a * a; }
 
+/* Timing mode.  With more than one thread the sparse products, the vector
+ * passes and the cone blocks of the solver run in OpenMP parallel loops (the
+ * reductions then add in another order); with one thread (the default) every
+ * loop runs in order in the calling thread, the deterministic mode the parity
+ * tests use.  The loops are the same in both modes: the `if` clause of each
+ * parallel loop only decides whether a team is started. */
+static int g_threads = 1;
+void orc_set_threads(int n) { g_threads = n > 1 ? n : 1; }
+int orc_get_threads(void) { return g_threads; }
+#define ORC_PAR _Pragma("omp parallel for if(g_threads > 1) num_threads(g_threads) schedule(static)")
+
 /* ------------------------------------------------------------------------ */
 /* Cone membership (definitions of K_exp and K_exp^* in Appendix A.2)        */
 /* ------------------------------------------------------------------------ */
@@ -303,13 +314,16 @@ static int dual_type(int t) {
 
 void orc_proj_blocks(int64_t nblk, const int32_t *type, const int64_t *dim, int dual,
                      const double *d, double *v) {
+    int64_t *offs = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nblk > 0 ? nblk : 1));
     int64_t off = 0;
-    double tmp[3];
+    for (int64_t b = 0; b < nblk; ++b) offs[b] = off, off += dim[b];
+#pragma omp parallel for if(g_threads > 1) num_threads(g_threads) schedule(dynamic, 256)
     for (int64_t b = 0; b < nblk; ++b) {
         int t = dual ? dual_type(type[b]) : type[b];
         int64_t k = dim[b];
-        double *vb = v + off;
-        const double *db = d ? d + off : NULL;
+        double *vb = v + offs[b];
+        const double *db = d ? d + offs[b] : NULL;
+        double tmp[3];
         switch (t) {
         case ORC_ZERO:
             for (int64_t i = 0; i < k; ++i) vb[i] = 0.0;
@@ -334,8 +348,8 @@ void orc_proj_blocks(int64_t nblk, const int32_t *type, const int64_t *dim, int 
             memcpy(vb, tmp, sizeof tmp);
             break;
         }
-        off += k;
     }
+    free(offs);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -343,6 +357,7 @@ void orc_proj_blocks(int64_t nblk, const int32_t *type, const int64_t *dim, int 
 /* ------------------------------------------------------------------------ */
 static void spmv(int64_t rows, const int64_t *rp, const int32_t *ci, const double *v,
                  const double *x, double *y) {
+#pragma omp parallel for if(g_threads > 1) num_threads(g_threads) schedule(dynamic, 1024)
     for (int64_t i = 0; i < rows; ++i) {
         double acc = 0.0;
         for (int64_t k = rp[i]; k < rp[i + 1]; ++k) acc += v[k] * x[ci[k]];
@@ -374,6 +389,7 @@ void orc_spmv(int64_t rows, const int64_t *rp, const int32_t *ci, const double *
 
 static double dot(int64_t n, const double *a, const double *b) {
     double s = 0.0;
+#pragma omp parallel for if(g_threads > 1) num_threads(g_threads) schedule(static) reduction(+:s)
     for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
     return s;
 }
@@ -521,6 +537,7 @@ int orc_kkt(const orc_problem *p, const double *x, const double *y, double *err_
 /* ------------------------------------------------------------------------ */
 static void proj_x(const orc_problem *p, const double *l, const double *u, const double *d,
                    double *x) {
+    ORC_PAR
     for (int64_t j = 0; j < p->n_box; ++j) x[j] = fmin(fmax(x[j], l[j]), u[j]);
     orc_proj_blocks(p->n_xcones, p->xcone_type, p->xcone_dim, 0, d ? d + p->n_box : NULL,
                     x + p->n_box);
@@ -578,6 +595,13 @@ void orc_settings_default(orc_settings *s) {
 typedef struct {
     double err_p, err_d, err_gap, pobj, dobj;
 } kkt_t;
+
+/* Relative distance of a deciding quantity a from its threshold b (a
+ * decision log entry; 0 means a tie, +inf when both are infinite). */
+static double rel_margin(double a, double b) {
+    double d = fabs(a - b), s = fmax(fabs(a), fabs(b));
+    return s > 0.0 && d == d ? d / s : (a == b ? 0.0 : INFINITY);
+}
 
 static double kkt_avg(const kkt_t *k) { return (k->err_p + k->err_d + k->err_gap) / 3.0; }
 static double kkt_max(const kkt_t *k) { return fmax(k->err_p, fmax(k->err_d, k->err_gap)); }
@@ -684,6 +708,7 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
     while (status < 0) {
         /* ---- AdaptiveStepPDHG (reading: the PDLP step rule) ---- */
         double tau, sigma, nx2 = 0, ny2 = 0, eta_used = 0;
+        double margin = INFINITY;   /* closest decision of this iteration */
         int attempts = 0;
         for (;;) {
             ++attempts;
@@ -691,15 +716,20 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
             sigma = eta * omega;
             /* x^ = Proj_X(x - tau (c - G^T y)) */
             spmv(n, trp, tci, tv, y, gty);
+            ORC_PAR
             for (int64_t j = 0; j < n; ++j) xh[j] = x[j] - tau * (cs[j] - gty[j]);
             proj_x(p, ls, us, dx, xh);
             /* y^ = Proj_Y(y + sigma (h - G (2 x^ - x))) */
+            ORC_PAR
             for (int64_t j = 0; j < n; ++j) xt[j] = 2.0 * xh[j] - x[j];
             spmv(m, p->row_ptr, p->col, gv, xt, gxt);
+            ORC_PAR
             for (int64_t i = 0; i < m; ++i) yh[i] = y[i] + sigma * (hs[i] - gxt[i]);
             proj_y(p, dy, yh);
             /* largest step the iteration would have allowed */
+            ORC_PAR
             for (int64_t j = 0; j < n; ++j) ddx[j] = xh[j] - x[j];
+            ORC_PAR
             for (int64_t i = 0; i < m; ++i) ddy[i] = yh[i] - y[i];
             spmv(m, p->row_ptr, p->col, gv, ddx, gdx);
             nx2 = nrm2sq(n, ddx);
@@ -707,6 +737,7 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
             double ip = dot(m, ddy, gdx);
             double den = 2.0 * fabs(ip);
             double ebar = den > 0.0 ? (omega * nx2 + ny2 / omega) / den : INFINITY;
+            if (s->step_mode != 1 && !plain) margin = fmin(margin, rel_margin(eta, ebar));
             if (!(ebar == ebar)) {
                 status = ORC_NUMERICAL;
                 break;
@@ -721,7 +752,10 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
                 eta_used = eta;
                 break;
             }
-            if (eta <= ebar) {
+            /* replay: the other run's attempt count decides acceptance */
+            int accept = eta <= ebar;
+            if (tr && N < tr->replay_count) accept = attempts == tr->replay_attempts[N];
+            if (accept) {
                 eta_used = eta;
                 eta = enew;
                 break;
@@ -739,12 +773,16 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
         /* ---- AdaptiveReflectionParameter (reading) ---- */
         double beta;
         double r = sqrt(omega * nx2 + ny2 / omega);
+        if (!plain && s->beta_mode != 1 && r_prev < INFINITY) margin = fmin(margin, rel_margin(r, r_prev));
         if (plain) {
             beta = 0.0;
         } else if (s->beta_mode == 1) {
             beta = s->beta_const;
         } else {
-            beta = r <= r_prev ? fmin(1.0, s->beta_grow * beta_prev) : s->beta_shrink * beta_prev;
+            int grow = r <= r_prev;
+            /* replay: the other run's beta says which branch it took */
+            if (tr && N < tr->replay_count) grow = tr->replay_beta[N] >= beta_prev;
+            beta = grow ? fmin(1.0, s->beta_grow * beta_prev) : s->beta_shrink * beta_prev;
         }
         r_prev = r;
         beta_prev = beta;
@@ -753,10 +791,14 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
         /* the baseline PDHG keeps z = z^: weights 1 and 0 */
         double a = plain ? 1.0 : (double)(kin + 1) / (double)(kin + 2);
         double b = plain ? 0.0 : 1.0 / (double)(kin + 2);
+        ORC_PAR
         for (int64_t j = 0; j < n; ++j) x[j] = a * ((1.0 + beta) * xh[j] - beta * x[j]) + b * xa[j];
+        ORC_PAR
         for (int64_t i = 0; i < m; ++i) y[i] = a * ((1.0 + beta) * yh[i] - beta * y[i]) + b * ya[i];
         /* ---- weighted average (Algorithm 1) ---- */
+        ORC_PAR
         for (int64_t j = 0; j < n; ++j) xsum[j] += eta_used * x[j];
+        ORC_PAR
         for (int64_t i = 0; i < m; ++i) ysum[i] += eta_used * y[i];
         wsum += eta_used;
         ++kin;
@@ -770,6 +812,7 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
             tr->omega[rec] = omega_iter;
             tr->check_code[rec] = 0;
             tr->check_kkt[rec] = 0.0;
+            if (tr->margin) tr->margin[rec] = margin;
             tr->count = rec + 1;
         }
         if (tr && snap < tr->n_snap && tr->snap_iter[snap] == N) {
@@ -813,9 +856,33 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
             else if ((double)kin >= s->restart_artificial * (double)N)
                 reason = 3;
         }
+        if (tr && rec < tr->replay_count && tr->replay_check_code[rec] > 0) {
+            /* replay: the other run's candidate, restart reason and stop */
+            int code = tr->replay_check_code[rec] - 1;
+            chosen = code & 1;
+            xc = chosen ? xc2 : xc1;
+            yc = chosen ? yc2 : yc1;
+            kc = chosen ? k2 : k1;
+            kcv = kkt_avg(&kc);
+            reason = (code >> 1) & 3;
+            stop = (code >> 3) & 1;
+            status = !stop ? -1 : (N >= s->max_iter && !(kkt_max(&kc) <= s->tol)) ? ORC_ITER_LIMIT
+                                                                                     : ORC_OPTIMAL;
+        }
         if (tr && rec < tr->cap) {
             tr->check_code[rec] = 1 + chosen + 2 * reason + 8 * stop;
             tr->check_kkt[rec] = kcv;
+            if (tr->margin && !plain) {
+                /* the candidate comparison and the restart thresholds */
+                double mg = fmin(tr->margin[rec], rel_margin(kkt_avg(&k2), kkt_avg(&k1)));
+                if (!stop) {
+                    mg = fmin(mg, rel_margin(kcv, s->restart_sufficient * kav));
+                    mg = fmin(mg, rel_margin(kcv, s->restart_necessary * kav));
+                    if (kprev_avg < INFINITY) mg = fmin(mg, rel_margin(kcv, kprev_avg));
+                }
+                mg = fmin(mg, rel_margin(kkt_max(&kc), s->tol));
+                tr->margin[rec] = mg;
+            }
         }
         if (stop) {
             outx = xc;

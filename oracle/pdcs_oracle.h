@@ -15,7 +15,8 @@
  * K_p by blocks covering x_2 and the row cones by blocks covering the m
  * rows; a row block of type T states G x - h in T, so K_d = T^*.
  *
- * Everything is double precision, single threaded and deterministic.
+ * Everything is double precision and, by default, single threaded and
+ * deterministic (see orc_set_threads for the timing mode).
  */
 #ifndef PDCS_ORACLE_H
 #define PDCS_ORACLE_H
@@ -102,9 +103,33 @@ typedef struct {
     const int64_t *snap_iter;
     double *snap_x;         /* [n_snap * n] */
     double *snap_y;         /* [n_snap * m] */
+    /* Replay of another run's decisions (parity harness): for the first
+     * replay_count accepted iterations, iteration k is accepted at attempt
+     * replay_attempts[k] (whatever eta <= eta_bar says), its reflection
+     * parameter grows when replay_beta[k] >= the previous one and shrinks
+     * otherwise, and a check after it takes the candidate, restart reason and
+     * stop flag of replay_check_code[k] (codes as check_code).  Every
+     * continuous quantity is still computed by this run.  0 = no replay. */
+    int64_t replay_count;
+    const int32_t *replay_attempts;
+    const double *replay_beta;
+    const int32_t *replay_check_code;
+    /* Optional [cap]: per iteration, the smallest relative distance between a
+     * deciding quantity and its threshold (eta against eta_bar at every
+     * attempt, ||z^ - z||_omega against its previous value, and at a check
+     * the two candidates' KKT averages, the restart thresholds and the
+     * tolerance); NULL = not recorded. */
+    double *margin;
 } orc_trace;
 
 void orc_settings_default(orc_settings *s);
+
+/* Threads of the timing mode (default 1).  With n > 1 the sparse products,
+ * vector passes and cone blocks of orc_solve run on n OpenMP threads and the
+ * reductions add in a different order; n <= 1 restores the deterministic
+ * single-thread mode that parity is measured in. */
+void orc_set_threads(int n);
+int orc_get_threads(void);
 
 /* Projections onto one diagonally rescaled cone D K (Section 3, Theorems 1-3).
  * d is the diagonal of D (NULL = identity); v and out hold one block.

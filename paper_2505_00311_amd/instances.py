@@ -580,6 +580,64 @@ def lasso(seed, rows=10_000, cols=100_000, density=1e-4, form="soc_rows", balanc
                               a_row_ptr=arp, a_col=aci, a_val=aval))
 
 
+def logistic(seed, samples=100_000, features=10_000, density=1e-3, l1=0.01, w_density=0.1,
+             noise=0.1):
+    """Sparse L1-regularised logistic regression as an exponential-cone
+    program: min sum_i log(1 + exp(-y_i a_i^T w)) + l1 ||w||_1 over w in R^p,
+    for N samples (the loss summed, not averaged: with the average, l1 = 0.01
+    exceeds every component of the loss gradient at w = 0 on this data and the
+    solution is w = 0).  With w = w+ - w- (w+, w- >= 0) and per sample an
+    epigraph variable t_i, log(1 + e^z) <= t holds exactly when
+    e^-t + e^(z-t) <= 1, i.e. when some u, v satisfy
+        (-t_i, 1, u_i) in K_exp,  (z_i - t_i, 1, v_i) in K_exp,  u_i + v_i <= 1,
+    with z_i = -y_i a_i^T w and K_exp = cl{(r, s, t): s > 0, s e^(r/s) <= t}
+    (Appendix A.2's order).
+    Variables: [w+ (p), w- (p), then (t_i, u_i, v_i) per sample], n = 2p + 3N.
+    Rows: N rows 1 - u_i - v_i >= 0 (NONNEG), then per sample two EXP blocks
+    of three rows each (their middle rows have no entries and h = -1), so
+    m = 7N and 2N exponential cones, whose dual variables take the dual
+    exponential projection.  c = (l1 on w+ and w-, 1 on each t_i).
+    Data: A (N x p) with Bernoulli(density) pattern and N(0,1) values, a
+    planted w* with w_density nonzeros N(0,1), labels y_i =
+    sign(a_i^T w* + noise eps_i) (0 -> +1).  No planted optimum: the
+    reference objective comes from a tight oracle solve."""
+    rng = np.random.default_rng(seed)
+    N, p = samples, features
+    arp, aci, aval = bernoulli_csr(rng, N, p, density)
+    wstar = np.where(rng.random(p) < w_density, rng.standard_normal(p), 0.0)
+    score = csr_matvec(arp, aci, aval, wstar) + noise * rng.standard_normal(N)
+    lab = np.where(score >= 0.0, 1.0, -1.0)
+    n = 2 * p + 3 * N
+    m = 7 * N
+    i = np.arange(N, dtype=np.int64)
+    ct, cu, cv = 2 * p + 3 * i, 2 * p + 3 * i + 1, 2 * p + 3 * i + 2
+    base = N + 6 * i
+    alen = np.diff(arp)
+    ar = np.repeat(i, alen)
+    ya = lab[ar] * aval
+    rows = np.concatenate([i, i, base, base + 2, base[ar] + 3, base[ar] + 3, base + 3, base + 5])
+    cols = np.concatenate([cu, cv, ct, cu, aci.astype(np.int64), p + aci.astype(np.int64), ct, cv])
+    vals = np.concatenate([-np.ones(N), -np.ones(N), -np.ones(N), np.ones(N), -ya, ya,
+                           -np.ones(N), np.ones(N)])
+    rp, ci, v = csr_from_coo(m, n, rows, cols, vals)
+    h = np.zeros(m)
+    h[:N] = -1.0
+    h[base + 1] = -1.0
+    h[base + 4] = -1.0
+    c = np.zeros(n)
+    c[:2 * p] = l1
+    c[ct] = 1.0
+    return Instance(n=n, m=m, n_box=0, row_ptr=rp, col=ci, val=v, c=c, h=h,
+                    l=np.zeros(0), u=np.zeros(0),
+                    xcone_type=np.array([NONNEG, FREE], np.int32),
+                    xcone_dim=np.array([2 * p, 3 * N], np.int64),
+                    rcone_type=np.array([NONNEG] + [EXP] * (2 * N), np.int32),
+                    rcone_dim=np.array([N] + [3] * (2 * N), np.int64),
+                    name=f"logistic_N{N}_p{p}",
+                    meta=dict(samples=N, features=p, l1=l1, labels=lab, w_star=wstar,
+                              a_row_ptr=arp, a_col=aci, a_val=aval, a_nnz=int(aval.size)))
+
+
 def rsoc_min_sum(seed, k=5, form="x"):
     """min u + v over the rotated cone 2 u v >= ||w||^2 (u, v >= 0) with w
     fixed to a seeded w0 ~ N(0, 1)^k.  form "x": x = (u, v, w) is a rotated x

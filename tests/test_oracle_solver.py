@@ -60,6 +60,47 @@ def test_onepdhg_hand_example(orc):
     assert np.allclose(yh, g["y_hat"], rtol=1e-15, atol=1e-15)
 
 
+@pytest.mark.parametrize("name", ["alg1_fixed_2x2.json", "alg1_adaptive_2x2.json"])
+def test_algorithm1_worked_examples(orc, name):
+    """Four or five iterations of Algorithm 1 on a 2x2 problem, worked out by
+    hand (tests/golden/, every intermediate written out): the PDHG step, the
+    step acceptance and next step size (adaptive example: a rejection, then
+    growth and reduction steps), the reflection parameter (two shrinks, then
+    a growth from below 1), the reflected Halpern weights (k+1)/(k+2) and
+    1/(k+2), the eta-weighted average, the candidate choice, the restart with
+    its primal weight, and the first iteration after it.  A wrong Halpern
+    weight or reflection, an unweighted average, another step-size count, a
+    missing beta growth factor or an inverted primal-weight ratio each change
+    these values (checked by planting each mistake in a copy of the oracle)."""
+    g = load_golden(name)
+    pr, st = g["problem"], dict(g["settings"])
+    inst = instance_from_dense(pr["n"], pr["m"], pr["n_box"], pr["G"], pr["c"], pr["h"], [], [],
+                               pr["xcones"], pr["rcones"])
+    omega0 = st.pop("omega0")
+    its = g["iterations"]
+    res = orc.solve(inst, orc.default_settings(**st), omega0=omega0, log_cap=len(its),
+                    snap_iters=[r["iteration"] for r in its])
+    log = res["log"]
+    assert res["iterations"] == len(its) and res["status"] == 1   # iteration limit
+    for i, r in enumerate(its):
+        assert log["attempts"][i] == r["attempts"], (i, "attempts")
+        for key in ("eta_used", "beta", "omega"):
+            assert log[key][i] == pytest.approx(r[key], rel=1e-13), (i, key)
+        assert np.allclose(log["snap_x"][i], r["x"], rtol=1e-12, atol=1e-14), (i, "x")
+        assert np.allclose(log["snap_y"][i], r["y"], rtol=1e-12, atol=1e-14), (i, "y")
+    ck = g["check"]
+    j = ck["after_iteration"] - 1
+    assert log["check_code"][j] == ck["code"]
+    kc = ck["kkt_average"] if ck["chosen"] else ck["kkt_current"]
+    assert log["check_kkt"][j] == pytest.approx(kc, rel=1e-12)
+    assert all(log["check_code"][i] == 0 for i in range(j))
+    assert log["check_code"][len(its) - 1] & 8            # the final check stops the solve
+    assert res["eta"] == pytest.approx(its[-1]["eta_next"], rel=1e-12)
+    # the first iteration after the restart starts from the chosen candidate
+    # with the new primal weight
+    assert its[j + 1]["omega"] == pytest.approx(ck["omega_after"], rel=1e-15)
+
+
 def test_onepdhg_fixed_point_at_optimum(orc):
     """A saddle point is a fixed point of eq. (5) for any step sizes."""
     inst = I.small_mixed(2)
@@ -276,3 +317,23 @@ def test_plain_pdhg_reaches_the_planted_optimum(orc):
     assert r["status"] == 0
     assert r["pobj"] == pytest.approx(inst.opt, rel=1e-5, abs=1e-5)
     assert r["restarts"] == 0
+
+
+def test_timing_mode_threads(orc):
+    """The OpenMP timing mode runs the same iteration with reductions in
+    another order: fixed-step iterates stay within rounding of the
+    single-thread ones, and switching back to one thread restores the
+    deterministic bits."""
+    inst = I.large_mixed(7, n=20000, m=10000)
+    s = orc.default_settings(max_iter=128, step_mode=1)
+    a = orc.solve(inst, s)
+    try:
+        orc.set_threads(4)
+        assert orc.get_threads() == 4
+        b = orc.solve(inst, s)
+    finally:
+        orc.set_threads(1)
+    c = orc.solve(inst, s)
+    assert np.array_equal(a["x"], c["x"]) and np.array_equal(a["y"], c["y"])
+    za, zb = np.concatenate([a["x"], a["y"]]), np.concatenate([b["x"], b["y"]])
+    assert np.linalg.norm(za - zb) <= 1e-8 * np.linalg.norm(za)
