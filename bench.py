@@ -337,19 +337,246 @@ def warm_start_form(pdcs, instances, torch, n_assets, n_train, n_test):
             "mfma_bf16_peak_tflops": 2500.0}
 
 
-def cpu_baseline(inst, iters):
-    """The oracle as it stands, single thread, on the first `iters` iterations."""
+def host_threads():
+    """Host threads the oracle's timing mode may use: the box's share
+    (OMP_NUM_THREADS when set), else every core."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, int(env)) if env.isdigit() else (os.cpu_count() or 1)
+
+
+def oracle_rate(inst, iters, threads, **kw):
+    """Oracle iterations per second over its first `iters` iterations, setup
+    (rescaling, transpose) excluded by subtracting a 0-iteration run."""
     import oracle
     oracle.build(force=False)
-    t0 = time.perf_counter()
-    oracle.solve(inst, oracle.default_settings(max_iter=0))
-    t1 = time.perf_counter()
-    r = oracle.solve(inst, oracle.default_settings(max_iter=iters))
-    t2 = time.perf_counter()
+    oracle.set_threads(threads)
+    try:
+        t0 = time.perf_counter()
+        oracle.solve(inst, oracle.default_settings(max_iter=0, **kw))
+        t1 = time.perf_counter()
+        r = oracle.solve(inst, oracle.default_settings(max_iter=iters, **kw))
+        t2 = time.perf_counter()
+    finally:
+        oracle.set_threads(1)
     run = (t2 - t1) - (t1 - t0)
-    return {"value": r["iterations"] / run, "unit": "iter/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {iters} PDHG iterations (one check period) of the same instance, "
-                      f"setup excluded; {run:.1f} s on 1 host thread"}
+    return r["iterations"] / run, run
+
+
+def cpu_baseline(inst, iters, gpu_iters_to_tol=None):
+    """The oracle as it stands on the first `iters` iterations of the same
+    instance: the OpenMP timing mode on the host's threads (the value) and the
+    deterministic single-thread mode beside it.  With the GPU's iteration
+    count to 1e-6, the oracle's time to tolerance is extrapolated from its
+    rate (an estimate: the oracle is not run that long)."""
+    threads = host_threads()
+    v_all, run_all = oracle_rate(inst, iters, threads)
+    v_one, run_one = oracle_rate(inst, iters, 1)
+    rec = {"value": round(v_all, 3), "unit": "iter/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {iters} PDHG iterations (one check period) of the same instance, "
+                     f"setup excluded; {run_all:.1f} s on {threads} host threads (OpenMP timing "
+                     f"mode), {run_one:.1f} s on 1 thread",
+           "single_thread_value": round(v_one, 3), "host_cpu_count": os.cpu_count()}
+    if gpu_iters_to_tol:
+        rec["estimated_time_to_tol_s"] = round(gpu_iters_to_tol / v_all, 1)
+        rec["estimated_time_to_tol_note"] = (f"estimate: {gpu_iters_to_tol} iterations (the GPU "
+                                             f"solve's count to 1e-6) at the measured oracle rate")
+    return rec
+
+
+def small_instance(pdcs, instances, torch, oracle_on=True):
+    """The small single instance (n = 1000, m = 500, 1% density, 500 nonneg +
+    50 SOC(10) on x; latency-bound): iterations per second, microseconds per
+    iteration and time to 1e-6 on the GPU, and the oracle's full solve to 1e-6
+    on one host thread beside it."""
+    inst = instances.lp_soc_small(20250501)
+    prob = pdcs.Problem(inst)
+    prob.solve(pdcs.settings_default(max_iter=64))   # scaling and graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = prob.solve(pdcs.settings_default(max_iter=64 * 50, tol=0.0))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ips = r["iterations"] / r["solve_s"]
+    t0 = time.perf_counter()
+    rt = prob.solve(pdcs.settings_default())
+    torch.cuda.synchronize()
+    wall_t = time.perf_counter() - t0
+    prob.close()
+    rec = {"workload": f"lp_soc n={inst.n} m={inst.m} nnz={inst.nnz} (500 nonneg + 50 SOC(10) on x, "
+                       "250 equality + 250 inequality rows, seed 20250501)",
+           "bound": "latency (five launches per step attempt; 0.29 MB per iteration stays in L2)",
+           "iter_per_s": round(ips, 1), "us_per_iteration": round(1e6 / ips, 2),
+           "timed_iterations": r["iterations"], "wall_s": round(wall, 3),
+           "time_to_tol": {"tol": 1e-6, "status": pdcs.SOLVE_STATUS[rt["status"]],
+                           "solve_s": round(rt["solve_s"], 4), "wall_s": round(wall_t, 4),
+                           "iterations": rt["iterations"], "objective": rt["pobj"],
+                           "planted_objective": inst.opt}}
+    if oracle_on:
+        import oracle
+        oracle.build(force=False)
+        t0 = time.perf_counter()
+        ro = oracle.solve(inst, oracle.default_settings())
+        wall_o = time.perf_counter() - t0
+        rec["oracle_1_thread"] = {"solve_s_incl_setup": round(wall_o, 3), "iterations": ro["iterations"],
+                                  "iter_per_s": round(ro["iterations"] / wall_o, 1),
+                                  "status": ro["status"], "objective": ro["pobj"]}
+        rec["speedup_time_to_tol_vs_oracle"] = round(wall_o / max(rt["solve_s"], 1e-9), 2)
+    log(f"small instance: {ips:.0f} iter/s ({1e6 / ips:.1f} us/iteration); to 1e-6 in "
+        f"{rt['solve_s']:.4f}s, {rt['iterations']} iterations")
+    return rec
+
+
+SEED_LOGISTIC = 20250503
+
+
+def logistic_form(pdcs, instances, torch):
+    """The exponential-cone logistic-regression workload (1e5 samples x 1e4
+    features, 0.1% density, 2e5 exponential cones on the rows): time to 1e-6 in
+    FP64 and in the mixed form, each answer's objective error against the
+    oracle's 1e-9 reference (tests/golden/logistic_reference.json), iterations
+    per second, and the dual exponential projection of the 2e5 cones timed on
+    its own (a projection plan applied to the dual iterate of the solve)."""
+    t = time.perf_counter()
+    inst = instances.logistic(SEED_LOGISTIC)
+    log(f"logistic: n={inst.n} m={inst.m} nnz={inst.nnz} generated in {time.perf_counter() - t:.1f}s")
+    ref_path = os.path.join(ROOT, "tests", "golden", "logistic_reference.json")
+    ref = json.load(open(ref_path)) if os.path.exists(ref_path) else None
+    prob = pdcs.Problem(inst)
+    prob.solve(pdcs.settings_default(max_iter=64))
+    torch.cuda.synchronize()
+    rec = {"workload": f"logistic N=1e5 p=1e4 density 1e-3 l1 0.01, n={inst.n} m={inst.m} "
+                       f"nnz={inst.nnz}, {2 * inst.meta['samples']} exp cones on rows, seed {SEED_LOGISTIC}",
+           "reference": None if ref is None else {"objective": ref["pobj"], "tol": ref["tol"],
+                                                   "iterations": ref["iterations"]}}
+    out = {}
+    for name, kw in (("fp64", {}), ("mixed", {"precision": 1})):
+        t0 = time.perf_counter()
+        r = prob.solve(pdcs.settings_default(time_limit=120.0, **kw))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        e = {"status": pdcs.SOLVE_STATUS[r["status"]], "solve_s": round(r["solve_s"], 3),
+             "wall_s": round(wall, 3), "iterations": r["iterations"],
+             "iter_per_s": round(r["iterations"] / max(r["solve_s"], 1e-9), 1),
+             "kkt_max": max(r["err_p"], r["err_d"], r["err_gap"]), "objective": r["pobj"]}
+        if ref is not None:
+            e["objective_rel_err_vs_oracle"] = abs(r["pobj"] - ref["pobj"]) / abs(ref["pobj"])
+        if name == "mixed":
+            e["polish_iter"] = r["polish_iter"]
+        out[name] = (e, r)
+        rec[name] = e
+        log(f"logistic {name}: {e['status']} in {e['solve_s']}s, {e['iterations']} iterations, "
+            f"objective error {e.get('objective_rel_err_vs_oracle')}")
+    rec["mixed_speedup_time_to_tol"] = round(rec["fp64"]["solve_s"] / max(rec["mixed"]["solve_s"], 1e-9), 3)
+    # the 2e5 dual exponential projections alone, on the final dual iterate
+    N = inst.meta["samples"]
+    y = torch.from_numpy(out["fp64"][1]["y"][N:].copy()).cuda()
+    cones = pdcs.Cones(np.full(2 * N, 4, np.int32), np.full(2 * N, 3, np.int64))
+    v = torch.empty_like(y)
+    ms = []
+    for k in range(6):
+        v.copy_(y)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        cones.project(v, dual=True)
+        b.record()
+        torch.cuda.synchronize()
+        if k:
+            ms.append(a.elapsed_time(b))
+    cones.close()
+    t_exp = float(np.median(ms))
+    rec["dual_exp_projection"] = {"cones": 2 * N, "ms": round(t_exp, 4),
+                                  "cones_per_s": round(2 * N / (t_exp * 1e-3), 1),
+                                  "input": "the FP64 solve's dual iterate on the exponential rows"}
+    prob.close()
+    return rec
+
+
+def _member(args):
+    seed, b, count = args
+    from paper_2505_00311_amd import instances
+    return instances.batch_member(seed, b, count)
+
+
+def sgm(times, shift=10.0):
+    """Shifted geometric mean SGM(k) of Section 5: (prod (t_i + k))^(1/N) - k."""
+    t = np.asarray(times, dtype=np.float64)
+    return float(np.exp(np.mean(np.log(t + shift))) - shift)
+
+
+def config4(args):
+    """The batched configuration at its size: `count` independent planted
+    LP/SOCP instances (n uniform in 1e3..1e5, m = n/2, 0.5% density, 20% of the
+    variables in SOC blocks of dims 3..50; about 4.3e9 nonzeros in all).
+
+    mode "batch": one batch of all of them in the mixed form (FP32 products,
+    FP64 checks and polish), product layouts by the autotuner, with a time
+    limit; reports the wall time, how many finished, and SGM(10) of the
+    instances' finish times (an unfinished instance counts the limit).
+    mode "single": every stride-th instance solved alone with the plain FP64
+    solver (the same time limit each), the per-instance times and SGM(10) of
+    that sample.  Instances are generated on the host by a process pool
+    before anything touches the GPU (each member has its own child seed)."""
+    import multiprocessing as mp
+    from paper_2505_00311_amd import instances
+    count, seed = args.c4_count, SEED_BATCH
+    sizes = instances.batch_sizes(seed, count)
+    idx = list(range(count)) if args.c4_mode == "batch" else list(range(0, count, args.c4_stride))
+    t0 = time.perf_counter()
+    workers = max(1, min(host_threads(), 16))
+    with mp.get_context("fork").Pool(workers) as pool:
+        insts = pool.map(_member, [(seed, b, count) for b in idx], chunksize=1)
+    gen_s = time.perf_counter() - t0
+    nnz = sum(i.nnz for i in insts)
+    log(f"config 4 ({args.c4_mode}): {len(insts)} instances, sum nnz {nnz}, generated in {gen_s:.1f}s "
+        f"on {workers} processes")
+    import torch
+    from paper_2505_00311_amd import pdcs
+    torch.cuda.set_device(0)
+    out = {"metric": METRIC, "mode": args.c4_mode, "data": "synthetic",
+           "workload": f"{count} planted LP/SOCP instances (n uniform in 1e3..1e5, m = n/2, 0.5% density, "
+                       f"20% SOC dims 3..50, seed {seed}); sum n {int(sizes.sum())}",
+           "instances": len(insts), "sum_nnz": nnz, "generate_s": round(gen_s, 1),
+           "time_limit_s": args.c4_time_limit}
+    if args.c4_mode == "batch":
+        t0 = time.perf_counter()
+        batch = pdcs.Batch(insts)
+        torch.cuda.synchronize()
+        out["create_s"] = round(time.perf_counter() - t0, 1)
+        log(f"  batch created in {out['create_s']}s")
+        del insts
+        t0 = time.perf_counter()
+        rb = batch.solve(pdcs.settings_default(precision=1, autotune=1, time_limit=args.c4_time_limit))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        batch.close()
+        done = [r["done_s"] if r["status"] == 0 else args.c4_time_limit for r in rb]
+        its = [r["iterations"] for r in rb]
+        out.update({"form": "batched, FP32 products + FP64 checks and polish, autotuned layouts",
+                    "wall_s": round(wall, 2), "solve_s": round(rb[0]["solve_s"], 2),
+                    "setup_s": round(rb[0]["setup_s"], 2),
+                    "optimal": sum(r["status"] == 0 for r in rb),
+                    "sgm10_s": round(sgm(done), 3),
+                    "iterations_median": int(np.median(its)), "iterations_max": int(max(its)),
+                    "finish_s_quantiles": [round(float(q), 2) for q in np.quantile(done, [0.1, 0.5, 0.9, 1.0])]})
+    else:
+        times, its, ok = [], [], 0
+        for k, inst in zip(idx, insts):
+            prob = pdcs.Problem(inst)
+            prob.solve(pdcs.settings_default(max_iter=64))
+            torch.cuda.synchronize()
+            r = prob.solve(pdcs.settings_default(time_limit=args.c4_time_limit))
+            torch.cuda.synchronize()
+            prob.close()
+            t = r["solve_s"] if r["status"] == 0 else args.c4_time_limit
+            times.append(t), its.append(r["iterations"])
+            ok += r["status"] == 0
+            log(f"  instance {k} (n {inst.n}, nnz {inst.nnz}): {pdcs.SOLVE_STATUS[r['status']]} in "
+                f"{r['solve_s']:.2f}s, {r['iterations']} iterations")
+        out.update({"form": "one by one, plain FP64", "sample_stride": args.c4_stride,
+                    "sample": idx, "optimal": ok, "times_s": [round(t, 3) for t in times],
+                    "iterations": its, "sum_s": round(sum(times), 2), "sgm10_s": round(sgm(times), 3),
+                    "sum_s_extrapolated_to_all": round(sum(times) * count / len(times), 1)})
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -364,6 +591,8 @@ def main():
     ap.add_argument("--no-paper-workloads", action="store_true")
     ap.add_argument("--no-projection-sweeps", action="store_true")
     ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--no-small", action="store_true", help="skip the n = 1000 latency-bound instance")
+    ap.add_argument("--no-logistic", action="store_true", help="skip the logistic-regression workload")
     ap.add_argument("--lasso-sizes", default="",
                     help="extra Lasso sizes 'ROWSxCOLS,...' for the paper workloads (the paper's "
                          "larger ones: 400000x7000000,700000x7000000,750000x7500000; each takes "
@@ -380,11 +609,22 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (the reference kernel "
                          "for scaling HBM byte counters) and exit")
+    ap.add_argument("--config4", action="store_true",
+                    help="only the batched configuration at its size (512 instances, ~4.3e9 "
+                         "nonzeros; many minutes), printing its own JSON line")
+    ap.add_argument("--c4-mode", choices=["batch", "single"], default="batch")
+    ap.add_argument("--c4-count", type=int, default=512)
+    ap.add_argument("--c4-stride", type=int, default=16)
+    ap.add_argument("--c4-time-limit", type=float, default=300.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the sharded "
               "multi-GPU path is not implemented", file=sys.stderr)
         sys.exit(2)
+
+    if args.config4:   # generates on the host before anything touches the GPU
+        config4(args)
+        return
 
     import torch
     from paper_2505_00311_amd import instances
@@ -527,10 +767,17 @@ def main():
     if not args.no_ablation:
         out["pdhg_ablation"] = pdhg_ablation(pdcs, instances, torch)
 
+    if not args.no_small:
+        out["small_instance"] = small_instance(pdcs, instances, torch, not args.no_cpu_baseline)
+    if not args.no_logistic:
+        out["logistic"] = logistic_form(pdcs, instances, torch)
+
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_iters)
-        log(f"oracle: {out['cpu_baseline']['value']:.3f} iter/s")
+        tt = out.get("time_to_tol", {})
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_iters,
+                                           tt.get("iterations") if tt.get("status") == "optimal" else None)
+        log(f"oracle: {out['cpu_baseline']['value']:.3f} iter/s on {out['cpu_baseline']['cores']} threads")
 
     prob.close()
     print(json.dumps(out), flush=True)

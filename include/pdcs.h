@@ -132,11 +132,15 @@ typedef struct {
     /* Mixed precision (not in the paper): precision 1 runs the two products of
      * every step attempt with FP32 matrix values and FP32 copies of x^ and y^
      * (products and sums in FP64); iterates, anchors, averages, projections,
-     * step decisions and every check stay FP64.  The solve switches to the
-     * FP64 products for good (the polish phase) once the chosen candidate's
-     * max(err_p, err_d, err_gap) <= polish_tol, or after polish_stall checks in
-     * a row without a new best; the kept products G~x, G~^T y and those of the
-     * anchor are then recomputed in FP64.  precision 0 is plain FP64. */
+     * step decisions and every check stay FP64.  precision 2 also projects
+     * the SOC blocks of at most 256 entries and the exponential cones of the
+     * two step passes in FP32 (see pdcs_project_fp32; the exponential cone's
+     * case tests and range safeguards stay FP64).  The solve switches to the
+     * FP64 products and projections for good (the polish phase) once the
+     * chosen candidate's max(err_p, err_d, err_gap) <= polish_tol, or after
+     * polish_stall checks in a row without a new best; the kept products
+     * G~x, G~^T y and those of the anchor are then recomputed in FP64.
+     * precision 0 is plain FP64. */
     int32_t precision;
     double polish_tol;
     int32_t polish_stall;
@@ -191,6 +195,9 @@ typedef struct {
     int64_t kernel_launches[PDCS_K_COUNT];
     int64_t polish_iter;        /* precision 1: accepted iterations before the switch to
                                  * FP64 products (-1: never switched); 0 otherwise     */
+    double done_s;              /* seconds from the first iteration until this problem
+                                 * stopped: in a batch, the check at which this
+                                 * instance finished (solve_s is the whole batch's)  */
 } pdcs_info;
 
 /* Optional decision log and iterate snapshots of pdcs_solve, host memory.
@@ -214,6 +221,22 @@ typedef struct {
     const int64_t *snap_iter;
     double *snap_x;             /* [n_snap * n] */
     double *snap_y;             /* [n_snap * m] */
+    /* Replay of another run's decisions (a parity harness: the decision log
+     * of the reference implementation, same settings).  For the first
+     * replay_count accepted iterations (host arrays of that length),
+     * iteration k is accepted at attempt replay_attempts[k] (>= 1) whatever
+     * eta <= eta_bar says here, its reflection parameter grows when
+     * replay_beta[k] >= the previous one and shrinks otherwise, and a check
+     * after it takes the candidate, restart reason and stop flag encoded in
+     * replay_check_code[k] (codes as check_code).  Every continuous quantity
+     * (step sizes, reflection parameters, primal weights, iterates) is still
+     * computed by this run, so two implementations can be compared iterate by
+     * iterate past a decision that rounding tips the other way.
+     * replay_count 0 = no replay. */
+    int64_t replay_count;
+    const int32_t *replay_attempts;
+    const double *replay_beta;
+    const int32_t *replay_check_code;
 } pdcs_trace;
 
 typedef struct pdcs_problem pdcs_problem;
@@ -245,7 +268,9 @@ void pdcs_problem_destroy(pdcs_problem *p);
  * cold start from zero) are an unscaled starting point; omega0 <= 0 selects
  * the default primal weight.  x_out [n] and y_out [m] receive the unscaled
  * solution (host memory unless settings->out_on_device).  info and trace are
- * nullable.  Errors: INVALID_ARG, OOM, HIP; the solve outcome is info->status. */
+ * nullable.  Errors: INVALID_ARG, OOM, HIP (also when a grid-level SOC
+ * projection timed out waiting for its workgroups, detected at the next
+ * check); the solve outcome is info->status. */
 pdcs_status pdcs_solve(pdcs_problem *p, const pdcs_settings *settings, const double *x0,
                        const double *y0, double omega0, double *x_out, double *y_out,
                        pdcs_info *info, pdcs_trace *trace);
@@ -308,6 +333,17 @@ pdcs_status pdcs_kkt(pdcs_problem *p, const double *x_dev, const double *y_dev, 
 pdcs_status pdcs_project(int64_t nblocks, const int32_t *types, const int64_t *dims, int dual,
                          const double *d_dev, double *v_dev, void *hip_stream);
 
+/* pdcs_project in the arithmetic of the mixed-precision form's FP32
+ * projections (not in the paper; settings.precision 2): SOC blocks of at most
+ * 256 entries and exponential cones are projected in FP32 (inputs rounded to
+ * FP32, norms, case tests and the root search in FP32, results widened), with
+ * the FP64 routine taking over wherever FP32 cannot be trusted (the
+ * exponential cone's case tests and unbounded or wide search intervals, and
+ * any search that leaves the FP32 range or does not settle).  Other blocks as
+ * pdcs_project.  A test and measurement hook; same arguments and errors. */
+pdcs_status pdcs_project_fp32(int64_t nblocks, const int32_t *types, const int64_t *dims, int dual,
+                              const double *d_dev, double *v_dev, void *hip_stream);
+
 /* A projection plan for one product of cones, built once and reused: the
  * dispatch of pdcs_project (the thread-, wavefront- and workgroup-level
  * classes of Section 4) kept on the device.  pdcs_cones_create takes host
@@ -315,7 +351,10 @@ pdcs_status pdcs_project(int64_t nblocks, const int32_t *types, const int64_t *d
  * v_dev (device, length sum(dims)) in place on hip_stream without waiting,
  * with d_dev (device, nullable = identity) the diagonal of D and dual != 0
  * for the dual cones.  Calls on one plan must not overlap (they share its
- * scratch and the barrier state of its grid-level SOC blocks).  Errors:
+ * scratch and the barrier state of its grid-level SOC blocks); each call
+ * first clears that barrier state.  The call does not wait, so a barrier
+ * wait that times out (the launch's projections are then invalid) is not
+ * reported here; pdcs_project and pdcs_solve, which wait, report it.  Errors:
  * INVALID_ARG, DIMENSION, OOM, HIP; NOT_SUPPORTED for a plan with RSOC blocks
  * given a d_dev. */
 typedef struct pdcs_cones pdcs_cones;
@@ -325,6 +364,7 @@ pdcs_status pdcs_cones_project(pdcs_cones *c, int dual, const double *d_dev, dou
                                void *hip_stream);
 void pdcs_cones_destroy(pdcs_cones *c);
 
+
 /* ---------------------------------------------------------------------------
  * Batches (not in the paper): `count` independent problems solved together.
  * Their data are laid out block-diagonally on the device and every kernel of a
@@ -332,8 +372,10 @@ void pdcs_cones_destroy(pdcs_cones *c);
  * from a captured HIP graph), each instance with its own step size, primal
  * weight, reflection parameter, restarts and termination.  An instance that
  * has converged stops taking work.  descs: host arrays of every instance,
- * deep-copied (the totals of n, m and nnz must each stay below 2^31).  Same
- * errors as pdcs_problem_create, plus NOT_SUPPORTED for device arrays. */
+ * deep-copied.  Each instance's nnz, and the totals of n and m, must stay
+ * below 2^31; the total nnz may exceed it (indices into the batch's entries
+ * are 64-bit, G^T is built instance by instance).  Same errors as
+ * pdcs_problem_create, plus NOT_SUPPORTED for device arrays. */
 typedef struct pdcs_batch pdcs_batch;
 pdcs_status pdcs_batch_create(const pdcs_problem_desc *descs, int64_t count, void *hip_stream,
                               pdcs_batch **out);

@@ -512,7 +512,7 @@ struct pdcs_problem {
     // a captured batch of step attempts, replayed on a library stream
     hipStream_t gstream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};   // [mixed]
+    hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};   // [precision mode]
     // timing events of settings.time_kernels: (PDCS_K_COUNT + 1) per attempt
     std::vector<hipEvent_t> tev;
     // mixed-precision form: FP32 copies of the scaled values (Gs.v32, Gts.v32)
@@ -775,6 +775,14 @@ static void rotate_host(double *v, const int64_t *offs, int64_t count, int64_t b
 // diagonally: instance b owns entries [x0, x0 + n) of x, rows [y0, y0 + m) and
 // nonzeros [k0, k0 + nnz); its columns are shifted by x0.  A batch needs host
 // arrays; one problem may also come from device arrays.
+// G^T of a problem or batch, instance by instance (the transpose of a
+// block-diagonal matrix is block-diagonal).
+static void transpose_blocks(pdcs_problem *P, hipStream_t s) {
+    std::vector<TBlock> blk;
+    for (const InstDims &I : P->inst) blk.push_back(TBlock{I.y0, I.m, I.x0, I.n, I.k0, I.nnz});
+    transpose_csr(P->G, P->Gt, blk.data(), (int64_t)blk.size(), s);
+}
+
 static pdcs_problem *create_impl(const pdcs_problem_desc *Ds, int64_t count, void *stream,
                                  bool on_device) {
     if (!Ds) fail(PDCS_ERR_INVALID_ARG, "desc is NULL");
@@ -804,7 +812,9 @@ static pdcs_problem *create_impl(const pdcs_problem_desc *Ds, int64_t count, voi
         n += D->n, m += D->m, nnz += D->nnz;
         P->inst.push_back(I);
     }
-    if (nnz >= ((int64_t)1 << 31)) fail(PDCS_ERR_NOT_SUPPORTED, "nnz must be below 2^31");
+    for (const InstDims &I : P->inst)
+        if (I.nnz >= ((int64_t)1 << 31))
+            fail(PDCS_ERR_NOT_SUPPORTED, "each instance's nnz must be below 2^31");
     if (n >= ((int64_t)1 << 31) || m >= ((int64_t)1 << 31))
         fail(PDCS_ERR_NOT_SUPPORTED, "n and m must be below 2^31");
     P->n = n, P->m = m, P->nnz = nnz;
@@ -909,7 +919,7 @@ static pdcs_problem *create_impl(const pdcs_problem_desc *Ds, int64_t count, voi
         h2d(P->ry_dev, P->ry.data(), (int64_t)P->ry.size(), s);
         PDCS_HIP(hipStreamSynchronize(s));
     }
-    transpose_csr(P->G, P->Gt, s);
+    transpose_blocks(P.get(), s);
     std::vector<int64_t> hrp(m + 1), hrpt(n + 1);
     d2h(hrp.data(), P->G.rp, m + 1, s);
     d2h(hrpt.data(), P->Gt.rp, n + 1, s);
@@ -1033,7 +1043,7 @@ static pdcs_problem *create_impl(const pdcs_problem_desc *Ds, int64_t count, voi
         double *cu = M.alloc<double>(n);
         copy_vec(P->c, cu, n, s);
         gather(P->c, cu, P->xperm, n, s);
-        transpose_csr(P->G, P->Gt, s);
+        transpose_blocks(P.get(), s);
         d2h(hrpt.data(), P->Gt.rp, n + 1, s);
         PDCS_HIP(hipStreamSynchronize(s));   // the host vectors die at the end of this block
     }
@@ -1359,13 +1369,15 @@ static void fill_info(pdcs_info *info, int status, const DevState &hs, long long
 // `batch` times.  With `ev`, event ev[(PDCS_K_COUNT + 1) b + j] is recorded
 // before kernel j of attempt b and ev[(PDCS_K_COUNT + 1) b + PDCS_K_COUNT]
 // after its last kernel.
-static void enqueue_attempts(pdcs_problem *P, long long batch, bool mixed, hipStream_t s,
+static void enqueue_attempts(pdcs_problem *P, long long batch, int mode, hipStream_t s,
                              const hipEvent_t *ev = nullptr) {
+    const bool mixed = mode > 0;
     const PrimalArgs pa{P->x, P->aty, P->cs, P->ls, P->us, P->dx, P->xh, P->st,
-                        mixed ? P->xh32 : nullptr};
+                        mixed ? P->xh32 : nullptr, mode == 2 ? 1 : 0};
     // each product is one launch: its finishing sums are taken by the dual
     // pass (G~x^) and the Halpern step (G~^T y^)
     DualArgs da{P->y, P->gxh, P->gx, P->hs, P->dy, P->yh, P->st, mixed ? P->yh32 : nullptr};
+    da.fp32proj = mode == 2 ? 1 : 0;
     da.gt = tail_of(P->pG, P->m);
     da.gxh_out = P->gxh;
     HalpernArgs ha{P->x,  P->aty, P->xsum, P->xh, P->atyh, P->xa, P->aty0, P->y, P->gx,
@@ -1411,30 +1423,30 @@ static void enqueue_attempts(pdcs_problem *P, long long batch, bool mixed, hipSt
 
 // Captures kGraphBatch attempts once per problem on a library-owned stream
 // (the caller's stream may be the null stream, which cannot be captured).
-static void ensure_graph(pdcs_problem *P, bool mixed) {
-    if (P->gexec[mixed]) return;
+static void ensure_graph(pdcs_problem *P, int mode) {
+    if (P->gexec[mode]) return;
     if (!P->gstream) PDCS_HIP(hipStreamCreateWithFlags(&P->gstream, hipStreamNonBlocking));
     if (!P->ev_in) PDCS_HIP(hipEventCreateWithFlags(&P->ev_in, hipEventDisableTiming));
     if (!P->ev_out) PDCS_HIP(hipEventCreateWithFlags(&P->ev_out, hipEventDisableTiming));
     hipGraph_t g = nullptr;
     PDCS_HIP(hipStreamBeginCapture(P->gstream, hipStreamCaptureModeThreadLocal));
     try {
-        enqueue_attempts(P, kGraphBatch, mixed, P->gstream);
+        enqueue_attempts(P, kGraphBatch, mode, P->gstream);
     } catch (...) {
         (void)hipStreamEndCapture(P->gstream, &g);
         if (g) (void)hipGraphDestroy(g);
         throw;
     }
     PDCS_HIP(hipStreamEndCapture(P->gstream, &g));
-    hipError_t e = hipGraphInstantiate(&P->gexec[mixed], g, nullptr, nullptr, 0);
+    hipError_t e = hipGraphInstantiate(&P->gexec[mode], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     PDCS_HIP(e);
 }
 
-static void run_graph(pdcs_problem *P, bool mixed, hipStream_t s) {
+static void run_graph(pdcs_problem *P, int mode, hipStream_t s) {
     PDCS_HIP(hipEventRecord(P->ev_in, s));
     PDCS_HIP(hipStreamWaitEvent(P->gstream, P->ev_in, 0));
-    PDCS_HIP(hipGraphLaunch(P->gexec[mixed], P->gstream));
+    PDCS_HIP(hipGraphLaunch(P->gexec[mode], P->gstream));
     PDCS_HIP(hipEventRecord(P->ev_out, P->gstream));
     PDCS_HIP(hipStreamWaitEvent(s, P->ev_out, 0));
 }
@@ -1471,20 +1483,28 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
         if (!xo[b] || !yo[b]) fail(PDCS_ERR_INVALID_ARG, "settings, x_out and y_out are required");
     if (S->check_every < 1 || S->ruiz_iters < 0 || S->max_attempts < 1 || !(S->tol >= 0.0) ||
         S->step_mode < 0 || S->step_mode > 1 || (S->step_mode == 1 && !(S->step_fixed > 0.0)) ||
-        S->precision < 0 || S->precision > 1 || !(S->polish_tol >= 0.0) || S->polish_stall < 1 ||
+        S->precision < 0 || S->precision > 2 || !(S->polish_tol >= 0.0) || S->polish_stall < 1 ||
         S->plain_pdhg < 0 || S->plain_pdhg > 1 || (S->plain_pdhg == 1 && !(S->step_fixed > 0.0)))
         fail(PDCS_ERR_INVALID_ARG, "bad settings");
     if (tr && B != 1) fail(PDCS_ERR_INVALID_ARG, "a trace is for a single problem");
     if (tr && (tr->cap < 0 || tr->n_snap < 0 || (tr->n_snap > 0 && (!tr->snap_iter || !tr->snap_x || !tr->snap_y)) ||
                (tr->cap > 0 && (!tr->attempts || !tr->eta_used || !tr->beta || !tr->omega ||
-                                !tr->check_code || !tr->check_kkt))))
+                                !tr->check_code || !tr->check_kkt)) ||
+               tr->replay_count < 0 ||
+               (tr->replay_count > 0 && (!tr->replay_attempts || !tr->replay_beta || !tr->replay_check_code))))
         fail(PDCS_ERR_INVALID_ARG, "bad trace");
+    const int64_t n_replay = tr ? tr->replay_count : 0;
+    for (int64_t k = 0; k < n_replay; ++k)
+        if (tr->replay_attempts[k] < 1 || tr->replay_check_code[k] < 0 || tr->replay_check_code[k] > 16)
+            fail(PDCS_ERR_INVALID_ARG, "bad replay log");
     const auto t_start = clk::now();
     hipStream_t s = P->stream;
     const int64_t n = P->n, m = P->m;
     ensure_scaling(P, S->ruiz_iters, S->pock_chambolle ? 1 : 0);
     if (S->autotune && !P->tuned) autotune_spmv(P);   // drops graphs of the old plans
-    bool mixed = S->precision == 1;
+    // precision mode: 0 FP64; 1 FP32 products; 2 FP32 products and projections
+    int mode = S->precision;
+    bool mixed = mode > 0;
     if (mixed) ensure_fp32(P);
     int64_t polish_iter = mixed ? -1 : 0;
     std::vector<double> best_mixed(B, INFINITY);
@@ -1500,11 +1520,21 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
         tr->count = 0;
         for (int64_t i = 0; i < cap; ++i) tr->check_code[i] = 0, tr->check_kkt[i] = 0.0;
     }
+    int *rp_att = tmem.alloc<int>(n_replay);
+    double *rp_beta = tmem.alloc<double>(n_replay);
+    if (n_replay > 0) {
+        static_assert(sizeof(int) == sizeof(int32_t), "replay log layout");
+        h2d(rp_att, (const int *)tr->replay_attempts, n_replay, P->stream);
+        h2d(rp_beta, tr->replay_beta, n_replay, P->stream);
+    }
 
-    // no root guesses yet: every solve starts from the same state
+    // no root guesses yet: every solve starts from the same state; barrier
+    // counters and the timeout flag of grid-level blocks start from zero (a
+    // timed-out earlier solve leaves them out of step)
     for (ConePlan *pl : {&P->planX, &P->planY}) {
         fill(pl->soc_root, pl->n_soc, NAN, s);
         fill(pl->exp_root, pl->n_exp, NAN, s);
+        clear_grid(*pl, s);
     }
 
     // z^{0,0}: the mapped starting point projected onto X x Y (reading)
@@ -1576,6 +1606,7 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
         h.step_grow_exp = S->step_grow_exp;
         h.log_cap = cap, h.log_attempts = log_att, h.log_eta = log_eta, h.log_beta = log_beta,
         h.log_omega = log_om;
+        h.rp_count = n_replay, h.rp_attempts = rp_att, h.rp_beta = rp_beta;
         h.skip_update = 1, h.status = -1;
         k_anchor[b] = kout[b] = kkt_from_raw(P, b, raw[2 * B + b]);
         if (k_anchor[b].mx() <= S->tol) status[b] = PDCS_SOLVE_OPTIMAL;
@@ -1610,6 +1641,7 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
     }
     std::vector<int32_t> code(B, 0), last_src(B, -1);
     std::vector<pdcs_info> handed(B);     // results of instances finished on their own
+    std::vector<double> done(B, -1.0);    // seconds until each instance stopped
     std::vector<char> was_handed(B, 0);
     while (any_active()) {
         // ---- step attempts until every running instance asks for a check ----
@@ -1620,12 +1652,12 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
                     todo = std::min<long long>(todo, S->check_every - hs[b].kin % S->check_every);
             const long long batch = stepwise ? 1 : std::max<long long>(1, todo);
             if (S->time_kernels) {
-                enqueue_attempts(P, batch, mixed, s, P->tev.data());
+                enqueue_attempts(P, batch, mode, s, P->tev.data());
             } else if (S->use_graph && batch == kGraphBatch) {
-                ensure_graph(P, mixed);
-                run_graph(P, mixed, s);
+                ensure_graph(P, mode);
+                run_graph(P, mode, s);
             } else {
-                enqueue_attempts(P, batch, mixed, s);
+                enqueue_attempts(P, batch, mode, s);
             }
             const long long it_before = hs[0].n_iter;
             std::vector<long long> att_before(B), acc_before(B);
@@ -1675,7 +1707,12 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
             enqueue_kkt(P, P->xc[cnd], P->yc[cnd], P->gxc[cnd], P->atyc[cnd], P->xa, P->ya, P->e, P->f, cnd);
         }
         d2h(raw.data(), P->kraw, 2 * B, s);
+        int gerr[2] = {0, 0};
+        if (P->planX.n_grid > 0) d2h(gerr, P->planX.grid_err, 1, s);
+        if (P->planY.n_grid > 0) d2h(gerr + 1, P->planY.grid_err, 1, s);
         PDCS_HIP(hipStreamSynchronize(s));
+        if (gerr[0] || gerr[1])
+            fail(PDCS_ERR_HIP, "a grid-level SOC projection timed out waiting for its workgroups");
         const double elapsed = std::chrono::duration<double>(clk::now() - t_iter).count();
         bool any_restart = false, switch_ok = mixed;
         for (int64_t b = 0; b < B; ++b) {
@@ -1684,10 +1721,11 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
             DevState &h = hs[b];
             ++checks[b];
             const Kkt k1 = kkt_from_raw(P, b, raw[b]), k2 = kkt_from_raw(P, b, raw[B + b]);
-            const int chosen = !plain && k2.avg() < k1.avg() ? 1 : 0;
+            int chosen = !plain && k2.avg() < k1.avg() ? 1 : 0;
             last_src[b] = chosen;
-            const Kkt kc = chosen ? k2 : k1;
-            const double kcv = kc.avg(), kav = k_anchor[b].avg();
+            Kkt kc = chosen ? k2 : k1;
+            double kcv = kc.avg();
+            const double kav = k_anchor[b].avg();
             int reason = 0, stop = 0;
             if (!(kcv == kcv)) {
                 status[b] = PDCS_SOLVE_NUMERICAL, stop = 1;
@@ -1707,12 +1745,26 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
                     reason = 3;
             }
             const int64_t rec = h.n_iter - 1;
+            if (rec >= 0 && rec < n_replay && tr->replay_check_code[rec] > 0) {
+                // replay: the other run's candidate, restart reason and stop
+                const int rc = tr->replay_check_code[rec] - 1;
+                chosen = rc & 1;
+                last_src[b] = chosen;
+                kc = chosen ? k2 : k1;
+                kcv = kc.avg();
+                reason = (rc >> 1) & 3;
+                stop = (rc >> 3) & 1;
+                status[b] = !stop ? -1
+                            : (h.n_iter >= S->max_iter && !(kc.mx() <= S->tol)) ? PDCS_SOLVE_ITER_LIMIT
+                                                                                : PDCS_SOLVE_OPTIMAL;
+            }
             if (tr && rec >= 0 && rec < cap) {
                 tr->check_code[rec] = 1 + chosen + 2 * reason + 8 * stop;
                 tr->check_kkt[rec] = kcv;
             }
             if (stop) {
                 kout[b] = kc;
+                done[b] = elapsed;
                 h.halt = 1;   // finished: its tiles and rows stay idle
                 emit(b, chosen);
                 continue;
@@ -1753,6 +1805,7 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
             // the kept products are recomputed in FP64 (a restart brought them
             // with its candidate already; recomputing gives the same bits)
             mixed = false;
+            mode = 0;
             for (int64_t b = 0; b < B; ++b)
                 if (active(b)) { polish_iter = hs[b].n_iter; break; }
             spmv(P->Gs, P->pG, P->x, P->gx, SpmvSkip{}, s);
@@ -1798,6 +1851,7 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
                     si.spmv += hs[b].attempts_total + hs[b].attempts_cur + hs[b].n_iter + 2 + 4 * checks[b];
                     handed[b] = si;
                     was_handed[b] = 1;
+                    done[b] = std::chrono::duration<double>(clk::now() - t_iter).count();
                     status[b] = si.status;
                     out_src[b] = src;   // written by the problem of its own
                     hs[b].halt = 1;
@@ -1835,9 +1889,11 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
         if (was_handed[b]) {
             infos[b] = handed[b];
             infos[b].setup_s = setup_s, infos[b].solve_s = solve_s;
+            infos[b].done_s = done[b];
             continue;
         }
         fill_info(infos + b, status[b], hs[b], restarts[b], spmv_count, kout[b], setup_s, solve_s);
+        infos[b].done_s = done[b] >= 0.0 ? done[b] : solve_s;
         for (int j = 0; j < PDCS_K_COUNT; ++j)
             infos[b].kernel_ms[j] = kms[j], infos[b].kernel_launches[j] = klaunch[j];
         infos[b].polish_iter = polish_iter;
@@ -2114,8 +2170,9 @@ static std::vector<int64_t> rsoc_to_soc(std::vector<int32_t> &t, const std::vect
     return rot;
 }
 
-pdcs_status pdcs_project(int64_t nblocks, const int32_t *types, const int64_t *dims, int dual,
-                         const double *d_dev, double *v_dev, void *hip_stream) {
+static pdcs_status project_impl(int64_t nblocks, const int32_t *types, const int64_t *dims,
+                                int dual, const double *d_dev, double *v_dev, void *hip_stream,
+                                int fp32proj) {
     return guarded([&] {
         if (nblocks < 0 || (nblocks > 0 && (!types || !dims || !v_dev)))
             fail(PDCS_ERR_INVALID_ARG, "NULL argument");
@@ -2132,11 +2189,21 @@ pdcs_status pdcs_project(int64_t nblocks, const int32_t *types, const int64_t *d
         int64_t *rot_dev = mem.alloc<int64_t>((int64_t)rot.size());
         h2d(rot_dev, rot.data(), (int64_t)rot.size(), s);
         rotate_pairs(v_dev, rot_dev, (int64_t)rot.size(), 0, s);
-        pass_project(plan, dual != 0, ProjArgs{v_dev, d_dev}, part, s);
+        pass_project(plan, dual != 0, ProjArgs{v_dev, d_dev, fp32proj}, part, s);
         rotate_pairs(v_dev, rot_dev, (int64_t)rot.size(), 0, s);
         PDCS_HIP(hipStreamSynchronize(s));
         check_grid(plan, s);
     });
+}
+
+pdcs_status pdcs_project(int64_t nblocks, const int32_t *types, const int64_t *dims, int dual,
+                         const double *d_dev, double *v_dev, void *hip_stream) {
+    return project_impl(nblocks, types, dims, dual, d_dev, v_dev, hip_stream, 0);
+}
+
+pdcs_status pdcs_project_fp32(int64_t nblocks, const int32_t *types, const int64_t *dims, int dual,
+                              const double *d_dev, double *v_dev, void *hip_stream) {
+    return project_impl(nblocks, types, dims, dual, d_dev, v_dev, hip_stream, 1);
 }
 
 struct pdcs_cones {
@@ -2182,6 +2249,7 @@ pdcs_status pdcs_cones_project(pdcs_cones *c, int dual, const double *d_dev, dou
         if (!c || (c->len > 0 && !v_dev)) fail(PDCS_ERR_INVALID_ARG, "NULL argument");
         if (c->n_rot > 0 && d_dev) fail(PDCS_ERR_NOT_SUPPORTED, "rotated SOC blocks are projected with D = I");
         hipStream_t s = (hipStream_t)hip_stream;
+        clear_grid(c->plan, s);   // an earlier call that timed out leaves the counters out of step
         rotate_pairs(v_dev, c->rot, c->n_rot, 0, s);
         pass_project(c->plan, dual != 0, ProjArgs{v_dev, d_dev}, c->part, s);
         rotate_pairs(v_dev, c->rot, c->n_rot, 0, s);

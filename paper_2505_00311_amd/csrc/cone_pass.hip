@@ -130,6 +130,7 @@ struct OpPrimal {  // x^ = Proj_X(x - tau (c~ - G~^T y)), acc.s0 += (x^ - x)^2
         st = a.st + inst;
         tau = st->tau;
     }
+    __host__ __device__ bool fp32() const { return a.fp32proj != 0; }
     __device__ bool skip() const { return st->halt != 0; }
     __device__ double load(int64_t j) const { return a.x[j] - tau * (a.cs[j] - a.aty[j]); }
     __device__ double scale(int64_t j) const { return a.dx[j]; }
@@ -169,6 +170,7 @@ struct OpDual {  // y^ = Proj_Y(y + sigma (h~ - 2 G~x^ + G~x)), acc: |dy|^2, <dy
         st = a.st + inst;
         sigma = st->sigma;
     }
+    __host__ __device__ bool fp32() const { return a.fp32proj != 0; }
     __device__ bool skip() const { return st->halt != 0; }
     // G~x^ at row i (finished here when the product left its last sums);
     // load and store of a row run on the same thread
@@ -214,6 +216,7 @@ struct OpCand {  // dst = Proj(src / div), div = 1 or the sum of step weights
     CandArgs a;
     double div;
     __device__ void begin(int inst) { div = a.use_avg ? a.st[inst].eta_sum : 1.0; }
+    __host__ __device__ bool fp32() const { return false; }
     __device__ bool skip() const { return false; }
     __device__ double load(int64_t j) const { return a.use_avg ? a.src[j] / div : a.src[j]; }
     __device__ double scale(int64_t j) const { return a.d[j]; }
@@ -229,6 +232,7 @@ struct OpKktRows {
     static constexpr bool kCarry = false;
     KktRowsArgs a;
     __device__ void begin(int) {}
+    __host__ __device__ bool fp32() const { return false; }
     __device__ bool skip() const { return false; }
     __device__ double load(int64_t i) const { return a.gxc[i] / a.e[i] - a.h[i]; }
     __device__ double scale(int64_t) const { return 1.0; }
@@ -252,6 +256,7 @@ struct OpKktCols {
     static constexpr bool kCarry = false;
     KktColsArgs a;
     __device__ void begin(int) {}
+    __host__ __device__ bool fp32() const { return false; }
     __device__ bool skip() const { return false; }
     __device__ double load(int64_t j) const { return a.c[j] - a.atyc[j] / a.f[j]; }
     __device__ double scale(int64_t) const { return 1.0; }
@@ -283,6 +288,7 @@ struct OpProject {
     static constexpr bool kCarry = false;
     ProjArgs a;
     __device__ void begin(int) {}
+    __host__ __device__ bool fp32() const { return a.fp32proj != 0; }
     __device__ bool skip() const { return false; }
     __device__ double load(int64_t j) const { return a.v[j]; }
     __device__ double scale(int64_t j) const { return a.d ? a.d[j] : 1.0; }
@@ -555,7 +561,7 @@ __device__ void soc_grid_part(Op &op, const Tile &tl, const int64_t *__restrict_
 }
 
 // --------------------------------------- lane-group-per-SOC block (dim <= 256)
-template <class Op, int LPB, int R>
+template <class Op, int LPB, int R, bool F32>
 __device__ __forceinline__ void soc_tile(Op &op, const Tile &tl, const int64_t *__restrict__ soc_off,
                                          const int32_t *__restrict__ soc_dim, double *soc_root,
                                          Acc &acc) {
@@ -582,7 +588,10 @@ __device__ __forceinline__ void soc_tile(Op &op, const Tile &tl, const int64_t *
         d[r] = on ? d[r] : 1.0;
     }
     double s_new;
-    soc_project_group<LPB, R>(dim, v, d, p, guess, s_new);
+    if constexpr (F32)
+        soc_project_group_f<LPB, R>(dim, v, d, p, guess, s_new);
+    else
+        soc_project_group<LPB, R>(dim, v, d, p, guess, s_new);
     if (soc_root && g == 0 && s_new == s_new) soc_root[b] = s_new;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -592,7 +601,9 @@ __device__ __forceinline__ void soc_tile(Op &op, const Tile &tl, const int64_t *
 }
 
 // ------------------------------------------------------------------ kernel
-template <class Op, bool DUAL>
+// F32: the lane-group SOC and exponential projections in FP32 (the mixed
+// form's; a kernel of its own so the FP64 kernels keep their registers).
+template <class Op, bool DUAL, bool F32>
 __global__ __launch_bounds__(kBlock) void cone_pass_kernel(Op op, const Tile *__restrict__ tiles,
                                                            const int64_t *__restrict__ soc_off,
                                                            const int32_t *__restrict__ soc_dim,
@@ -648,12 +659,12 @@ __global__ __launch_bounds__(kBlock) void cone_pass_kernel(Op op, const Tile *__
             op.store(j, v, v > 0.0 ? v : 0.0, acc);
         }
         break;
-    case kTileSoc8: soc_tile<Op, 8, 1>(op, tl, soc_off, soc_dim, soc_root, acc); break;
-    case kTileSoc16: soc_tile<Op, 16, 1>(op, tl, soc_off, soc_dim, soc_root, acc); break;
-    case kTileSoc32: soc_tile<Op, 32, 1>(op, tl, soc_off, soc_dim, soc_root, acc); break;
-    case kTileSoc64: soc_tile<Op, 64, 1>(op, tl, soc_off, soc_dim, soc_root, acc); break;
-    case kTileSoc128: soc_tile<Op, 64, 2>(op, tl, soc_off, soc_dim, soc_root, acc); break;
-    case kTileSoc256: soc_tile<Op, 64, 4>(op, tl, soc_off, soc_dim, soc_root, acc); break;
+    case kTileSoc8: soc_tile<Op, 8, 1, F32>(op, tl, soc_off, soc_dim, soc_root, acc); break;
+    case kTileSoc16: soc_tile<Op, 16, 1, F32>(op, tl, soc_off, soc_dim, soc_root, acc); break;
+    case kTileSoc32: soc_tile<Op, 32, 1, F32>(op, tl, soc_off, soc_dim, soc_root, acc); break;
+    case kTileSoc64: soc_tile<Op, 64, 1, F32>(op, tl, soc_off, soc_dim, soc_root, acc); break;
+    case kTileSoc128: soc_tile<Op, 64, 2, F32>(op, tl, soc_off, soc_dim, soc_root, acc); break;
+    case kTileSoc256: soc_tile<Op, 64, 4, F32>(op, tl, soc_off, soc_dim, soc_root, acc); break;
     case kTileSocBlock:
         soc_block(op, soc_off[tl.start], soc_dim[tl.start], acc,
                   soc_root ? soc_root + tl.start : nullptr);
@@ -670,10 +681,16 @@ __global__ __launch_bounds__(kBlock) void cone_pass_kernel(Op op, const Tile *__
             const double dr = op.scale(off), ds = op.scale(off + 1), dt = op.scale(off + 2);
             double pr, ps, pt, rho;
             const double guess = exp_root ? exp_root[tl.start + tid] : __builtin_nan("");
-            if (kind == kTileExp)
+            if constexpr (F32) {
+                if (kind == kTileExp)
+                    exp_project_f(r0, s0, t0, dr, ds, dt, pr, ps, pt, guess, rho);
+                else
+                    exp_dual_project_f(r0, s0, t0, dr, ds, dt, pr, ps, pt, guess, rho);
+            } else if (kind == kTileExp) {
                 exp_project(r0, s0, t0, dr, ds, dt, pr, ps, pt, guess, rho);
-            else
+            } else {
                 exp_dual_project(r0, s0, t0, dr, ds, dt, pr, ps, pt, guess, rho);
+            }
             if (exp_root && rho == rho) exp_root[tl.start + tid] = rho;
             store_ld(op, off, lr, pr, acc);
             store_ld(op, off + 1, ls, ps, acc);
@@ -687,10 +704,27 @@ __global__ __launch_bounds__(kBlock) void cone_pass_kernel(Op op, const Tile *__
 template <class Op, bool DUAL>
 static void launch(const ConePlan &p, const Op &op, double *partials, hipStream_t s) {
     if (p.ntiles == 0) return;
-    hipLaunchKernelGGL((cone_pass_kernel<Op, DUAL>), dim3((unsigned)p.ntiles), dim3(kBlock), 0, s,
-                       op, p.tiles, p.soc_off, p.soc_dim, p.exp_off, partials,
-                       Op::kWarm ? p.soc_root : nullptr, Op::kWarm ? p.exp_root : nullptr,
-                       GridSync{p.grid_ctr, p.grid_part, p.grid_err});
+    const GridSync gs{p.grid_ctr, p.grid_part, p.grid_err};
+    double *sr = Op::kWarm ? p.soc_root : nullptr, *er = Op::kWarm ? p.exp_root : nullptr;
+    if (op.fp32())
+        hipLaunchKernelGGL((cone_pass_kernel<Op, DUAL, true>), dim3((unsigned)p.ntiles), dim3(kBlock), 0,
+                           s, op, p.tiles, p.soc_off, p.soc_dim, p.exp_off, partials, sr, er, gs);
+    else
+        hipLaunchKernelGGL((cone_pass_kernel<Op, DUAL, false>), dim3((unsigned)p.ntiles), dim3(kBlock), 0,
+                           s, op, p.tiles, p.soc_off, p.soc_dim, p.exp_off, partials, sr, er, gs);
+    PDCS_HIP(hipGetLastError());
+}
+
+__global__ void clear_grid_kernel(unsigned long long *ctr, int64_t n, int *err) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) ctr[i] = 0ull;
+    if (i == 0) *err = 0;
+}
+
+void clear_grid(const ConePlan &p, hipStream_t s) {
+    if (p.n_grid == 0) return;
+    hipLaunchKernelGGL(clear_grid_kernel, dim3((unsigned)((p.n_grid + 255) / 256)), dim3(256), 0, s,
+                       p.grid_ctr, p.n_grid, p.grid_err);
     PDCS_HIP(hipGetLastError());
 }
 

@@ -372,4 +372,281 @@ __device__ void soc_project_group(int dim, const double (&v)[R], const double (&
     s_out = s;
 }
 
+// ------------------------------------------ FP32 projections (mixed form)
+// The mixed-precision form (not in the paper) may project the lane-group SOC
+// blocks and the exponential cones in FP32 arithmetic: inputs are rounded to
+// FP32, the norms, case tests and root search run in FP32, and the result is
+// widened back.  FP64 stays where FP32 cannot be trusted: the exponential
+// cone's case tests (membership of v0 and -D v0), its bracket ends, and every
+// search that leaves the FP32 range or does not converge fall back to the FP64
+// routines above on the same input.
+constexpr float kEpsF = 1.1920929e-7f;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_partner_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// group_sum for FP32 values: the same involutions, one 32-bit exchange per stage
+template <int LPB>
+__device__ __forceinline__ float group_sum_f(float v) {
+#pragma clang fp contract(off)
+    if (LPB >= 2) v = v + dpp_partner_f<0xB1>(v);
+    if (LPB >= 4) v = v + dpp_partner_f<0x4E>(v);
+    if (LPB >= 8) v = v + dpp_partner_f<0x141>(v);
+    if (LPB >= 16) v = v + dpp_partner_f<0x140>(v);
+    if (LPB >= 32) {
+        const float o = __shfl_xor(v, 16, kWave);
+        v = v + o;
+    }
+    if (LPB >= 64) {
+        const float o = __shfl_xor(v, 32, kWave);
+        v = v + o;
+    }
+    return v;
+}
+
+// soc_project_group in FP32 arithmetic (same cases, bracket and safeguarded
+// Newton search).  The FP64 routine takes over, for the whole group, when a
+// search value leaves the FP32 range or the search does not settle within 60
+// steps (both decisions are taken on group sums, so the group stays together).
+template <int LPB, int R>
+__device__ void soc_project_group_f(int dim, const double (&v)[R], const double (&d)[R],
+                                    double (&p)[R], double s_guess, double &s_out) {
+    s_out = __builtin_nan("");
+    const int lane = threadIdx.x % kWave;
+    const int g = lane % LPB;
+    const int base = lane - g;
+    const float t = (float)__shfl(v[0], base, kWave);
+    const double d0 = __shfl(d[0], base, kWave);
+    float x[R], dh[R];
+    float snd = 0.0f, sndi = 0.0f, snx = 0.0f;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = g + LPB * r;
+        const bool on = e >= 1 && e < dim;
+        x[r] = on ? (float)v[r] : 0.0f;
+        dh[r] = on ? (float)(d[r] / d0) : 1.0f;
+        snd += (dh[r] * x[r]) * (dh[r] * x[r]);
+        sndi += (x[r] / dh[r]) * (x[r] / dh[r]);
+        snx += x[r] * x[r];
+    }
+    const float nd = sqrtf(group_sum_f<LPB>(snd));
+    const float ndi = sqrtf(group_sum_f<LPB>(sndi));
+    const float nx2 = group_sum_f<LPB>(snx);
+    if (!(isfinite(nd) && isfinite(ndi) && isfinite(nx2) && isfinite(t))) {
+        soc_project_group<LPB, R>(dim, v, d, p, s_guess, s_out);
+        return;
+    }
+    if (t <= 0.0f && nd <= -t) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) p[r] = 0.0;
+        return;
+    }
+    if (ndi <= t) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) p[r] = v[r];
+        return;
+    }
+    if (t == 0.0f) {
+        float s2 = 0.0f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float q = x[r] / (dh[r] + 1.0f / dh[r]);
+            s2 += q * q;
+            p[r] = (double)(x[r] / (1.0f + 1.0f / (dh[r] * dh[r])));
+        }
+        s2 = sqrtf(group_sum_f<LPB>(s2));
+        if (g == 0) p[0] = (double)s2;
+        return;
+    }
+    float w[R], h2[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        w[r] = (x[r] * dh[r]) * (x[r] * dh[r]);
+        h2[r] = dh[r] * dh[r];
+    }
+    const float lo = t > 0.0f ? t : 0.0f, hi = sqrtf(t * t + nx2);
+    float xpos = lo, xneg = hi;
+    float s = 0.5f * (t + sqrtf(nx2));
+    if (!(s > lo && s < hi)) s = 0.5f * (lo + hi);
+    const float sg = (float)s_guess;
+    if (sg > lo && sg < hi) s = sg;
+    float dxold = hi - lo, dx = dxold;
+    auto eval = [&](float ss, float &f, float &df) {
+        const float a = 1.0f - t / ss;
+        float g1 = 0.0f, g2 = 0.0f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float iq = 1.0f / (h2[r] + a);
+            const float u = w[r] * iq * iq;
+            g1 += u;
+            g2 += u * iq;
+        }
+        g1 = group_sum_f<LPB>(g1);
+        g2 = group_sum_f<LPB>(g2);
+        f = g1 - ss * ss;
+        df = -2.0f * (t / (ss * ss)) * g2 - 2.0f * ss;
+    };
+    float f, df;
+    eval(s, f, df);
+    bool settled = false;
+    for (int it = 0; it < 60; ++it) {
+        if (f == 0.0f) {
+            settled = true;
+            break;
+        }
+        if (f > 0.0f)
+            xpos = s;
+        else
+            xneg = s;
+        const bool finite = isfinite(f) && isfinite(df) && df != 0.0f;
+        if (!finite) break;   // out of the FP32 range: FP64 below
+        const bool out = ((s - xpos) * df - f) * ((s - xneg) * df - f) > 0.0f;
+        const bool slow = fabsf(2.0f * f) > fabsf(dxold * df);
+        dxold = dx;
+        if (out || slow) {
+            dx = 0.5f * (xneg - xpos);
+            s = xpos + dx;
+        } else {
+            dx = f / df;
+            s -= dx;
+        }
+        if (fabsf(dx) <= 4.0f * kEpsF * s) {
+            settled = true;
+            break;
+        }
+        eval(s, f, df);
+    }
+    if (!settled) {
+        soc_project_group<LPB, R>(dim, v, d, p, s_guess, s_out);
+        return;
+    }
+    const float a = 1.0f - t / s;
+#pragma unroll
+    for (int r = 0; r < R; ++r) p[r] = (double)(x[r] / (1.0f + a / h2[r]));
+    if (g == 0) p[0] = (double)s;
+    s_out = (double)s;
+}
+
+// e^{-|rho|} h(rho) and its derivative in FP32 (exp_hs in FP32 arithmetic).
+struct ExpPtF {
+    float r0, s0, t0, ds, dt, tau, idr, idt;
+};
+
+__device__ __forceinline__ void exp_hs_f(const ExpPtF &c, float rho, float &f, float &df) {
+    const float den = rho * rho - rho + c.tau * c.tau;
+    const float iden = 1.0f / den;
+    const float ns = c.s0 * c.tau - c.r0 + c.r0 * rho;
+    const float nr = c.tau * c.r0 - rho * c.s0;
+    const float sp = ns * iden * c.idr;
+    const float rd = c.ds * nr * iden;
+    const float q = 2.0f * rho - 1.0f;
+    const float dsp = (c.r0 * den - ns * q) * (iden * iden) * c.idr;
+    const float drd = c.ds * (-c.s0 * den - nr * q) * (iden * iden);
+    if (rho >= 0.0f) {
+        const float em = expf(-rho);
+        f = c.dt * sp - em * em * rd * c.idt - c.t0 * em;
+        df = c.dt * dsp + em * em * (2.0f * rd - drd) * c.idt + c.t0 * em;
+    } else {
+        const float ep = expf(rho);
+        f = c.dt * ep * ep * sp - rd * c.idt - c.t0 * ep;
+        df = c.dt * ep * ep * (2.0f * sp + dsp) - drd * c.idt - c.t0 * ep;
+    }
+}
+
+// The FP64 routine as the FP32 paths' fallback, kept out of line so that the
+// rarely taken fallback does not add its registers to the FP32 path's.
+__device__ __noinline__ void exp_project_fallback(double r0, double s0, double t0, double dr,
+                                                  double ds, double dt, double &pr, double &ps,
+                                                  double &pt, double guess, double &rho_out) {
+    exp_project(r0, s0, t0, dr, ds, dt, pr, ps, pt, guess, rho_out);
+}
+
+// exp_project with the case-4 root search in FP32 when the search interval
+// lies inside |rho| <= 40 (e^{-2|rho|} stays a normal FP32 number); the case
+// tests, the interval, every other search and any FP32 search that does not
+// settle within 60 steps are the FP64 routine's.
+__device__ void exp_project_f(double r0, double s0, double t0, double dr, double ds, double dt,
+                              double &pr, double &ps, double &pt, double guess, double &rho_out) {
+    constexpr double RF = 40.0;
+    const bool c4 = !in_kexp(r0 / dr, s0 / ds, t0 / dt) && !in_kexp_dual(-dr * r0, -ds * s0, -dt * t0) &&
+                    !(r0 <= 0.0 && s0 <= 0.0);
+    double lo = 0.0, hi = 0.0;
+    bool fits = false;
+    if (c4) {
+        if (r0 > 0.0 && s0 > 0.0) {
+            hi = r0 * ds / (s0 * dr);
+            lo = 1.0 - s0 * ds / (r0 * dr);
+            fits = lo >= -RF && hi <= RF;
+        }
+    }
+    if (!fits) {   // cases 1-3, unbounded intervals, or beyond the FP32 range
+        exp_project_fallback(r0, s0, t0, dr, ds, dt, pr, ps, pt, guess, rho_out);
+        return;
+    }
+    const ExpPtF c{(float)r0, (float)s0, (float)t0, (float)ds, (float)dt, (float)(ds / dr),
+                   (float)(1.0 / dr), (float)(1.0 / dt)};
+    float xneg = (float)lo, xpos = (float)hi;
+    float rho = (guess > lo && guess < hi) ? (float)guess : 0.5f * (xneg + xpos);
+    if (!(rho >= fminf(xneg, xpos) && rho <= fmaxf(xneg, xpos))) rho = 0.5f * (xneg + xpos);
+    float dxold = fabsf(xpos - xneg), dx = dxold;
+    float f, df;
+    exp_hs_f(c, rho, f, df);
+    bool settled = false;
+    for (int it = 0; it < 60; ++it) {
+        if (f == 0.0f) {
+            settled = true;
+            break;
+        }
+        if (f < 0.0f)
+            xneg = rho;
+        else
+            xpos = rho;
+        const bool finite = isfinite(f) && isfinite(df) && df != 0.0f;
+        if (!finite) break;
+        const bool out = ((rho - xpos) * df - f) * ((rho - xneg) * df - f) > 0.0f;
+        const bool slow = fabsf(2.0f * f) > fabsf(dxold * df);
+        dxold = dx;
+        if (out || slow) {
+            dx = 0.5f * (xpos - xneg);
+            rho = xneg + dx;
+        } else {
+            dx = f / df;
+            rho -= dx;
+        }
+        if (fabsf(dx) <= 4.0f * kEpsF * fmaxf(1.0f, fabsf(rho))) {
+            settled = true;
+            break;
+        }
+        exp_hs_f(c, rho, f, df);
+    }
+    if (!settled) {
+        exp_project_fallback(r0, s0, t0, dr, ds, dt, pr, ps, pt, guess, rho_out);
+        return;
+    }
+    rho_out = (double)rho;
+    // v_p = projection of v0 onto the ray w(rho), as in exp_project
+    float w0, w1, w2;
+    if (rho > 0.0f) {
+        const float em = expf(-rho);
+        w0 = (float)dr * rho * em, w1 = (float)ds * em, w2 = (float)dt;
+    } else {
+        w0 = (float)dr * rho, w1 = (float)ds, w2 = (float)dt * expf(rho);
+    }
+    float cf = (c.r0 * w0 + c.s0 * w1 + c.t0 * w2) / (w0 * w0 + w1 * w1 + w2 * w2);
+    if (!(cf > 0.0f)) cf = 0.0f;
+    pr = (double)(cf * w0);
+    ps = (double)(cf * w1);
+    pt = (double)(cf * w2);
+}
+
+__device__ __forceinline__ void exp_dual_project_f(double r0, double s0, double t0, double dr,
+                                                   double ds, double dt, double &pr, double &ps,
+                                                   double &pt, double guess, double &rho_out) {
+    double qr, qs, qt;
+    exp_project_f(-r0, -s0, -t0, 1.0 / dr, 1.0 / ds, 1.0 / dt, qr, qs, qt, guess, rho_out);
+    pr = r0 + qr, ps = s0 + qs, pt = t0 + qt;
+}
+
 }  // namespace pdcs

@@ -53,14 +53,18 @@ __device__ void decide_body(DevState *__restrict__ st, const double *__restrict_
     const double e2 = (1.0 + pow(nn, -st->step_grow_exp)) * eta;
     const bool fixed = st->step_mode == 1;   // fixed step: every attempt is accepted
     const double enew = fixed ? eta : (e1 < e2 ? e1 : e2);
-    if (fixed || eta <= ebar) {
+    // replay: the other run's attempt count decides acceptance, its beta the branch
+    const bool replay = st->n_iter < st->rp_count;
+    const bool accept = fixed || (replay ? st->attempts_cur == st->rp_attempts[st->n_iter] : eta <= ebar);
+    if (accept) {
         const double r = sqrt(omega * nx2 + ny2 / omega);
         double beta;
-        if (st->beta_mode == 1)
+        if (st->beta_mode == 1) {
             beta = st->beta_const;
-        else
-            beta = r <= st->r_prev ? fmin(1.0, st->beta_grow * st->beta_prev)
-                                   : st->beta_shrink * st->beta_prev;
+        } else {
+            const bool grow = replay ? st->rp_beta[st->n_iter] >= st->beta_prev : r <= st->r_prev;
+            beta = grow ? fmin(1.0, st->beta_grow * st->beta_prev) : st->beta_shrink * st->beta_prev;
+        }
         st->r_prev = r;
         st->beta_prev = beta;
         st->beta = beta;

@@ -203,6 +203,12 @@ struct DevState {
     long long log_cap;
     int *log_attempts;
     double *log_eta, *log_beta, *log_omega;
+    // replay of another run's decisions for the first rp_count accepted
+    // iterations (parity harness): accept at attempt rp_attempts[k]; the
+    // reflection parameter grows when rp_beta[k] >= beta_prev
+    long long rp_count;
+    const int *rp_attempts;
+    const double *rp_beta;
 };
 
 // Per-candidate raw KKT reductions (unscaled quantities), see kkt kernels.
@@ -264,7 +270,12 @@ void to_float(const double *in, float *out, int64_t n, hipStream_t s);
 int choose_lanes(double avg_row_nnz);
 
 // setup.hip
-void transpose_csr(const Csr &A, Csr &At, hipStream_t s);   // At arrays preallocated
+// One diagonal block of a block-diagonal CSR matrix (an instance of a batch).
+struct TBlock {
+    int64_t r0, rows, c0, cols, k0, nnz;
+};
+// At (arrays preallocated) = A^T, block by block; each block below 2^31 entries
+void transpose_csr(const Csr &A, Csr &At, const TBlock *blocks, int64_t nblocks, hipStream_t s);
 void fill(double *p, int64_t n, double v, hipStream_t s);
 void rows_absmax_scaled(const Csr &A, const double *er, const double *ec, bool row_first,
                         double *out, hipStream_t s);
@@ -308,12 +319,14 @@ struct PrimalArgs {
     double *xh;
     const DevState *st;
     float *xh32 = nullptr;   // FP32 copy of x^ for the FP32 product (mixed form)
+    int fp32proj = 0;        // 1: lane-group SOC and exponential projections in FP32
 };
 struct DualArgs {
     const double *y, *gxh, *gx, *hs, *dy;
     double *yh;
     const DevState *st;
     float *yh32 = nullptr;   // FP32 copy of y^ for the FP32 product (mixed form)
+    int fp32proj = 0;        // 1: lane-group SOC and exponential projections in FP32
     // when active, G~x^ is finished here from what spmv_head left in gxh, and
     // written to gxh_out
     ProductTail gt{};
@@ -336,6 +349,7 @@ struct KktColsArgs {
 struct ProjArgs {
     double *v;
     const double *d;
+    int fp32proj = 0;        // 1: lane-group SOC and exponential projections in FP32
 };
 void pass_primal(const ConePlan &p, const PrimalArgs &a, double *partials, hipStream_t s);
 void pass_dual(const ConePlan &p, const DualArgs &a, double *partials, hipStream_t s);
@@ -345,6 +359,9 @@ void pass_kkt_rows(const ConePlan &p, const KktRowsArgs &a, double *partials, hi
 void pass_kkt_cols(const ConePlan &p, const KktColsArgs &a, double *partials, hipStream_t s);
 void pass_project(const ConePlan &p, bool dual, const ProjArgs &a, double *partials,
                   hipStream_t s);
+// Zeroes the grid-level SOC blocks' barrier counters and error flag (a kernel,
+// so the clear may also sit in a captured graph).
+void clear_grid(const ConePlan &p, hipStream_t s);
 
 // iterate.hip
 struct HalpernArgs {

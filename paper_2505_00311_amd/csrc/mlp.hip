@@ -9,10 +9,12 @@
 // BF16.  op(A)(m, k) = a[m lda + k] (ta = 0) or a[k lda + m] (ta = 1); op(B)(k, n)
 // = b[k ldb + n] (tb = 0) or b[n ldb + k] (tb = 1).  A workgroup of 4 wavefronts
 // owns a 128 x 128 tile of C, each wavefront a 64 x 64 quarter (2 x 2 blocks of
-// 32 x 32 on the matrix cores); K advances by 32 through LDS, where each row of
-// A and each column of B keeps its k-values contiguous so a lane reads its 8
-// operands in one 16-byte access, and operands read along k come in 16-byte
-// vectors when their rows are aligned.
+// 32 x 32 on the matrix cores); K advances through LDS, where each row of A and
+// each column of B keeps its k-values contiguous so a lane reads its 8
+// operands in one 16-byte access.  When both operands are read along k with
+// aligned rows (the forward pass), K advances by 64 and the next slab's global
+// loads overlap the current slab's MFMAs (gemm_bf16_pipe_kernel); the other
+// transpose combinations advance by 32, staging and computing in turn.
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
@@ -127,6 +129,106 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int64_t M, int64_t N, in
     }
 }
 
+// The common case of the network (both operands read along k with 16-byte
+// vectors: the forward pass and dH = dZ W), pipelined: the global loads of the
+// next 64-wide k-slab go to registers while the matrix cores work on the
+// current one in LDS, so the load latency overlaps the MFMAs instead of
+// preceding them.  Same tile and MFMA layout as gemm_bf16_kernel.
+constexpr int kKStepP = 64, kLdsKP = 72;   // LDS row: 64 k-values + 8 padding
+
+// op(X)[r0 .. r0+127][k0 .. k0+63] (X read along k, 8-aligned rows) into four
+// 16-byte registers per thread, zero outside.
+__device__ __forceinline__ void fetch_k64(uint4 (&r)[4], const uint16_t *__restrict__ x, int64_t ld,
+                                          int64_t R, int64_t K, int64_t r0, int64_t k0) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = t + u * 256, rr = e / 8, c = (e % 8) * 8;
+        const int64_t gr = r0 + rr, gk = k0 + c;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (gr < R && gk + 7 < K) {
+            v = *reinterpret_cast<const uint4 *>(x + gr * ld + gk);
+        } else if (gr < R && gk < K) {   // the ragged end of k
+            uint32_t q[4];
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t lo = gk + 2 * j < K ? x[gr * ld + gk + 2 * j] : 0;
+                const uint32_t hi = gk + 2 * j + 1 < K ? x[gr * ld + gk + 2 * j + 1] : 0;
+                q[j] = lo | (hi << 16);
+            }
+            v = make_uint4(q[0], q[1], q[2], q[3]);
+        }
+        r[u] = v;
+    }
+}
+
+__device__ __forceinline__ void put_k64(uint16_t (*S)[kLdsKP], const uint4 (&r)[4]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = t + u * 256, rr = e / 8, c = (e % 8) * 8;
+        *reinterpret_cast<uint4 *>(&S[rr][c]) = r[u];
+    }
+}
+
+__global__ __launch_bounds__(256) void gemm_bf16_pipe_kernel(int64_t M, int64_t N, int64_t K,
+                                                             const uint16_t *__restrict__ a, int64_t lda,
+                                                             const uint16_t *__restrict__ b, int64_t ldb,
+                                                             const float *__restrict__ bias, int relu,
+                                                             float *__restrict__ c32,
+                                                             uint16_t *__restrict__ c16, int64_t ldc) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[kTile][kLdsKP];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kTile][kLdsKP];
+    const int t = threadIdx.x, lane = t % 64, w = t / 64;
+    const int wm = w / 2, wn = w % 2;
+    const int64_t m0 = (int64_t)blockIdx.y * kTile, n0 = (int64_t)blockIdx.x * kTile;
+    f32x16 acc[2][2] = {};
+    const int half = lane / 32, idx = lane % 32;
+    uint4 ra[4], rb[4];
+    fetch_k64(ra, a, lda, M, K, m0, 0);
+    fetch_k64(rb, b, ldb, N, K, n0, 0);
+    for (int64_t k0 = 0; k0 < K; k0 += kKStepP) {
+        put_k64(As, ra);
+        put_k64(Bs, rb);
+        __syncthreads();
+        if (k0 + kKStepP < K) {   // the next slab's loads fly during this slab's MFMAs
+            fetch_k64(ra, a, lda, M, K, m0, k0 + kKStepP);
+            fetch_k64(rb, b, ldb, N, K, n0, k0 + kKStepP);
+        }
+#pragma unroll
+        for (int kk = 0; kk < kKStepP; kk += 16) {
+            bf16x8 av[2], bv[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                av[i] = *reinterpret_cast<const bf16x8 *>(&As[wm * 64 + i * 32 + idx][kk + 8 * half]);
+                bv[i] = *reinterpret_cast<const bf16x8 *>(&Bs[wn * 64 + i * 32 + idx][kk + 8 * half]);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int64_t gn = n0 + wn * 64 + j * 32 + idx;
+        if (gn >= N) continue;
+        const float bn = bias ? bias[gn] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t gm = m0 + wm * 64 + i * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+                if (gm >= M) continue;
+                float v = acc[i][j][r] + bn;
+                if (relu && v < 0.0f) v = 0.0f;
+                if (c32) c32[gm * ldc + gn] = v;
+                if (c16) c16[gm * ldc + gn] = f32_to_bf16(v);
+            }
+    }
+}
+
 void gemm_bf16(int ta, int tb, int64_t M, int64_t N, int64_t K, const uint16_t *a, int64_t lda,
                const uint16_t *b, int64_t ldb, const float *bias, int relu, float *c32,
                uint16_t *c16, int64_t ldc, hipStream_t s) {
@@ -139,7 +241,9 @@ void gemm_bf16(int ta, int tb, int64_t M, int64_t N, int64_t K, const uint16_t *
     hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, VA, VB>), grid, dim3(256), 0, s, M, N, K, a, lda, \
                        b, ldb, bias, relu, c32, c16, ldc)
     if (ta == 0 && tb == 1) {
-        if (va && vb) PDCS_GEMM(0, 1, true, true);
+        if (va && vb)
+            hipLaunchKernelGGL(gemm_bf16_pipe_kernel, grid, dim3(256), 0, s, M, N, K, a, lda, b, ldb,
+                               bias, relu, c32, c16, ldc);
         else if (va) PDCS_GEMM(0, 1, true, false);
         else if (vb) PDCS_GEMM(0, 1, false, true);
         else PDCS_GEMM(0, 1, false, false);

@@ -2,6 +2,7 @@
 // diagonal rescaling of Section 3 (reading: Ruiz infinity-norm passes, then one
 // Pock-Chambolle pass with alpha = 1), the scaled problem vectors, input
 // validation and small deterministic reductions.
+#include <algorithm>
 #include <cmath>
 
 #include <rocprim/device/device_radix_sort.hpp>
@@ -21,24 +22,28 @@ __global__ void iota_kernel(int32_t *p, int64_t n) {
     if (i < n) p[i] = (int32_t)i;
 }
 
-// rp[j] = first position whose sorted key is >= j
-__global__ void rowptr_from_sorted(const int32_t *__restrict__ keys, int64_t nnz, int64_t nrows,
-                                   int64_t *__restrict__ rp) {
+// Rows [c0, c0 + cols] of the transpose's row pointers from the block's sorted
+// column keys (global columns in [c0, c0 + cols)): rp[j] = k0 + the first
+// position whose key is >= j.
+__global__ void rowptr_from_sorted(const int32_t *__restrict__ keys, int64_t nnz, int64_t c0,
+                                   int64_t cols, int64_t k0, int64_t *__restrict__ rp) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k > nnz) return;
-    const int64_t prev = k == 0 ? -1 : (int64_t)keys[k - 1];
-    const int64_t cur = k == nnz ? nrows : (int64_t)keys[k];
-    for (int64_t j = prev + 1; j <= cur; ++j) rp[j] = k;
+    const int64_t prev = k == 0 ? c0 - 1 : (int64_t)keys[k - 1];
+    const int64_t cur = k == nnz ? c0 + cols : (int64_t)keys[k];
+    for (int64_t j = prev + 1; j <= cur; ++j) rp[j] = k0 + k;
 }
 
-// entry p of G^T is entry perm[p] of G; its column in G^T is that entry's row
-__global__ void gather_transpose(const int64_t *__restrict__ rp, int64_t m,
+// Entry k0 + p of the transposed block is entry k0 + perm[p] of the block;
+// its column in G^T is that entry's row, found among rows [r0, r0 + rows].
+__global__ void gather_transpose(const int64_t *__restrict__ rp, int64_t r0, int64_t rows,
                                  const double *__restrict__ v, const int32_t *__restrict__ perm,
-                                 int64_t nnz, int32_t *__restrict__ tci, double *__restrict__ tv) {
+                                 int64_t k0, int64_t nnz, int32_t *__restrict__ tci,
+                                 double *__restrict__ tv) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nnz) return;
-    const int64_t k = perm[p];
-    int64_t lo = 0, hi = m;  // largest row i with rp[i] <= k
+    const int64_t k = k0 + perm[p];
+    int64_t lo = r0, hi = r0 + rows;  // largest row i with rp[i] <= k
     while (hi - lo > 1) {
         const int64_t mid = (lo + hi) / 2;
         if (rp[mid] <= k)
@@ -46,42 +51,60 @@ __global__ void gather_transpose(const int64_t *__restrict__ rp, int64_t m,
         else
             hi = mid;
     }
-    tci[p] = (int32_t)lo;
-    tv[p] = v[k];
+    tci[k0 + p] = (int32_t)lo;
+    tv[k0 + p] = v[k];
 }
 
-void transpose_csr(const Csr &A, Csr &At, hipStream_t s) {
-    const int64_t nnz = A.nnz;
-    if (nnz == 0) {
-        hipLaunchKernelGGL(rowptr_from_sorted, dim3(1), dim3(1), 0, s, (const int32_t *)nullptr,
-                           (int64_t)0, At.rows, At.rp);
-        PDCS_HIP(hipGetLastError());
-        return;
-    }
+// The transpose of a block-diagonal A, block by block (a single problem is
+// one block): each block's entries are sorted by column with a stable radix
+// sort of 32-bit positions, so a block needs fewer than 2^31 entries while
+// the whole matrix may hold more.  Block b of A (rows [r0, r0 + rows),
+// columns [c0, c0 + cols), entries [k0, k0 + nnz)) becomes rows [c0, c0 +
+// cols) and the same entries of At.
+void transpose_csr(const Csr &A, Csr &At, const TBlock *blocks, int64_t nblocks, hipStream_t s) {
+    int64_t big = 0;
+    for (int64_t b = 0; b < nblocks; ++b) big = std::max(big, blocks[b].nnz);
+    if (big >= ((int64_t)1 << 31))
+        throw_hip(hipErrorInvalidValue, "transpose block of 2^31 or more entries", __FILE__, __LINE__);
     int32_t *keys_out = nullptr, *perm_in = nullptr, *perm_out = nullptr;
-    PDCS_HIP(hipMallocAsync((void **)&keys_out, sizeof(int32_t) * nnz, s));
-    PDCS_HIP(hipMallocAsync((void **)&perm_in, sizeof(int32_t) * nnz, s));
-    PDCS_HIP(hipMallocAsync((void **)&perm_out, sizeof(int32_t) * nnz, s));
-    hipLaunchKernelGGL(iota_kernel, dim3(grid_for(nnz)), dim3(kBlock), 0, s, perm_in, nnz);
+    void *tmp = nullptr;
+    size_t tmp_bytes = 0;
     unsigned bits = 1;
     while (bits < 31 && ((int64_t)1 << bits) < A.cols) ++bits;
-    size_t tmp_bytes = 0;
-    PDCS_HIP(rocprim::radix_sort_pairs(nullptr, tmp_bytes, A.ci, keys_out, perm_in, perm_out,
-                                       (size_t)nnz, 0, bits, s));
-    void *tmp = nullptr;
-    PDCS_HIP(hipMallocAsync(&tmp, tmp_bytes, s));
-    // LSD radix sort is stable: entries of a column keep increasing row order
-    PDCS_HIP(rocprim::radix_sort_pairs(tmp, tmp_bytes, A.ci, keys_out, perm_in, perm_out,
-                                       (size_t)nnz, 0, bits, s));
-    hipLaunchKernelGGL(rowptr_from_sorted, dim3(grid_for(nnz + 1)), dim3(kBlock), 0, s, keys_out,
-                       nnz, At.rows, At.rp);
-    hipLaunchKernelGGL(gather_transpose, dim3(grid_for(nnz)), dim3(kBlock), 0, s, A.rp, A.rows,
-                       A.v, perm_out, nnz, At.ci, At.v);
+    if (big > 0) {
+        PDCS_HIP(hipMallocAsync((void **)&keys_out, sizeof(int32_t) * big, s));
+        PDCS_HIP(hipMallocAsync((void **)&perm_in, sizeof(int32_t) * big, s));
+        PDCS_HIP(hipMallocAsync((void **)&perm_out, sizeof(int32_t) * big, s));
+        PDCS_HIP(rocprim::radix_sort_pairs(nullptr, tmp_bytes, A.ci, keys_out, perm_in, perm_out,
+                                           (size_t)big, 0, bits, s));
+        PDCS_HIP(hipMallocAsync(&tmp, tmp_bytes, s));
+    }
+    for (int64_t b = 0; b < nblocks; ++b) {
+        const TBlock &B = blocks[b];
+        if (B.nnz == 0) {
+            hipLaunchKernelGGL(rowptr_from_sorted, dim3(1), dim3(1), 0, s, (const int32_t *)nullptr,
+                               (int64_t)0, B.c0, B.cols, B.k0, At.rp);
+            continue;
+        }
+        hipLaunchKernelGGL(iota_kernel, dim3(grid_for(B.nnz)), dim3(kBlock), 0, s, perm_in, B.nnz);
+        size_t need = 0;
+        PDCS_HIP(rocprim::radix_sort_pairs(nullptr, need, A.ci + B.k0, keys_out, perm_in, perm_out,
+                                           (size_t)B.nnz, 0, bits, s));
+        // LSD radix sort is stable: entries of a column keep increasing row order
+        PDCS_HIP(rocprim::radix_sort_pairs(tmp, need, A.ci + B.k0, keys_out, perm_in, perm_out,
+                                           (size_t)B.nnz, 0, bits, s));
+        hipLaunchKernelGGL(rowptr_from_sorted, dim3(grid_for(B.nnz + 1)), dim3(kBlock), 0, s, keys_out,
+                           B.nnz, B.c0, B.cols, B.k0, At.rp);
+        hipLaunchKernelGGL(gather_transpose, dim3(grid_for(B.nnz)), dim3(kBlock), 0, s, A.rp, B.r0,
+                           B.rows, A.v, perm_out, B.k0, B.nnz, At.ci, At.v);
+    }
     PDCS_HIP(hipGetLastError());
-    PDCS_HIP(hipFreeAsync(tmp, s));
-    PDCS_HIP(hipFreeAsync(keys_out, s));
-    PDCS_HIP(hipFreeAsync(perm_in, s));
-    PDCS_HIP(hipFreeAsync(perm_out, s));
+    if (big > 0) {
+        PDCS_HIP(hipFreeAsync(tmp, s));
+        PDCS_HIP(hipFreeAsync(keys_out, s));
+        PDCS_HIP(hipFreeAsync(perm_in, s));
+        PDCS_HIP(hipFreeAsync(perm_out, s));
+    }
 }
 
 // ------------------------------------------------------------- rescaling

@@ -277,6 +277,57 @@ def batch_lp_soc(seed, count, n_lo=1000, n_hi=100_000, density=0.005, soc_frac=0
     return out
 
 
+def bernoulli_csr_gaps(rng, m, n, density):
+    """Bernoulli(density) pattern over the m x n positions in row-major order,
+    drawn as a Bernoulli process: the gaps between successive present
+    positions are geometric(density), so every position is present
+    independently with probability density, in O(nnz); N(0,1) values."""
+    total = m * n
+    if total == 0 or density <= 0.0:
+        return np.zeros(m + 1, np.int64), np.zeros(0, np.int32), np.zeros(0)
+    mean = total * density
+    pos = np.cumsum(rng.geometric(density, size=int(mean + 8 * np.sqrt(mean) + 64))) - 1
+    while pos[-1] < total:
+        more = np.cumsum(rng.geometric(density, size=int(0.01 * mean) + 64)) + pos[-1]
+        pos = np.concatenate([pos, more])
+    pos = pos[pos < total]
+    rp = np.zeros(m + 1, dtype=np.int64)
+    rp[1:] = np.cumsum(np.bincount(pos // n, minlength=m))
+    return rp, (pos % n).astype(np.int32), rng.standard_normal(pos.size)
+
+
+def batch_sizes(seed, count, n_lo=1000, n_hi=100_000):
+    """The variable counts n_b ~ U{n_lo..n_hi} of batch_member(seed, b, ...)."""
+    return np.random.default_rng(seed).integers(n_lo, n_hi + 1, size=count)
+
+
+def batch_member(seed, b, count, n_lo=1000, n_hi=100_000, density=0.005, soc_frac=0.2,
+                 soc_lo=3, soc_hi=50):
+    """Instance b of a batch of `count` independent planted LP/SOCP instances
+    with the recipe of batch_lp_soc (n_b ~ U{n_lo..n_hi}, m = n/2, G
+    Bernoulli(density) with N(0,1) entries, soc_frac of the variables in SOC
+    blocks of dims U{soc_lo..soc_hi}, the rest nonnegative; rows half
+    equality, half inequality), each drawn from its own child seed so that
+    members can be generated independently (in parallel) at any size."""
+    n = int(batch_sizes(seed, count, n_lo, n_hi)[b])
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(count)[b])
+    m = n // 2
+    rp, ci, v = bernoulli_csr_gaps(rng, m, n, density)
+    dims, tot = [], 0
+    while tot < int(soc_frac * n):
+        k = min(int(rng.integers(soc_lo, soc_hi + 1)), n - tot)
+        dims.append(k)
+        tot += k
+    xt = [NONNEG] + [SOC] * len(dims)
+    xd = [n - tot] + dims
+    if xd[0] == 0:
+        xt, xd = xt[1:], xd[1:]
+    me = m // 2
+    rt = [ZERO, NONNEG] if me and m - me else ([ZERO] if me else [NONNEG])
+    rd = [me, m - me] if me and m - me else [m]
+    return plant(rng, n, m, 0, rp, ci, v, xt, xd, rt, rd, name=f"member{seed}_{b}_n{n}")
+
+
 def large_mixed(seed, n=1_000_000, m=500_000, n_box=None, n_soc_x=None, n_soc_r=None,
                 n_exp_r=None, mean_row_nnz=20):
     """The large single-instance workload (defaults: n=1e6, m=5e5, ~1e7 nnz).

@@ -51,13 +51,15 @@ class Info(ctypes.Structure):
                 ("spmv", _i64), ("pobj", _dbl), ("dobj", _dbl), ("err_p", _dbl), ("err_d", _dbl),
                 ("err_gap", _dbl), ("omega", _dbl), ("eta", _dbl), ("setup_s", _dbl),
                 ("solve_s", _dbl), ("kernel_ms", _dbl * 6), ("kernel_launches", _i64 * 6),
-                ("polish_iter", _i64)]
+                ("polish_iter", _i64), ("done_s", _dbl)]
 
 
 class Trace(ctypes.Structure):
     _fields_ = [("cap", _i64), ("count", _i64), ("attempts", _pi32), ("eta_used", _pd),
                 ("beta", _pd), ("omega", _pd), ("check_code", _pi32), ("check_kkt", _pd),
-                ("n_snap", _i64), ("snap_iter", _pi64), ("snap_x", _pd), ("snap_y", _pd)]
+                ("n_snap", _i64), ("snap_iter", _pi64), ("snap_x", _pd), ("snap_y", _pd),
+                ("replay_count", _i64), ("replay_attempts", _pi32), ("replay_beta", _pd),
+                ("replay_check_code", _pi32)]
 
 
 class PdcsError(RuntimeError):
@@ -69,7 +71,7 @@ _lib = None
 SYMBOLS = ["pdcs_settings_default", "pdcs_problem_create", "pdcs_problem_create_device",
            "pdcs_problem_destroy", "pdcs_solve", "pdcs_scaling", "pdcs_spmv", "pdcs_spmv32",
            "pdcs_set_layout", "pdcs_get_layout", "pdcs_kkt", "pdcs_cones_create", "pdcs_cones_project",
-           "pdcs_cones_destroy", "pdcs_project", "pdcs_batch_create", "pdcs_batch_solve", "pdcs_batch_size",
+           "pdcs_cones_destroy", "pdcs_project", "pdcs_project_fp32", "pdcs_batch_create", "pdcs_batch_solve", "pdcs_batch_size",
            "pdcs_batch_destroy", "pdcs_mlp_create", "pdcs_mlp_num_params", "pdcs_mlp_forward",
            "pdcs_mlp_gradient", "pdcs_mlp_train_step", "pdcs_mlp_get_params", "pdcs_mlp_destroy",
            "pdcs_gemm_bf16", "pdcs_status_string", "pdcs_last_error"]
@@ -108,6 +110,7 @@ def load():
     L.pdcs_cones_destroy.argtypes = [_vp]
     L.pdcs_cones_destroy.restype = None
     L.pdcs_project.argtypes = [_i64, _pi32, _pi64, ctypes.c_int, _vp, _vp, _vp]
+    L.pdcs_project_fp32.argtypes = [_i64, _pi32, _pi64, ctypes.c_int, _vp, _vp, _vp]
     L.pdcs_batch_create.argtypes = [ctypes.POINTER(ProblemDesc), _i64, _vp, ctypes.POINTER(_vp)]
     L.pdcs_batch_solve.argtypes = [_vp, ctypes.POINTER(Settings), _vp, _vp, _vp,
                                    ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(Info)]
@@ -296,9 +299,11 @@ class Problem:
 
     # ------------------------------------------------------------------ solve
     def solve(self, settings: Settings | None = None, x0=None, y0=None, omega0: float = 0.0,
-              log_cap: int = 0, snap_iters=None, x_out=None, y_out=None):
+              log_cap: int = 0, snap_iters=None, x_out=None, y_out=None, replay=None):
         """pdcs_solve.  Returns a dict of the info fields plus x, y (numpy, or the
-        given device tensors x_out/y_out) and, if requested, the decision log."""
+        given device tensors x_out/y_out) and, if requested, the decision log.
+        `replay`: another run's decision log (a dict with "attempts", "beta" and
+        "check_code" arrays) whose decisions this solve takes."""
         L = load()
         s = settings or settings_default()
         on_dev = x_out is not None
@@ -327,6 +332,17 @@ class Problem:
                        logs["check_kkt"].ctypes.data_as(_pd), int(snaps.size),
                        snaps.ctypes.data_as(_pi64), logs["snap_x"].ctypes.data_as(_pd),
                        logs["snap_y"].ctypes.data_as(_pd))
+        if replay is not None:
+            if tr is None:
+                raise ValueError("a replay needs log_cap or snap_iters")
+            ra = np.ascontiguousarray(replay["attempts"], np.int32)
+            rb = np.ascontiguousarray(replay["beta"], np.float64)
+            rc = np.ascontiguousarray(replay["check_code"], np.int32)
+            logs["_replay"] = (ra, rb, rc)   # alive until the call returns
+            tr.replay_count = int(min(ra.size, rb.size, rc.size))
+            tr.replay_attempts = ra.ctypes.data_as(_pi32)
+            tr.replay_beta = rb.ctypes.data_as(_pd)
+            tr.replay_check_code = rc.ctypes.data_as(_pi32)
         _check(L.pdcs_solve(self.handle, ctypes.byref(s),
                             None if x0a is None else ctypes.c_void_p(x0a.ctypes.data),
                             None if y0a is None else ctypes.c_void_p(y0a.ctypes.data),
@@ -340,6 +356,7 @@ class Problem:
             cnt = tr.count
             for k in ("attempts", "eta_used", "beta", "omega", "check_code", "check_kkt"):
                 logs[k] = logs[k][:cnt]
+            logs.pop("_replay", None)
             out["log"] = logs
         return out
 
@@ -381,6 +398,15 @@ def project(types, dims, v_dev, d_dev=None, dual=False, stream=None):
     _check(load().pdcs_project(int(t.size), t.ctypes.data_as(_pi32), k.ctypes.data_as(_pi64),
                                1 if dual else 0, None if d_dev is None else _dptr(d_dev),
                                _dptr(v_dev), _stream(stream)))
+
+
+def project_fp32(types, dims, v_dev, d_dev=None, dual=False, stream=None):
+    """pdcs_project_fp32: the mixed form's FP32 projections, in place."""
+    t = np.ascontiguousarray(types, np.int32)
+    k = np.ascontiguousarray(dims, np.int64)
+    _check(load().pdcs_project_fp32(int(t.size), t.ctypes.data_as(_pi32), k.ctypes.data_as(_pi64),
+                                    1 if dual else 0, None if d_dev is None else _dptr(d_dev),
+                                    _dptr(v_dev), _stream(stream)))
 
 
 class Cones:

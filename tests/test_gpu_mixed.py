@@ -60,13 +60,19 @@ MIXED = [("small_mixed_1", lambda: I.small_mixed(1)),
          ("large_mixed_n20000", lambda: I.large_mixed(7, n=20000, m=10000))]
 
 
+@pytest.mark.parametrize("precision", [1, 2])
 @pytest.mark.parametrize("name,maker", MIXED, ids=[t[0] for t in MIXED])
-def test_mixed_solve_reaches_tolerance(pd, orc, name, maker):
-    """precision = 1 ends OPTIMAL at 1e-6 as measured by the oracle at its
-    answer, and its objective agrees with the FP64 solve and the planted one."""
+def test_mixed_solve_reaches_tolerance(pd, orc, name, maker, precision):
+    """precision 1 (FP32 products) and 2 (FP32 products and projections) end
+    OPTIMAL at 1e-6 as measured by the oracle at their answer, and their
+    objective agrees with the FP64 solve and the planted one.  On the two
+    smaller instances the answer is also compared with the oracle's own 1e-6
+    solve: ||x - x_orc||_inf / ||x_orc||_inf, the objective and max-KKT are
+    printed (a 1e-6 answer is not unique, so these are stated, with loose
+    bounds)."""
     inst = maker()
     prob = pd.Problem(inst)
-    g = prob.solve(pd.settings_default(precision=1))
+    g = prob.solve(pd.settings_default(precision=precision))
     p = prob.solve(pd.settings_default())
     assert g["status"] == 0, g["status"]
     assert g["polish_iter"] != 0
@@ -76,7 +82,46 @@ def test_mixed_solve_reaches_tolerance(pd, orc, name, maker):
     assert g["pobj"] == pytest.approx(p["pobj"], rel=3e-5, abs=3e-5)
     if inst.opt is not None:
         assert g["pobj"] == pytest.approx(inst.opt, rel=3e-5, abs=3e-5)
+    if inst.n <= 2000:
+        o = orc.solve(inst, orc.default_settings())
+        xe = np.abs(g["x"] - o["x"]).max() / max(np.abs(o["x"]).max(), 1e-300)
+        oe = abs(g["pobj"] - o["pobj"]) / max(1.0, abs(o["pobj"]))
+        print(f"{name} precision {precision}: |x - x_orc|/|x_orc| {xe:.2e}, objective {oe:.2e}, "
+              f"max-KKT {max(k['err_p'], k['err_d'], k['err_gap']):.2e}, polish at {g['polish_iter']}",
+              flush=True)
+        assert oe <= 3e-5 and xe <= 5e-2
     prob.close()
+
+
+@pytest.mark.parametrize("dual", [False, True])
+def test_fp32_projection_within_fp32_bound(pd, orc, dual):
+    """pdcs_project_fp32 (the mixed form's FP32 projections) against the
+    oracle's FP64 projection: every block within 2e-5 of its scale
+    max(1, ||v_block||) -- FP32 rounding (2^-24) of the inputs, sums and root,
+    amplified by the conditioning of the scaled cones (scale factors over
+    10^+-1).  Blocks the FP32 path hands to the FP64 routine match to 1e-12."""
+    rng = np.random.default_rng(31 + dual)
+    types, dims = [], []
+    for _ in range(3000):
+        t = int(rng.choice([2, 3, 3, 3, 4, 5]))
+        k = 3 if t in (4, 5) else (int(rng.integers(1, 40)) if t == 2 else
+                                   int(rng.choice([2, 3, 5, 8, 13, 16, 31, 50, 64, 100, 128, 200, 256])))
+        types.append(t), dims.append(k)
+    v = np.concatenate([rng.standard_normal(k) * 10 ** rng.uniform(-1, 1) for k in dims])
+    d = 10 ** rng.uniform(-1.0, 1.0, v.size)
+    ref = orc.proj_blocks(types, dims, v, d, dual=dual)
+    vd = dev(v)
+    pd.project_fp32(types, dims, vd, dev(d), dual=dual)
+    got = vd.cpu().numpy()
+    offs = np.concatenate([[0], np.cumsum(dims)])
+    errs = np.array([np.abs(got[a:b] - ref[a:b]).max() / max(1.0, np.linalg.norm(v[a:b]))
+                     for a, b in zip(offs[:-1], offs[1:])])
+    cone = np.array([t in (3, 4, 5) for t in types])
+    print(f"fp32 projections (dual {dual}): worst {errs.max():.2e}, median over cones "
+          f"{np.median(errs[cone]):.2e}", flush=True)
+    assert np.all(np.isfinite(got))
+    assert errs.max() <= 2e-5, (int(errs.argmax()), errs.max())
+    assert errs[cone].max() > 1e-12        # the FP32 path did run
 
 
 def test_mixed_polish_switch_by_tolerance(pd, orc):

@@ -97,14 +97,14 @@ def test_project_soc_wide_scales(pd, orc, dual):
 
 
 def test_project_unscaled_extreme_exp(pd, orc):
-    """Inputs over 1e-4..1e4 with scales 10^+-2, where d_s/d_r reaches 1e-4 and
+    """Inputs over 1e-4..1e4 with scales 10^+-3, where d_s/d_r reaches 1e-6 and
     the closed form of eq. (sp_rd) would cancel: both sides evaluate v_p as the
     projection of v0 onto the ray w(rho) (Step 1 of the proof of Theorem 3),
     so they agree to rounding level."""
     rng = np.random.default_rng(5)
     nb = 4000
     v = rng.standard_normal(3 * nb) * 10 ** rng.uniform(-4, 4, 3 * nb)
-    d = 10 ** rng.uniform(-2.0, 2.0, 3 * nb)
+    d = 10 ** rng.uniform(-3.0, 3.0, 3 * nb)
     for dual in (False, True):
         ref = orc.proj_blocks([4] * nb, [3] * nb, v, d, dual=dual)
         vd = dev(v)
@@ -241,6 +241,74 @@ def test_trajectory_adaptive_reflection_first_32(pd, orc, name, maker):
     errs = _trajectory(pd, orc, inst, 32)
     say("  worst relative iterate difference", errs.max())
     assert errs.max() <= 1e-10, (int(errs.argmax()) + 1, errs.max())
+
+
+# How far the GPU may drift from the oracle under the default method when both
+# take the oracle's decisions: the oracle-vs-oracle envelope (the same source
+# built with FMA contraction, replaying the same decisions; written by
+# tests/golden/make_replay_envelope.py) times this factor, and never below
+# 1e-10.  The adaptive step makes the iteration map amplify rounding: eta_bar
+# is a ratio of small differences, so two valid FP64 roundings drift apart
+# geometrically even with identical decisions (about 1e-9 by iteration 64 and
+# 1e-3 by iteration 200 on small_mixed_0).
+ENV_FACTOR = 100.0
+
+
+def _envelope(name):
+    from helpers import load_golden
+    w = load_golden("replay_envelope.json")["workloads"][name]
+    return np.array(w["envelope"]), np.array(w["eta_envelope"])
+
+
+@pytest.mark.parametrize("name,maker", TRAJ, ids=[t[0] for t in TRAJ])
+def test_trajectory_200_iterations_default_replay(pd, orc, name, maker):
+    """The default method (adaptive step of Algorithm 1 line 4, adaptive
+    reflection of line 5, restarts and primal weight) over the first 200
+    iterations.  Free run: wherever the GPU's decisions differ from the
+    oracle's, the oracle's deciding quantity was within rounding of its
+    threshold there (its margin is below what two valid FP64 roundings
+    already disagree by at that iteration).  Replay run (the oracle's
+    decisions forced): iterates within max(1e-10, ENV_FACTOR x envelope) at
+    every iteration, identical reflection parameters, step sizes and primal
+    weights within the same bounds."""
+    it = 200
+    inst = maker()
+    env, eta_env = _envelope(name)
+    say("trajectory default", name, inst.n, inst.m, inst.nnz)
+    snaps = np.arange(1, it + 1)
+    o = orc.solve(inst, orc.default_settings(max_iter=it), log_cap=it, snap_iters=snaps)
+    ol = o["log"]
+    prob = pd.Problem(inst)
+    free = prob.solve(pd.settings_default(max_iter=it), log_cap=it, snap_iters=snaps)["log"]
+    g = prob.solve(pd.settings_default(max_iter=it), log_cap=it, snap_iters=snaps, replay=ol)["log"]
+    prob.close()
+    # free run: differing decisions only at ties within rounding
+    k = min(len(free["attempts"]), len(ol["attempts"]))
+    diff = np.flatnonzero((free["attempts"][:k] != ol["attempts"][:k]) |
+                          (free["check_code"][:k] != ol["check_code"][:k]))
+    if diff.size:
+        d = int(diff[0])
+        tie = 1e-12 + ENV_FACTOR * max(eta_env[max(d - 1, 0)], env[max(d - 1, 0)])
+        say("  free run: first decision difference at iteration", d + 1, "oracle margin",
+            ol["margin"][d], "allowed", tie)
+        assert ol["margin"][d] <= tie, (d + 1, ol["margin"][d], tie)
+    # replay run
+    assert len(g["attempts"]) == it
+    assert np.array_equal(g["attempts"], ol["attempts"])
+    assert np.array_equal(g["check_code"], ol["check_code"])
+    assert np.array_equal(g["beta"], ol["beta"])
+    bound = np.maximum(1e-10, ENV_FACTOR * env)
+    errs = np.array([np.linalg.norm(np.concatenate([g["snap_x"][i] - ol["snap_x"][i],
+                                                    g["snap_y"][i] - ol["snap_y"][i]])) /
+                     max(1.0, np.linalg.norm(np.concatenate([ol["snap_x"][i], ol["snap_y"][i]])))
+                     for i in range(it)])
+    ratio = errs / bound
+    say("  replay: worst iterate difference", errs.max(), "at", int(errs.argmax()) + 1,
+        "; first 64:", errs[:64].max(), "; worst ratio to bound", ratio.max())
+    assert np.all(errs <= bound), (int(ratio.argmax()) + 1, errs[ratio.argmax()], bound[ratio.argmax()])
+    eta_bound = np.maximum(1e-10, ENV_FACTOR * eta_env)
+    assert np.all(np.abs(g["eta_used"] / ol["eta_used"] - 1.0) <= eta_bound)
+    assert np.all(np.abs(g["omega"] / ol["omega"] - 1.0) <= np.maximum(1e-10, ENV_FACTOR * env))
 
 
 # ------------------------------------------------------------ end to end
