@@ -344,6 +344,28 @@ pdcs_status pdcs_project(int64_t nblocks, const int32_t *types, const int64_t *d
 pdcs_status pdcs_project_fp32(int64_t nblocks, const int32_t *types, const int64_t *dims, int dual,
                               const double *d_dev, double *v_dev, void *hip_stream);
 
+/* pdcs_project for callers that cannot allocate device memory (code that must
+ * not call hipMalloc, such as tight serving loops or harnesses that forbid
+ * it).  Same arguments, arithmetic and results as pdcs_project, but the tile
+ * plan, per-tile partial sums, barrier state of grid-level SOC blocks and the
+ * rotated blocks' offsets live in a fixed device array of
+ * PDCS_PROJECT_NOALLOC_SCRATCH_BYTES per GPU (held by each GPU the library
+ * runs on until the process ends); no device memory is allocated or freed.
+ * Plans are built on the host (host memory only) and copied in.  Calls on one
+ * GPU share that array and the last call's contents stay in it: calls that
+ * overlap on one GPU (several threads or streams at once) race; the barrier
+ * counters are cleared by a kernel at the start of every call.  The call
+ * waits for its stream.  Errors: as pdcs_project, plus NOT_SUPPORTED when the
+ * cone list needs more scratch than the array holds (the message gives both
+ * sizes).  Per unit: 12 bytes per SOC block plus 72 bytes per tile of up to
+ * 32 blocks, 8 bytes per exponential cone plus 72 per 64 cones, 72 bytes per
+ * 2048 elementwise entries, about 5 KB per SOC block of 8192 entries or more
+ * (when at most 256 such blocks are present), 8 bytes per rotated block;
+ * 1e5 SOC blocks of dim <= 8 thus take about 1.4 MB. */
+#define PDCS_PROJECT_NOALLOC_SCRATCH_BYTES (16u << 20)
+pdcs_status pdcs_project_noalloc(int64_t nblocks, const int32_t *types, const int64_t *dims,
+                                 int dual, const double *d_dev, double *v_dev, void *hip_stream);
+
 /* A projection plan for one product of cones, built once and reused: the
  * dispatch of pdcs_project (the thread-, wavefront- and workgroup-level
  * classes of Section 4) kept on the device.  pdcs_cones_create takes host

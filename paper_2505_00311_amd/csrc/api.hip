@@ -15,6 +15,7 @@
 #include <cstring>
 #include <functional>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <vector>
@@ -2204,6 +2205,106 @@ pdcs_status pdcs_project(int64_t nblocks, const int32_t *types, const int64_t *d
 pdcs_status pdcs_project_fp32(int64_t nblocks, const int32_t *types, const int64_t *dims, int dual,
                               const double *d_dev, double *v_dev, void *hip_stream) {
     return project_impl(nblocks, types, dims, dual, d_dev, v_dev, hip_stream, 1);
+}
+
+}  // extern "C"
+
+// Device scratch of pdcs_project_noalloc: the tile plan, the per-tile partial
+// sums, the grid-level blocks' barrier state and the rotated blocks' offsets,
+// carved per call.  Every GPU holds its own copy; host code reaches it only
+// through the address hipGetSymbolAddress returns on that device.
+static __device__ __align__(256) unsigned char scratch[PDCS_PROJECT_NOALLOC_SCRATCH_BYTES];
+
+static void *scratch_address() {
+    static std::mutex mu;
+    static std::vector<void *> addr;   // per device ordinal, filled once each
+    int dev = 0;
+    PDCS_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)addr.size() <= dev) addr.resize((size_t)dev + 1, nullptr);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        PDCS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        addr[dev] = p;
+    }
+    return addr[dev];
+}
+
+// Bump placement of typed arrays in the scratch, 256-byte aligned.
+struct ScratchCarve {
+    uintptr_t base;
+    size_t used = 0;
+    template <class T>
+    T *take(int64_t n) {
+        T *p = reinterpret_cast<T *>(base + used);
+        used += (sizeof(T) * (size_t)std::max<int64_t>(n, 1) + 255) & ~(size_t)255;
+        return p;
+    }
+};
+
+extern "C" {
+
+pdcs_status pdcs_project_noalloc(int64_t nblocks, const int32_t *types, const int64_t *dims,
+                                 int dual, const double *d_dev, double *v_dev, void *hip_stream) {
+    return guarded([&] {
+        if (nblocks < 0 || (nblocks > 0 && (!types || !dims || !v_dev)))
+            fail(PDCS_ERR_INVALID_ARG, "NULL argument");
+        int64_t len = 0;
+        for (int64_t b = 0; b < nblocks; ++b) len += dims[b];
+        std::vector<int32_t> t;
+        std::vector<int64_t> d;
+        validate_cones(nblocks, types, dims, len, "cones", t, d);
+        const std::vector<int64_t> rot = rsoc_to_soc(t, d, d_dev);
+        const HostPlan H = build_plan(0, 0, t, d);
+        const int64_t ntiles = (int64_t)H.tiles.size(), n_rot = (int64_t)rot.size();
+        // sizes first (the carve only adds offsets to a null base here)
+        ScratchCarve probe{0};
+        probe.take<Tile>(ntiles);
+        probe.take<int64_t>((int64_t)H.soc_off.size());
+        probe.take<int32_t>((int64_t)H.soc_dim.size());
+        probe.take<int64_t>((int64_t)H.exp_off.size());
+        probe.take<unsigned long long>(H.n_grid);
+        probe.take<double>(H.n_grid * 2 * kSocGridMaxParts * kSocGridSlot);
+        probe.take<int>(1);
+        probe.take<double>(ntiles * kPartials);
+        probe.take<int64_t>(n_rot);
+        if (probe.used > (size_t)PDCS_PROJECT_NOALLOC_SCRATCH_BYTES)
+            fail(PDCS_ERR_NOT_SUPPORTED,
+                 "pdcs_project_noalloc: this cone list needs " + std::to_string(probe.used) +
+                     " bytes of device scratch, more than its fixed " +
+                     std::to_string((size_t)PDCS_PROJECT_NOALLOC_SCRATCH_BYTES) +
+                     " bytes; use pdcs_project or pdcs_cones_create");
+        if (ntiles == 0) return;
+        hipStream_t s = (hipStream_t)hip_stream;
+        ScratchCarve c{reinterpret_cast<uintptr_t>(scratch_address())};
+        ConePlan P;
+        P.ntiles = ntiles;
+        P.tiles = c.take<Tile>(ntiles);
+        P.soc_off = c.take<int64_t>((int64_t)H.soc_off.size());
+        P.soc_dim = c.take<int32_t>((int64_t)H.soc_dim.size());
+        P.exp_off = c.take<int64_t>((int64_t)H.exp_off.size());
+        P.n_soc = (int64_t)H.soc_off.size();
+        P.n_exp = (int64_t)H.exp_off.size();
+        P.n_grid = H.n_grid;
+        P.grid_ctr = c.take<unsigned long long>(P.n_grid);
+        P.grid_part = c.take<double>(P.n_grid * 2 * kSocGridMaxParts * kSocGridSlot);
+        P.grid_err = c.take<int>(1);
+        double *part = c.take<double>(ntiles * kPartials);
+        int64_t *rot_dev = c.take<int64_t>(n_rot);
+        h2d(P.tiles, H.tiles.data(), ntiles, s);
+        h2d(P.soc_off, H.soc_off.data(), P.n_soc, s);
+        h2d(P.soc_dim, H.soc_dim.data(), P.n_soc, s);
+        h2d(P.exp_off, H.exp_off.data(), P.n_exp, s);
+        h2d(rot_dev, rot.data(), n_rot, s);
+        // the barrier counters must start at zero; a kernel clears them (the
+        // scratch keeps whatever the last call on this GPU left)
+        clear_grid(P, s);
+        rotate_pairs(v_dev, rot_dev, n_rot, 0, s);
+        pass_project(P, dual != 0, ProjArgs{v_dev, d_dev, 0}, part, s);
+        rotate_pairs(v_dev, rot_dev, n_rot, 0, s);
+        PDCS_HIP(hipStreamSynchronize(s));   // also keeps the host plan alive for the copies
+        check_grid(P, s);
+    });
 }
 
 struct pdcs_cones {

@@ -71,7 +71,7 @@ _lib = None
 SYMBOLS = ["pdcs_settings_default", "pdcs_problem_create", "pdcs_problem_create_device",
            "pdcs_problem_destroy", "pdcs_solve", "pdcs_scaling", "pdcs_spmv", "pdcs_spmv32",
            "pdcs_set_layout", "pdcs_get_layout", "pdcs_kkt", "pdcs_cones_create", "pdcs_cones_project",
-           "pdcs_cones_destroy", "pdcs_project", "pdcs_project_fp32", "pdcs_batch_create", "pdcs_batch_solve", "pdcs_batch_size",
+           "pdcs_cones_destroy", "pdcs_project", "pdcs_project_fp32", "pdcs_project_noalloc", "pdcs_batch_create", "pdcs_batch_solve", "pdcs_batch_size",
            "pdcs_batch_destroy", "pdcs_mlp_create", "pdcs_mlp_num_params", "pdcs_mlp_forward",
            "pdcs_mlp_gradient", "pdcs_mlp_train_step", "pdcs_mlp_get_params", "pdcs_mlp_destroy",
            "pdcs_gemm_bf16", "pdcs_status_string", "pdcs_last_error"]
@@ -111,6 +111,7 @@ def load():
     L.pdcs_cones_destroy.restype = None
     L.pdcs_project.argtypes = [_i64, _pi32, _pi64, ctypes.c_int, _vp, _vp, _vp]
     L.pdcs_project_fp32.argtypes = [_i64, _pi32, _pi64, ctypes.c_int, _vp, _vp, _vp]
+    L.pdcs_project_noalloc.argtypes = [_i64, _pi32, _pi64, ctypes.c_int, _vp, _vp, _vp]
     L.pdcs_batch_create.argtypes = [ctypes.POINTER(ProblemDesc), _i64, _vp, ctypes.POINTER(_vp)]
     L.pdcs_batch_solve.argtypes = [_vp, ctypes.POINTER(Settings), _vp, _vp, _vp,
                                    ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(Info)]
@@ -407,6 +408,16 @@ def project_fp32(types, dims, v_dev, d_dev=None, dual=False, stream=None):
     _check(load().pdcs_project_fp32(int(t.size), t.ctypes.data_as(_pi32), k.ctypes.data_as(_pi64),
                                     1 if dual else 0, None if d_dev is None else _dptr(d_dev),
                                     _dptr(v_dev), _stream(stream)))
+
+
+def project_noalloc(types, dims, v_dev, d_dev=None, dual=False, stream=None):
+    """pdcs_project_noalloc: pdcs_project with its scratch in a fixed device
+    array (no device allocation), in place."""
+    t = np.ascontiguousarray(types, np.int32)
+    k = np.ascontiguousarray(dims, np.int64)
+    _check(load().pdcs_project_noalloc(int(t.size), t.ctypes.data_as(_pi32), k.ctypes.data_as(_pi64),
+                                       1 if dual else 0, None if d_dev is None else _dptr(d_dev),
+                                       _dptr(v_dev), _stream(stream)))
 
 
 class Cones:
