@@ -56,6 +56,7 @@ def iteration_bytes(n, m, nnz):
 
 
 FP32_ONLY = dict(precision=1, polish_tol=0.0, polish_stall=1 << 30)
+FP32_PROJ_ONLY = dict(precision=2, polish_tol=0.0, polish_stall=1 << 30)
 
 
 def kernel_timing(pdcs, prob, iters, **kw):
@@ -299,10 +300,11 @@ def warm_start_form(pdcs, instances, torch, n_assets, n_train, n_test):
     tr = fam.thetas(SEED_FAMILY + 1, n_train)
     te = fam.thetas(SEED_FAMILY + 2, n_test)
     t0 = time.perf_counter()
-    res, _ = W.solve_family(fam, tr)
+    res, _ = W.solve_family(fam, tr, log=log)
     gen_s = time.perf_counter() - t0
     T = W.targets_of(res)
-    net, norm, hist, train_s = W.train(tr, T, hidden=512, epochs=100, batch=256, lr=1e-3)
+    del res
+    net, norm, hist, train_s = W.train(tr, T, hidden=512, epochs=100, batch=256, lr=1e-3, log=log)
     # the output layer's GEMM on the matrix cores: 256 x (n + m + 1) x 512
     th = torch.randn(256, 64, dtype=torch.float32, device="cuda")
     out = torch.empty(256, net.n_out, dtype=torch.float32, device="cuda")
@@ -315,9 +317,9 @@ def warm_start_form(pdcs, instances, torch, n_assets, n_train, n_test):
     b.synchronize()
     fwd_ms = a.elapsed_time(b) / 20
     flops = 2.0 * 256 * (64 * 512 + 512 * 512 + 512 * net.n_out)
-    cold, cold_s = W.solve_family(fam, te)
+    cold, cold_s = W.solve_family(fam, te, log=log)
     starts = W.predict(net, norm, te, fam.n, fam.m)
-    warm, warm_s = W.solve_family(fam, te, starts=starts)
+    warm, warm_s = W.solve_family(fam, te, starts=starts, log=log)
     net.close()
     it_c = float(np.mean([r["iterations"] for r in cold]))
     it_w = float(np.mean([r["iterations"] for r in warm]))
@@ -449,7 +451,7 @@ def logistic_form(pdcs, instances, torch):
            "reference": None if ref is None else {"objective": ref["pobj"], "tol": ref["tol"],
                                                    "iterations": ref["iterations"]}}
     out = {}
-    for name, kw in (("fp64", {}), ("mixed", {"precision": 1})):
+    for name, kw in (("fp64", {}), ("mixed", {"precision": 1}), ("mixed_fp32_projections", {"precision": 2})):
         t0 = time.perf_counter()
         r = prob.solve(pdcs.settings_default(time_limit=120.0, **kw))
         torch.cuda.synchronize()
@@ -460,13 +462,15 @@ def logistic_form(pdcs, instances, torch):
              "kkt_max": max(r["err_p"], r["err_d"], r["err_gap"]), "objective": r["pobj"]}
         if ref is not None:
             e["objective_rel_err_vs_oracle"] = abs(r["pobj"] - ref["pobj"]) / abs(ref["pobj"])
-        if name == "mixed":
+        if name != "fp64":
             e["polish_iter"] = r["polish_iter"]
         out[name] = (e, r)
         rec[name] = e
         log(f"logistic {name}: {e['status']} in {e['solve_s']}s, {e['iterations']} iterations, "
             f"objective error {e.get('objective_rel_err_vs_oracle')}")
     rec["mixed_speedup_time_to_tol"] = round(rec["fp64"]["solve_s"] / max(rec["mixed"]["solve_s"], 1e-9), 3)
+    rec["mixed_fp32_projections_speedup_time_to_tol"] = round(
+        rec["fp64"]["solve_s"] / max(rec["mixed_fp32_projections"]["solve_s"], 1e-9), 3)
     # the 2e5 dual exponential projections alone, on the final dual iterate
     N = inst.meta["samples"]
     y = torch.from_numpy(out["fp64"][1]["y"][N:].copy()).cuda()
@@ -545,7 +549,8 @@ def config4(args):
         log(f"  batch created in {out['create_s']}s")
         del insts
         t0 = time.perf_counter()
-        rb = batch.solve(pdcs.settings_default(precision=1, autotune=1, time_limit=args.c4_time_limit))
+        rb = batch.solve(pdcs.settings_default(precision=1, autotune=1, time_limit=args.c4_time_limit,
+                                                 log_every=30.0))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         batch.close()
@@ -729,6 +734,23 @@ def main():
                     "iter_per_s": round(ips_m, 2), "ms_per_step": round(wall_m / K * 1e3, 3),
                     "speedup_iter_s": round(ips_m / ips, 3),
                     "kernel_us": {k: round(v, 2) for k, v in kus_m.items()}}
+    # precision 2: the FP32 products plus FP32 lane-group SOC and exponential projections
+    sp2 = pdcs.settings_default(max_iter=CHECK * K, **FP32_PROJ_ONLY)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rm2 = prob.solve(sp2)
+    torch.cuda.synchronize()
+    wall_m2 = time.perf_counter() - t0
+    ips_m2 = rm2["iterations"] / rm2["solve_s"]
+    kus_m2, _ = kernel_timing(pdcs, prob, CHECK * K, **FP32_PROJ_ONLY)
+    log(f"mixed form with FP32 projections: {ips_m2:.1f} iter/s; kernels (us): "
+        + ", ".join(f"{k} {v:.1f}" for k, v in kus_m2.items()))
+    out["mixed_fp32_projections"] = {
+        "form": "FP32 products and FP32 lane-group SOC / exponential projections (FP64 case tests "
+                "and fallbacks), FP64 iterates and checks, FP64 polish (settings.precision 2)",
+        "iter_per_s": round(ips_m2, 2), "ms_per_step": round(wall_m2 / K * 1e3, 3),
+        "speedup_iter_s": round(ips_m2 / ips, 3),
+        "kernel_us": {k: round(v, 2) for k, v in kus_m2.items()}}
 
     if not args.no_time_to_tol:
         def to_tol(**kw):
@@ -746,13 +768,14 @@ def main():
                 f"{pdcs.SOLVE_STATUS[rt['status']]}")
             return rt, rec
         rp_, out["time_to_tol"] = to_tol()
-        rmx, rec = to_tol(precision=1)
-        rec["polish_iter"] = rmx["polish_iter"]
         xs = np.abs(rp_["x"]).max()
-        rec["x_diff_vs_fp64_inf_rel"] = float(np.abs(rmx["x"] - rp_["x"]).max() / max(xs, 1e-300))
-        rec["objective_diff_vs_fp64_rel"] = abs(rmx["pobj"] - rp_["pobj"]) / max(1.0, abs(rp_["pobj"]))
-        out["mixed"]["time_to_tol"] = rec
-        out["mixed"]["speedup_time_to_tol"] = round(rp_["solve_s"] / rmx["solve_s"], 3)
+        for key, prec in (("mixed", 1), ("mixed_fp32_projections", 2)):
+            rmx, rec = to_tol(precision=prec)
+            rec["polish_iter"] = rmx["polish_iter"]
+            rec["x_diff_vs_fp64_inf_rel"] = float(np.abs(rmx["x"] - rp_["x"]).max() / max(xs, 1e-300))
+            rec["objective_diff_vs_fp64_rel"] = abs(rmx["pobj"] - rp_["pobj"]) / max(1.0, abs(rp_["pobj"]))
+            out[key]["time_to_tol"] = rec
+            out[key]["speedup_time_to_tol"] = round(rp_["solve_s"] / rmx["solve_s"], 3)
 
     if args.batch_count > 0:
         out["batched"] = batched_form(pdcs, instances, torch, args.batch_count)

@@ -161,6 +161,11 @@ typedef struct {
      * restarts, termination measured at the current iterate; the rescaling
      * still applies.  0: Algorithm 1. */
     int32_t plain_pdhg;
+    /* > 0: at a check, when at least this many seconds have passed since the
+     * last line, print one progress line to stderr (elapsed time, instances
+     * still running, their largest iteration count and worst max-KKT).
+     * 0: silent. */
+    double log_every;
 } pdcs_settings;
 
 /* Kernels of one step attempt, in launch order (indices of pdcs_info.kernel_ms). */

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -99,13 +100,14 @@ static void append_plan(HostPlan &P, int32_t inst, int64_t box0, int64_t n_box, 
             elem.push_back(tile(kind, std::min<int64_t>(kElemPerTile, len - o), start + o));
     };
     push_run(kTileBox, box0, n_box);
-    // SOC size classes: lanes per block 8, 16, 32, 64 (1 entry per lane), then
-    // one wavefront with 2 or 4 entries per lane, then a workgroup per block,
-    // then several workgroups per block (grid level)
+    // SOC size classes (dims up to 8, 16, 32, 64, 128, 256): lane groups of 8,
+    // 16, 16, 16, 32 and 64 lanes with 1, 1, 2, 4, 4 and 4 entries per lane,
+    // so a wavefront holds 8, 4, 4, 4, 2 and 1 blocks; then a workgroup per
+    // block, then several workgroups per block (grid level)
     constexpr int kClasses = 8;
     const int class_kind[kClasses] = {kTileSoc8, kTileSoc16, kTileSoc32, kTileSoc64,
                                       kTileSoc128, kTileSoc256, kTileSocBlock, kTileSocGrid};
-    const int class_per_tile[kClasses] = {32, 16, 8, 4, 4, 4, 1, 1};
+    const int class_per_tile[kClasses] = {32, 16, 16, 16, 8, 4, 1, 1};
     // The grid level pays for its barriers only while the large blocks alone
     // cannot fill the chip: with more than kSocGridMaxBlocks of them (one
     // workgroup each already covers every CU) they stay at the workgroup level.
@@ -230,7 +232,8 @@ struct SlabSource {
 };
 
 // Column slabs: slab k takes the columns [cb[k], cb[k+1]) that hold about
-// nnz k/S .. nnz (k+1)/S entries.  Each slab's arrays hold first the entries
+// nnz k/S .. nnz (k+1)/S entries (after a hot slab of the first columns, when
+// there is one).  Each slab's arrays hold first the entries
 // of its short rows (in row order, CSR order within a row), cut into streamed
 // blocks of at most kStreamNnz entries and kStreamRows rows, then the slab's
 // entries of the long rows (rows of more than long_thr entries), row after
@@ -248,12 +251,22 @@ static void add_slabs(DevMem &mem, SpmvPlan &P, const std::vector<int64_t> &rp,
     const int64_t rows = (int64_t)rp.size() - 1, nnz = rp.back(), cols = (int64_t)cc.size() - 1;
     if (rows >= INT32_MAX || nnz >= INT32_MAX)
         fail(PDCS_ERR_NOT_SUPPORTED, "column-slab plan limited to 2^31 rows and entries");
+    // The hot slab: the first min(cols, kHotCols) columns, when they hold at
+    // least 1/(2 S) of the entries.  Their gathers then come from LDS, and its
+    // blocks spread over every XCD; the S cold slabs share the remaining
+    // entries equally.
+    const int64_t H = S >= 2 ? std::min<int64_t>(cols, kHotCols) : 0;
+    const int hot = H > 0 && 2 * S * cc[H] >= nnz ? 1 : 0;
+    const int S_cold = S;
+    S = S_cold + hot;
     std::vector<int64_t> cb(S + 1, 0);
     cb[S] = cols;
-    for (int k = 1; k < S; ++k) {
-        const int64_t t = nnz * k / S;
+    if (hot) cb[1] = H;
+    const int64_t e0 = hot ? cc[H] : 0;
+    for (int k = 1; k < S_cold; ++k) {
+        const int64_t t = e0 + (nnz - e0) * k / S_cold;
         int64_t c = std::lower_bound(cc.begin(), cc.end(), t) - cc.begin();
-        cb[k] = std::min(cols, std::max(cb[k - 1], c));
+        cb[hot + k] = std::min(cols, std::max(cb[hot + k - 1], c));
     }
     std::vector<int8_t> slab_of(cols);
     for (int k = 0; k < S; ++k)
@@ -279,6 +292,7 @@ static void add_slabs(DevMem &mem, SpmvPlan &P, const std::vector<int64_t> &rp,
         if (lg) ++l;
     }
     P.n_slabs = S;
+    P.hot_cols = hot ? (int)H : 0;
     P.slab_base[0] = 0;
     std::vector<int64_t> long0(S);   // start of slab k's long-row region
     for (int k = 0; k < S; ++k) {
@@ -289,7 +303,7 @@ static void add_slabs(DevMem &mem, SpmvPlan &P, const std::vector<int64_t> &rp,
         long0[k] = P.slab_base[k] + l[rows];
         P.slab_base[k + 1] = long0[k] + nlong;
     }
-    for (int k = S + 1; k <= kMaxSlabs; ++k) P.slab_base[k] = P.slab_base[S];
+    for (int k = S + 1; k <= kMaxSlabs + 1; ++k) P.slab_base[k] = P.slab_base[S];
     const int64_t total = P.slab_base[S];
     // place the entries
     std::vector<int32_t> sci(total), sperm(total), cur(lrp);
@@ -343,13 +357,19 @@ static void add_slabs(DevMem &mem, SpmvPlan &P, const std::vector<int64_t> &rp,
         }
         if (rows > start) close(start, rows);
     }
-    const int g = kXcds / S;
+    // per XCD: the blocks of its cold slab (every g-th of them), then its
+    // share of the hot slab's blocks (every kXcds-th)
+    const int g = kXcds / S_cold;
+    std::vector<std::vector<SlabBlock>> per(kXcds);
+    for (int k = 0; k < S_cold; ++k)
+        for (size_t j = 0; j < lists[hot + k].size(); ++j) per[k * g + j % g].push_back(lists[hot + k][j]);
+    if (hot)
+        for (size_t j = 0; j < lists[0].size(); ++j) per[j % kXcds].push_back(lists[0][j]);
     size_t rounds = 0;
-    for (int k = 0; k < S; ++k) rounds = std::max(rounds, (lists[k].size() + g - 1) / g);
+    for (int x = 0; x < kXcds; ++x) rounds = std::max(rounds, per[x].size());
     std::vector<SlabBlock> blk(rounds * kXcds, SlabBlock{0, 0, 0, 0});
-    for (int k = 0; k < S; ++k)
-        for (size_t j = 0; j < lists[k].size(); ++j)
-            blk[(j / g) * kXcds + k * g + j % g] = lists[k][j];
+    for (int x = 0; x < kXcds; ++x)
+        for (size_t j = 0; j < per[x].size(); ++j) blk[j * kXcds + x] = per[x][j];
     P.n_slab_blocks = (int64_t)blk.size();
     P.slab_rp = mem.alloc<int32_t>(S * R1);
     P.slab_ci = mem.alloc<int32_t>(total);
@@ -1185,7 +1205,7 @@ static void slab_source(pdcs_problem *P, bool transposed, std::vector<int32_t> &
 
 // The layout code of a plan (see pdcs_set_layout).
 static int layout_code(const SpmvPlan &pl) {
-    return pl.n_slabs > 0 ? slab_code(pl.n_slabs) : pl.stream ? -1 : pl.lanes;
+    return pl.n_slabs > 0 ? slab_code(pl.n_slabs - (pl.hot_cols > 0)) : pl.stream ? -1 : pl.lanes;
 }
 
 static bool valid_layout(int code) {
@@ -1617,6 +1637,7 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
     }
     h2d(P->st, hs.data(), B, s);
     const auto t_iter = clk::now();
+    double last_log = 0.0;   // progress lines (settings.log_every)
     const double setup_s = std::chrono::duration<double>(t_iter - t_start).count();
 
     auto active = [&](int64_t b) { return status[b] < 0; };
@@ -1716,16 +1737,21 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
             fail(PDCS_ERR_HIP, "a grid-level SOC projection timed out waiting for its workgroups");
         const double elapsed = std::chrono::duration<double>(clk::now() - t_iter).count();
         bool any_restart = false, switch_ok = mixed;
+        int64_t log_running = 0, log_iter = 0;
+        double log_kkt = 0.0;
         for (int64_t b = 0; b < B; ++b) {
             code[b] = 0;
             if (!active(b)) continue;
             DevState &h = hs[b];
             ++checks[b];
+            ++log_running;
+            log_iter = std::max<int64_t>(log_iter, h.n_iter);
             const Kkt k1 = kkt_from_raw(P, b, raw[b]), k2 = kkt_from_raw(P, b, raw[B + b]);
             int chosen = !plain && k2.avg() < k1.avg() ? 1 : 0;
             last_src[b] = chosen;
             Kkt kc = chosen ? k2 : k1;
             double kcv = kc.avg();
+            log_kkt = std::max(log_kkt, kc.mx());
             const double kav = k_anchor[b].avg();
             int reason = 0, stop = 0;
             if (!(kcv == kcv)) {
@@ -1793,6 +1819,13 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
                 else ++stall[b];
                 if (!(kc.mx() <= S->polish_tol || stall[b] >= S->polish_stall)) switch_ok = false;
             }
+        }
+        if (S->log_every > 0.0 && elapsed - last_log >= S->log_every) {
+            last_log = elapsed;
+            std::fprintf(stderr, "pdcs: %9.2f s  %lld of %lld instance(s) at this check, up to %lld iterations, "
+                                 "worst max-KKT %.3e\n",
+                         elapsed, (long long)log_running, (long long)B, (long long)log_iter, log_kkt);
+            std::fflush(stderr);
         }
         if (any_restart) {
             h2d(P->rcode, code.data(), B, s);
@@ -2024,6 +2057,7 @@ pdcs_status pdcs_settings_default(pdcs_settings *s) {
     s->autotune = 0;
     s->batch_dropout = 0;
     s->plain_pdhg = 0;
+    s->log_every = 0.0;
     return PDCS_OK;
 }
 

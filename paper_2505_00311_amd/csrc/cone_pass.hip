@@ -661,9 +661,9 @@ __global__ __launch_bounds__(kBlock) void cone_pass_kernel(Op op, const Tile *__
         break;
     case kTileSoc8: soc_tile<Op, 8, 1, F32>(op, tl, soc_off, soc_dim, soc_root, acc); break;
     case kTileSoc16: soc_tile<Op, 16, 1, F32>(op, tl, soc_off, soc_dim, soc_root, acc); break;
-    case kTileSoc32: soc_tile<Op, 32, 1, F32>(op, tl, soc_off, soc_dim, soc_root, acc); break;
-    case kTileSoc64: soc_tile<Op, 64, 1, F32>(op, tl, soc_off, soc_dim, soc_root, acc); break;
-    case kTileSoc128: soc_tile<Op, 64, 2, F32>(op, tl, soc_off, soc_dim, soc_root, acc); break;
+    case kTileSoc32: soc_tile<Op, 16, 2, F32>(op, tl, soc_off, soc_dim, soc_root, acc); break;
+    case kTileSoc64: soc_tile<Op, 16, 4, F32>(op, tl, soc_off, soc_dim, soc_root, acc); break;
+    case kTileSoc128: soc_tile<Op, 32, 4, F32>(op, tl, soc_off, soc_dim, soc_root, acc); break;
     case kTileSoc256: soc_tile<Op, 64, 4, F32>(op, tl, soc_off, soc_dim, soc_root, acc); break;
     case kTileSocBlock:
         soc_block(op, soc_off[tl.start], soc_dim[tl.start], acc,

@@ -406,6 +406,16 @@ __device__ __forceinline__ float group_sum_f(float v) {
     return v;
 }
 
+// The FP64 routine as the FP32 one's fallback, kept out of line: inlined at
+// every call site it would raise the FP32 pass kernels' register count for a
+// path that rarely runs.
+template <int LPB, int R>
+__device__ __noinline__ void soc_project_group_fallback(int dim, const double (&v)[R],
+                                                        const double (&d)[R], double (&p)[R],
+                                                        double s_guess, double &s_out) {
+    soc_project_group<LPB, R>(dim, v, d, p, s_guess, s_out);
+}
+
 // soc_project_group in FP32 arithmetic (same cases, bracket and safeguarded
 // Newton search).  The FP64 routine takes over, for the whole group, when a
 // search value leaves the FP32 range or the search does not settle within 60
@@ -435,7 +445,7 @@ __device__ void soc_project_group_f(int dim, const double (&v)[R], const double 
     const float ndi = sqrtf(group_sum_f<LPB>(sndi));
     const float nx2 = group_sum_f<LPB>(snx);
     if (!(isfinite(nd) && isfinite(ndi) && isfinite(nx2) && isfinite(t))) {
-        soc_project_group<LPB, R>(dim, v, d, p, s_guess, s_out);
+        soc_project_group_fallback<LPB, R>(dim, v, d, p, s_guess, s_out);
         return;
     }
     if (t <= 0.0f && nd <= -t) {
@@ -519,7 +529,7 @@ __device__ void soc_project_group_f(int dim, const double (&v)[R], const double 
         eval(s, f, df);
     }
     if (!settled) {
-        soc_project_group<LPB, R>(dim, v, d, p, s_guess, s_out);
+        soc_project_group_fallback<LPB, R>(dim, v, d, p, s_guess, s_out);
         return;
     }
     const float a = 1.0f - t / s;

@@ -42,11 +42,11 @@ enum TileKind : int32_t {
     kTileExp = 6,
     kTileExpDual = 7,
     kTileSoc8 = 8,       // SOC blocks of dim <= 8, 8 lanes each (32 per tile)
-    kTileSoc16 = 9,      // dim <= 16, 16 lanes each
-    kTileSoc32 = 10,     // dim <= 32
-    kTileSoc64 = 11,     // dim <= 64, one wavefront each
-    kTileSoc128 = 12,    // dim <= 128, one wavefront, 2 entries per lane
-    kTileSoc256 = 13,    // dim <= 256, one wavefront, 4 entries per lane
+    kTileSoc16 = 9,      // dim <= 16, 16 lanes each (16 per tile)
+    kTileSoc32 = 10,     // dim <= 32, 16 lanes with 2 entries each (16 per tile)
+    kTileSoc64 = 11,     // dim <= 64, 16 lanes with 4 entries each (16 per tile)
+    kTileSoc128 = 12,    // dim <= 128, 32 lanes with 4 entries each (8 per tile)
+    kTileSoc256 = 13,    // dim <= 256, one wavefront, 4 entries per lane (4 per tile)
     kTileSocGrid = 14    // one part of an SOC block of dim >= kSocGridMin (start = block,
                          // count = part + 256 * parts, pad = grid slot)
 };
@@ -101,6 +101,10 @@ constexpr int64_t kLongChunk = 4096;
 constexpr int kStreamNnz = 2048;   // entries per streamed workgroup (CSR-stream, slabs)
 constexpr int kStreamRows = 1024;  // rows per streamed workgroup
 constexpr int kMaxSlabs = 8;
+// Hot slab: the first columns of x (the internal order puts the columns of
+// highest degree first), at most kHotCols of them (the entries of one
+// streamed block's LDS), staged in LDS by every block of that slab
+constexpr int kHotCols = kStreamNnz;
 constexpr int kXcds = 8;           // MI355X: workgroup i runs on XCD i mod 8
 constexpr double kXcdL2Bytes = 4.0 * 1024 * 1024;   // L2 of one XCD
 // One workgroup of the column-slab kernel: rows [r0, r1) of slab `slab`, whose
@@ -129,9 +133,10 @@ struct SpmvPlan {
     // the matrix's sv/sv32, taken from entry slab_perm of the plain CSR); its
     // workgroups run on the XCDs given to it, so each XCD gathers from one
     // slab of x, and the slab sums of a row are added in slab order.
-    int n_slabs = 0;
+    int n_slabs = 0;                   // slabs in all, the hot slab included
+    int hot_cols = 0;                  // > 0: slab 0 is the hot slab, columns [0, hot_cols)
     int64_t n_slab_blocks = 0;
-    int64_t slab_base[kMaxSlabs + 1] = {};
+    int64_t slab_base[kMaxSlabs + 2] = {};
     int32_t *slab_rp = nullptr;        // [n_slabs (rows+1)] row pointers into the slab arrays
     int32_t *slab_ci = nullptr;        // [nnz - long-row entries]
     int32_t *slab_perm = nullptr;      // [same]

@@ -16,6 +16,14 @@ static unsigned grid_for(int64_t n, int block = kBlock) {
     return (unsigned)(g < 1 ? 1 : g);
 }
 
+// Grid of the grid-stride kernels over a matrix's entries: a batch may hold
+// more entries than one launch has work-items (2^32), so these kernels loop.
+constexpr int64_t kStrideBlocks = (int64_t)1 << 20;
+static unsigned grid_stride(int64_t n) {
+    const int64_t g = (n + kBlock - 1) / kBlock;
+    return (unsigned)(g < 1 ? 1 : g < kStrideBlocks ? g : kStrideBlocks);
+}
+
 // ------------------------------------------------------------- transpose
 __global__ void iota_kernel(int32_t *p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -256,13 +264,16 @@ void reduce_absmax(const double *a, int64_t n, double *out, hipStream_t s) { red
 void reduce_sumsq(const double *a, int64_t n, double *out, hipStream_t s) { reduce<0>(a, n, out, s); }
 
 __global__ void check_finite_kernel(const double *a, int64_t n, int *flag) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && !isfinite(a[i])) atomicOr(flag, 1);
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step)
+        bad |= !isfinite(a[i]);
+    if (bad) atomicOr(flag, 1);
 }
 
 void check_finite(const double *a, int64_t n, int *flag, hipStream_t s) {
     if (n == 0) return;
-    hipLaunchKernelGGL(check_finite_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, a, n, flag);
+    hipLaunchKernelGGL(check_finite_kernel, dim3(grid_stride(n)), dim3(kBlock), 0, s, a, n, flag);
     PDCS_HIP(hipGetLastError());
 }
 
@@ -278,12 +289,13 @@ void fill(double *p, int64_t n, double v, hipStream_t s) {
 }
 
 __global__ void to_float_kernel(const double *in, float *out, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = (float)in[i];
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step)
+        out[i] = (float)in[i];
 }
 void to_float(const double *in, float *out, int64_t n, hipStream_t s) {
     if (n == 0) return;
-    hipLaunchKernelGGL(to_float_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, in, out, n);
+    hipLaunchKernelGGL(to_float_kernel, dim3(grid_stride(n)), dim3(kBlock), 0, s, in, out, n);
     PDCS_HIP(hipGetLastError());
 }
 
@@ -400,8 +412,9 @@ void scatter(double *out, const double *in, const int32_t *idx, int64_t n, int64
 }
 // ci[k] = pos[ci[k]]: column indices renumbered
 __global__ void relabel_kernel(int32_t *ci, int64_t nnz, const int32_t *pos) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < nnz) ci[k] = pos[ci[k]];
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += step)
+        ci[k] = pos[ci[k]];
 }
 // r = 1 / fl(sqrt 2), the constant the host side of the map uses, so both
 // sides round the same way
@@ -423,7 +436,7 @@ void rotate_pairs(double *v, const int64_t *offs, int64_t count, int64_t base, h
 
 void relabel(int32_t *ci, int64_t nnz, const int32_t *pos, hipStream_t s) {
     if (nnz == 0) return;
-    hipLaunchKernelGGL(relabel_kernel, dim3(grid_for(nnz)), dim3(kBlock), 0, s, ci, nnz, pos);
+    hipLaunchKernelGGL(relabel_kernel, dim3(grid_stride(nnz)), dim3(kBlock), 0, s, ci, nnz, pos);
     PDCS_HIP(hipGetLastError());
 }
 

@@ -17,7 +17,11 @@
 // XCD's L2 on almost every entry once x outgrows it.  The plan cuts the
 // columns into S slabs of equal entry counts; workgroup i runs on XCD i mod 8
 // and the plan orders the workgroups so that each XCD takes the blocks of one
-// slab only, whose slice of x (|x|/S) then stays in that XCD's L2.  Each
+// slab only, whose slice of x (|x|/S) then stays in that XCD's L2.  When the
+// first (hottest) columns hold a large share of the entries they form a hot
+// slab of their own, whose few columns every block stages in LDS and whose
+// blocks go to every XCD; a narrow hot slab cut like the others would leave
+// its XCDs idle while the others gather from L2.  Each
 // workgroup streams a row range of its slab like the CSR-stream kernel and
 // writes the slab's row sums; a second kernel adds a row's S slab sums in slab
 // order (a fixed order, so results repeat bit for bit from run to run).
@@ -65,10 +69,10 @@ __device__ __forceinline__ double chunk_sum(int64_t b, int64_t e, const int32_t 
         int32_t cc[U];
         T w[U], xv[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+        for (int u = 0; u < U; ++u) {   // streamed once: kept out of the way of x in L2
             const int64_t k = min(k0 + (int64_t)u * kBlock, e - 1);
-            cc[u] = ci[k];
-            w[u] = v[k];
+            cc[u] = __builtin_nontemporal_load(&ci[k]);
+            w[u] = __builtin_nontemporal_load(&v[k]);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) xv[u] = x[cc[u]];
@@ -139,7 +143,7 @@ template <class T, class RP>
 __device__ __forceinline__ void stream_block(int nrows, const RP *__restrict__ rp, RP k0, int cnt,
                                              const int32_t *__restrict__ ci,
                                              const T *__restrict__ v, const T *__restrict__ x,
-                                             double *__restrict__ out) {
+                                             double *__restrict__ out, int lds_cols = 0) {
     __shared__ double prod[kStreamNnz];
     __shared__ int32_t seg[kStreamRows + 1];
     constexpr int U = kStreamNnz / kBlock;
@@ -153,13 +157,21 @@ __device__ __forceinline__ void stream_block(int nrows, const RP *__restrict__ r
         int32_t c[U];
         T w[U], xv[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+        for (int u = 0; u < U; ++u) {   // streamed once: kept out of the way of x in L2
             const int i = min(t + u * kBlock, cnt - 1);
-            c[u] = ci[i];
-            w[u] = v[i];
+            c[u] = __builtin_nontemporal_load(&ci[i]);
+            w[u] = __builtin_nontemporal_load(&v[i]);
         }
+        if (lds_cols > 0) {   // a hot slab: its columns x[0, lds_cols) are staged in LDS first
+            for (int j = t; j < lds_cols; j += kBlock) prod[j] = (double)x[j];
+            __syncthreads();
 #pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+            for (int u = 0; u < U; ++u) xv[u] = (T)prod[c[u]];
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (t + u * kBlock < cnt) prod[t + u * kBlock] = (double)w[u] * (double)xv[u];
@@ -257,7 +269,8 @@ __global__ __launch_bounds__(kBlock) void spmv_slab_kernel(int64_t rows,
     const int cnt = d.cs & 0xffff, slab = d.cs >> 16;
     const int32_t *__restrict__ lrp = p.slab_rp + (int64_t)slab * (rows + 1) + d.r0;
     stream_block<T, int32_t>(d.r1 - d.r0, lrp, d.k0, cnt, p.slab_ci + d.k0, sv + d.k0, x,
-                             p.slab_part + (int64_t)slab * rows + d.r0);
+                             p.slab_part + (int64_t)slab * rows + d.r0,
+                             slab == 0 ? p.hot_cols : 0);
 }
 
 // y[i] = sum over slabs s = 0..S-1 of slab_part[s][i], in slab order.  Long
@@ -321,11 +334,14 @@ static void spmv_impl(const Csr &A, const SpmvPlan &p, const T *v, const T *sv, 
             return;
         }
         const dim3 g((unsigned)((A.rows + kBlock - 1) / kBlock));
-        switch (p.n_slabs) {
+        switch (p.n_slabs) {   // 1, 2, 4 or 8 slabs, plus one when there is a hot slab
         case 1: hipLaunchKernelGGL(spmv_slab_sum<1>, g, dim3(kBlock), 0, s, A.rows, p.slab_part, y, skip); break;
         case 2: hipLaunchKernelGGL(spmv_slab_sum<2>, g, dim3(kBlock), 0, s, A.rows, p.slab_part, y, skip); break;
+        case 3: hipLaunchKernelGGL(spmv_slab_sum<3>, g, dim3(kBlock), 0, s, A.rows, p.slab_part, y, skip); break;
         case 4: hipLaunchKernelGGL(spmv_slab_sum<4>, g, dim3(kBlock), 0, s, A.rows, p.slab_part, y, skip); break;
-        default: hipLaunchKernelGGL(spmv_slab_sum<8>, g, dim3(kBlock), 0, s, A.rows, p.slab_part, y, skip); break;
+        case 5: hipLaunchKernelGGL(spmv_slab_sum<5>, g, dim3(kBlock), 0, s, A.rows, p.slab_part, y, skip); break;
+        case 8: hipLaunchKernelGGL(spmv_slab_sum<8>, g, dim3(kBlock), 0, s, A.rows, p.slab_part, y, skip); break;
+        default: hipLaunchKernelGGL(spmv_slab_sum<9>, g, dim3(kBlock), 0, s, A.rows, p.slab_part, y, skip); break;
         }
     } else if (p.stream) {
         const int64_t blocks = dec.nblk + p.n_sblocks + p.n_chunks;

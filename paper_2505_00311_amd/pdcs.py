@@ -41,7 +41,7 @@ class Settings(ctypes.Structure):
                 ("step_mode", _i32), ("step_fixed", _dbl), ("power_iters", _i32),
                 ("use_graph", _i32), ("time_kernels", _i32), ("precision", _i32),
                 ("polish_tol", _dbl), ("polish_stall", _i32), ("autotune", _i32),
-                ("batch_dropout", _i32), ("plain_pdhg", _i32)]
+                ("batch_dropout", _i32), ("plain_pdhg", _i32), ("log_every", _dbl)]
 
 KERNELS = ("primal", "spmv_g", "dual", "decide", "spmv_gt", "halpern")
 

@@ -17,10 +17,11 @@ import numpy as np
 from . import pdcs as P
 
 
-def solve_family(family, thetas, settings=None, batch_size=256, starts=None):
+def solve_family(family, thetas, settings=None, batch_size=256, starts=None, log=None):
     """Batched solves of family.instance(theta) for every row of `thetas`.
-    starts: optional list of (x0, y0, omega0) per theta.  Returns the list of
-    result dicts (info fields plus x, y) and the summed batch solve times."""
+    starts: optional list of (x0, y0, omega0) per theta; log: optional
+    callable given a progress line per batch.  Returns the list of result
+    dicts (info fields plus x, y) and the summed batch solve times."""
     out, secs = [], 0.0
     for i in range(0, len(thetas), batch_size):
         chunk = thetas[i:i + batch_size]
@@ -34,6 +35,9 @@ def solve_family(family, thetas, settings=None, batch_size=256, starts=None):
         secs += res[0]["solve_s"] if res else 0.0
         batch.close()
         out += res
+        if log:
+            log(f"solved {len(out)} of {len(thetas)} (batch of {len(chunk)}: "
+                f"{res[0]['solve_s'] if res else 0.0:.2f}s)")
     return out, secs
 
 
