@@ -527,12 +527,17 @@ def config4(args):
     idx = list(range(count)) if args.c4_mode == "batch" else list(range(0, count, args.c4_stride))
     t0 = time.perf_counter()
     workers = max(1, min(host_threads(), 16))
+    insts = []
     with mp.get_context("fork").Pool(workers) as pool:
-        insts = pool.map(_member, [(seed, b, count) for b in idx], chunksize=1)
+        for inst in pool.imap(_member, [(seed, b, count) for b in idx], chunksize=1):
+            insts.append(inst)
+            if len(insts) % 64 == 0:
+                log(f"  generated {len(insts)} of {len(idx)} instances ({time.perf_counter() - t0:.0f}s)")
     gen_s = time.perf_counter() - t0
     nnz = sum(i.nnz for i in insts)
     log(f"config 4 ({args.c4_mode}): {len(insts)} instances, sum nnz {nnz}, generated in {gen_s:.1f}s "
         f"on {workers} processes")
+    os.environ.setdefault("PDCS_LOG", "1")   # stage lines of the batch set-up (minutes)
     import torch
     from paper_2505_00311_amd import pdcs
     torch.cuda.set_device(0)

@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -804,8 +805,19 @@ static void transpose_blocks(pdcs_problem *P, hipStream_t s) {
     transpose_csr(P->G, P->Gt, blk.data(), (int64_t)blk.size(), s);
 }
 
+// Stage lines of problem and batch creation on stderr when the environment
+// sets PDCS_LOG (setting up a batch of billions of entries takes minutes).
+static void create_log(const char *stage, std::chrono::steady_clock::time_point t0) {
+    static const bool on = std::getenv("PDCS_LOG") != nullptr;
+    if (!on) return;
+    std::fprintf(stderr, "pdcs: create: %s at %.1f s\n", stage,
+                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+    std::fflush(stderr);
+}
+
 static pdcs_problem *create_impl(const pdcs_problem_desc *Ds, int64_t count, void *stream,
                                  bool on_device) {
+    const auto t_create = std::chrono::steady_clock::now();
     if (!Ds) fail(PDCS_ERR_INVALID_ARG, "desc is NULL");
     if (count < 1) fail(PDCS_ERR_INVALID_ARG, "no problem in the batch");
     if (on_device && count != 1) fail(PDCS_ERR_NOT_SUPPORTED, "a batch takes host arrays");
@@ -940,7 +952,9 @@ static pdcs_problem *create_impl(const pdcs_problem_desc *Ds, int64_t count, voi
         h2d(P->ry_dev, P->ry.data(), (int64_t)P->ry.size(), s);
         PDCS_HIP(hipStreamSynchronize(s));
     }
+    create_log("uploaded", t_create);
     transpose_blocks(P.get(), s);
+    create_log("transposed", t_create);
     std::vector<int64_t> hrp(m + 1), hrpt(n + 1);
     d2h(hrp.data(), P->G.rp, m + 1, s);
     d2h(hrpt.data(), P->Gt.rp, n + 1, s);
@@ -1060,6 +1074,7 @@ static pdcs_problem *create_impl(const pdcs_problem_desc *Ds, int64_t count, voi
         h2d(P->xpos, pos.data(), n, s);
         h2d(P->l, il.data(), n, s);
         h2d(P->u, iu.data(), n, s);
+        create_log("column order chosen", t_create);
         relabel(P->G.ci, nnz, P->xpos, s);
         double *cu = M.alloc<double>(n);
         copy_vec(P->c, cu, n, s);
@@ -1068,8 +1083,10 @@ static pdcs_problem *create_impl(const pdcs_problem_desc *Ds, int64_t count, voi
         d2h(hrpt.data(), P->Gt.rp, n + 1, s);
         PDCS_HIP(hipStreamSynchronize(s));   // the host vectors die at the end of this block
     }
+    create_log("transposed in the column order", t_create);
     set_plan(P.get(), 0, 0);
     set_plan(P.get(), 1, 0);
+    create_log("product plans built", t_create);
     HostPlan hx, hy;
     for (int64_t b = 0; b < B; ++b) {
         const InstDims &I = P->inst[b];
@@ -1123,6 +1140,7 @@ static pdcs_problem *create_impl(const pdcs_problem_desc *Ds, int64_t count, voi
     for (int64_t b = 0; b < B; ++b)
         if (P->inst[b].m == 0) P->hinf[b] = 0.0;
     sync_slab_values(P.get());
+    create_log("ready", t_create);
     return P.release();
 }
 
