@@ -89,6 +89,26 @@ def counter_traffic(kernel):
     return rec["kernels"][kernel]["bytes_per_launch"]
 
 
+def exp_fp64_flops():
+    """FP64 operations per launch of the 2e5-cone dual exponential projection of
+    the logistic workload, from the committed rocprofv3 counter summary (FMA
+    counted as two), or None when it is missing or the projection code changed
+    since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "exp_projection_logistic.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"<!-- fp64: (\{.*?\}) -->", open(path).read())
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    src = os.path.join(ROOT, rec["source"])
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["sha256"]:
+        return None
+    return rec["fp64_flop_per_launch"]
+
+
 def layout_name(code):
     if code <= -10:
         return f"{-10 - code} column slabs (spmv_slab_kernel)"
@@ -491,6 +511,12 @@ def logistic_form(pdcs, instances, torch):
     rec["dual_exp_projection"] = {"cones": 2 * N, "ms": round(t_exp, 4),
                                   "cones_per_s": round(2 * N / (t_exp * 1e-3), 1),
                                   "input": "the FP64 solve's dual iterate on the exponential rows"}
+    fl = exp_fp64_flops()
+    if fl is not None:   # ALU-bound work: FP64 operations against the vector peak
+        rec["dual_exp_projection"].update({
+            "fp64_flop_per_launch": fl, "fp64_tflops": round(fl / (t_exp * 1e-3) / 1e12, 2),
+            "fp64_vector_peak_tflops": 78.6,
+            "timing_note": "HIP events around one launch (includes the launch gap)"})
     prob.close()
     return rec
 

@@ -1309,6 +1309,9 @@ static void autotune_spmv(pdcs_problem *P) {
         for (int c : cands) {
             DevMem tmp;
             const SpmvPlan plan = build_spmv_plan(tmp, rp, s, c, src);
+            // a plan whose launch would exceed 2^31 work-items (a workgroup per
+            // long-row chunk when most rows count as long) is not a candidate
+            if (spmv_blocks(A, plan) + 64 > kMaxLaunchBlocks) continue;
             slab_values(A, plan, s);
             spmv(A, plan, in, out, SpmvSkip{}, s);   // warm
             PDCS_HIP(hipEventRecord(a, s));
@@ -2507,9 +2510,12 @@ int64_t pdcs_mlp_num_params(const pdcs_mlp *m) { return m ? m->np : 0; }
 static void mlp_forward(pdcs_mlp *M, const float *theta, int64_t B, float *out) {
     hipStream_t s = M->stream;
     const int64_t in = M->in, hid = M->hid, O = M->out;
-    to_bf16(theta, M->xb, B * in, s);
-    gemm_bf16(0, 1, B, hid, in, M->xb, in, M->p16 + M->off[0], in, M->p + M->off[1], 1, M->h1, M->h1b, hid, s);
-    gemm_bf16(0, 1, B, hid, hid, M->h1b, hid, M->p16 + M->off[2], hid, M->p + M->off[3], 1, M->h2, M->h2b, hid, s);
+    if (!mlp_hidden(B, in, hid, theta, M->p16 + M->off[0], M->p + M->off[1], M->p16 + M->off[2],
+                    M->p + M->off[3], M->xb, M->h1, M->h1b, M->h2, M->h2b, s)) {
+        to_bf16(theta, M->xb, B * in, s);
+        gemm_bf16(0, 1, B, hid, in, M->xb, in, M->p16 + M->off[0], in, M->p + M->off[1], 1, M->h1, M->h1b, hid, s);
+        gemm_bf16(0, 1, B, hid, hid, M->h1b, hid, M->p16 + M->off[2], hid, M->p + M->off[3], 1, M->h2, M->h2b, hid, s);
+    }
     gemm_bf16(0, 1, B, O, hid, M->h2b, hid, M->p16 + M->off[4], hid, M->p + M->off[5], 0, out, nullptr, O, s);
 }
 

@@ -227,6 +227,18 @@ __device__ __forceinline__ void exp_dual_project(double r0, double s0, double t0
 }
 
 // ------------------------------------------------------- second-order cone
+// 1/x for finite nonzero x: the hardware estimate refined by two Newton steps
+// for the reciprocal (e = 1 - x r, r += r e), each of which squares the
+// estimate's relative error; four dependent FMAs after the estimate, against
+// the longer sequence of an IEEE division.
+__device__ __forceinline__ double nr_recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 // A lane's partner value under a DPP pattern (CTRL), for a double.
 template <int CTRL>
 __device__ __forceinline__ double dpp_partner(double v) {
@@ -329,11 +341,12 @@ __device__ void soc_project_group(int dim, const double (&v)[R], const double (&
     if (s_guess > lo && s_guess < hi) s = s_guess;        // root of an earlier, nearby input
     double dxold = hi - lo, dx = dxold;
     auto eval = [&](double ss, double &f, double &df) {
-        const double a = 1.0 - t / ss;
+        const double is = nr_recip(ss);
+        const double a = 1.0 - t * is;
         double g1 = 0.0, g2 = 0.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const double iq = 1.0 / (h2[r] + a);
+            const double iq = nr_recip(h2[r] + a);
             const double u = w[r] * iq * iq;
             g1 += u;
             g2 += u * iq;
@@ -341,7 +354,7 @@ __device__ void soc_project_group(int dim, const double (&v)[R], const double (&
         g1 = group_sum<LPB>(g1);
         g2 = group_sum<LPB>(g2);
         f = g1 - ss * ss;
-        df = -2.0 * (t / (ss * ss)) * g2 - 2.0 * ss;
+        df = -2.0 * (t * is * is) * g2 - 2.0 * ss;
     };
     double f, df;
     eval(s, f, df);
@@ -359,7 +372,7 @@ __device__ void soc_project_group(int dim, const double (&v)[R], const double (&
             dx = 0.5 * (xneg - xpos);
             s = xpos + dx;
         } else {
-            dx = f / df;
+            dx = f * nr_recip(df);
             s -= dx;
         }
         if (fabs(dx) <= 4.0 * kEps * s) break;

@@ -273,6 +273,11 @@ void spmv32_head(const Csr &A, const SpmvPlan &plan, const float *x, double *y,
                  const SpmvSkip &skip, hipStream_t s, const DecideArgs &dec = DecideArgs{});
 void to_float(const double *in, float *out, int64_t n, hipStream_t s);
 int choose_lanes(double avg_row_nnz);
+// Workgroups of the first kernel of a product under `plan` (the step
+// decision's workgroups not counted).  A launch holds at most
+// kMaxLaunchBlocks workgroups of kBlock work-items (2^31 work-items).
+int64_t spmv_blocks(const Csr &A, const SpmvPlan &plan);
+constexpr int64_t kMaxLaunchBlocks = (((int64_t)1 << 31) - 1) / kBlock - 64;
 
 // setup.hip
 // One diagonal block of a block-diagonal CSR matrix (an instance of a batch).
@@ -404,6 +409,12 @@ void gemm_bf16(int ta, int tb, int64_t M, int64_t N, int64_t K, const uint16_t *
                const uint16_t *b, int64_t ldb, const float *bias, int relu, float *c32,
                uint16_t *c16, int64_t ldc, hipStream_t s);
 void to_bf16(const float *in, uint16_t *out, int64_t n, hipStream_t s);
+// Both hidden layers of the network in one launch (theta FP32 in; theta's BF16
+// copy, h1 and h2 in FP32 and BF16 out); false (nothing launched) for shapes
+// it does not cover.
+bool mlp_hidden(int64_t B, int64_t in, int64_t hid, const float *theta, const uint16_t *w1,
+                const float *b1, const uint16_t *w2, const float *b2, uint16_t *xb, float *h1,
+                uint16_t *h1b, float *h2, uint16_t *h2b, hipStream_t s);
 void mse_grad(const float *out, const float *target, int64_t n, int64_t cols, int64_t ld16,
               float inv, float *d32, uint16_t *d16, double *part, hipStream_t s);
 void transpose_bf16(const uint16_t *in, int64_t rows, int64_t cols, int64_t ldi, uint16_t *out,

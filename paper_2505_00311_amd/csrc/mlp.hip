@@ -260,6 +260,109 @@ void gemm_bf16(int ta, int tb, int64_t M, int64_t N, int64_t K, const uint16_t *
     PDCS_HIP(hipGetLastError());
 }
 
+// ------------------------------------------------ fused hidden layers
+// The network's two hidden layers for a block of 32 rows (samples) in one
+// launch: h1 = relu(W1 theta + b1) for all hid units of those rows (theta
+// rounded to BF16 on the way in, h1 kept in LDS as BF16), then h2 = relu(W2 h1
+// + b2) for 128 of the hid units, one 32 x 32 block of the matrix cores per
+// wavefront.  Workgroup (x, y) takes rows 32 y .. and units 128 x ..; the
+// workgroups with x = 0 also write theta's BF16 copy and h1 (FP32 and BF16)
+// for the backward pass.  The weights (B operands) are read straight from
+// global memory with the lane layout of gemm_bf16_kernel; the products
+// accumulate over k in ascending steps of 16 as in that kernel, so the
+// results are the same bits as the three separate launches.
+constexpr int kHidRows = 32, kHidMaxIn = 256, kHidMaxHid = 1024;
+__global__ __launch_bounds__(256) void mlp_hidden_kernel(int64_t B, int in, int hid,
+                                                         const float *__restrict__ theta,
+                                                         const uint16_t *__restrict__ w1,
+                                                         const float *__restrict__ b1,
+                                                         const uint16_t *__restrict__ w2,
+                                                         const float *__restrict__ b2,
+                                                         uint16_t *__restrict__ xb,
+                                                         float *__restrict__ h1, uint16_t *__restrict__ h1b,
+                                                         float *__restrict__ h2, uint16_t *__restrict__ h2b) {
+    __shared__ __attribute__((aligned(16))) uint16_t ts[kHidRows][kHidMaxIn + 8];
+    __shared__ __attribute__((aligned(16))) uint16_t hs[kHidRows][kHidMaxHid + 8];
+    const int t = threadIdx.x, lane = t % 64, w = t / 64;
+    const int half = lane / 32, idx = lane % 32;
+    const int64_t r0 = (int64_t)blockIdx.y * kHidRows;
+    const bool first = blockIdx.x == 0;
+    for (int e = t; e < kHidRows * in; e += 256) {   // theta rows in BF16
+        const int r = e / in, k = e % in;
+        const uint16_t v = r0 + r < B ? f32_to_bf16(theta[(r0 + r) * in + k]) : 0;
+        ts[r][k] = v;
+        if (first && r0 + r < B) xb[(r0 + r) * in + k] = v;
+    }
+    __syncthreads();
+    // layer 1: every 32-unit block of h1, block jb on wavefront jb mod 4
+    for (int jb = w; jb * 32 < hid; jb += 4) {
+        f32x16 acc = {};
+        const uint16_t *wr = w1 + (int64_t)(jb * 32 + idx) * in + 8 * half;
+        for (int kk = 0; kk < in; kk += 16) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&ts[idx][kk + 8 * half]);
+            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(wr + kk);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        }
+        const int col = jb * 32 + idx;
+        const float bn = b1[col];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = 8 * (r / 4) + 4 * half + (r % 4);
+            float v = acc[r] + bn;
+            if (v < 0.0f) v = 0.0f;
+            const uint16_t v16 = f32_to_bf16(v);
+            hs[row][col] = v16;
+            if (first && r0 + row < B) {
+                h1[(r0 + row) * hid + col] = v;
+                h1b[(r0 + row) * hid + col] = v16;
+            }
+        }
+    }
+    __syncthreads();
+    // layer 2: units [128 x + 32 w, +32) of h2, eight k-steps of weights in flight
+    const int cb = blockIdx.x * 4 + w;
+    if (cb * 32 >= hid) return;
+    f32x16 acc = {};
+    const uint16_t *wr = w2 + (int64_t)(cb * 32 + idx) * hid + 8 * half;
+    for (int k0 = 0; k0 < hid; k0 += 128) {
+        bf16x8 bv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            bv[u] = k0 + 16 * u < hid ? *reinterpret_cast<const bf16x8 *>(wr + k0 + 16 * u) : bf16x8{};
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (k0 + 16 * u >= hid) break;
+            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&hs[idx][k0 + 16 * u + 8 * half]);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv[u], acc, 0, 0, 0);
+        }
+    }
+    const int col = cb * 32 + idx;
+    const float bn = b2[col];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int row = 8 * (r / 4) + 4 * half + (r % 4);
+        if (r0 + row >= B) continue;
+        float v = acc[r] + bn;
+        if (v < 0.0f) v = 0.0f;
+        h2[(r0 + row) * hid + col] = v;
+        h2b[(r0 + row) * hid + col] = f32_to_bf16(v);
+    }
+}
+
+bool mlp_hidden(int64_t B, int64_t in, int64_t hid, const float *theta, const uint16_t *w1,
+                const float *b1, const uint16_t *w2, const float *b2, uint16_t *xb, float *h1,
+                uint16_t *h1b, float *h2, uint16_t *h2b, hipStream_t s) {
+    // shapes the fused kernel covers: whole 16-wide k-steps, 128-unit blocks of
+    // h2, the LDS tiles' sizes, and 16-byte aligned weight rows
+    if (B < 1 || in % 16 || in > kHidMaxIn || hid % 128 || hid > kHidMaxHid) return false;
+    if ((uintptr_t)w1 % 16 || (uintptr_t)w2 % 16) return false;
+    const dim3 grid((unsigned)(hid / 128), (unsigned)((B + kHidRows - 1) / kHidRows));
+    hipLaunchKernelGGL(mlp_hidden_kernel, grid, dim3(256), 0, s, B, (int)in, (int)hid, theta, w1, b1,
+                       w2, b2, xb, h1, h1b, h2, h2b);
+    PDCS_HIP(hipGetLastError());
+    return true;
+}
+
 // ------------------------------------------------------------- elementwise
 __global__ void to_bf16_kernel(const float *in, uint16_t *out, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;

@@ -231,6 +231,13 @@ int choose_lanes(double avg) {
     return L;
 }
 
+int64_t spmv_blocks(const Csr &A, const SpmvPlan &p) {
+    if (A.rows == 0) return 0;
+    if (p.n_slabs > 0) return p.n_slab_blocks;
+    if (p.stream) return p.n_sblocks + p.n_chunks;
+    return (A.rows * p.lanes + kBlock - 1) / kBlock + p.n_chunks;
+}
+
 template <int L, class T>
 static void launch_rows(const Csr &A, const SpmvPlan &p, const T *v, const T *x, double *y,
                         const SpmvSkip &skip, const DecideArgs &dec, hipStream_t s) {
@@ -316,6 +323,9 @@ static void spmv_impl(const Csr &A, const SpmvPlan &p, const T *v, const T *sv, 
                       const DecideArgs &dec_in = DecideArgs{}) {
     DecideArgs dec = dec_in;
     dec.nblk = dec.st ? (dec.B + kXcds - 1) / kXcds * kXcds : 0;
+    if (spmv_blocks(A, p) + dec.nblk > kMaxLaunchBlocks)
+        throw_hip(hipErrorInvalidConfiguration, "product plan needs more workgroups than one launch holds",
+                  __FILE__, __LINE__);
     if (A.rows == 0) {   // no product: the decision still runs
         if (dec.nblk > 0)
             hipLaunchKernelGGL((spmv_stream_kernel<T>), dim3((unsigned)dec.nblk), dim3(kBlock), 0, s,

@@ -104,3 +104,38 @@ def test_training_fits_a_teacher(pd):
     ref = OM.forward(net.params(), theta.astype(np.float32), n_in, hid, n_out, quantize=True)["o"]
     assert np.abs(out.cpu().numpy() - ref).max() <= 1e-3 * max(1.0, np.abs(ref).max())
     net.close()
+
+
+@pytest.mark.parametrize("n_in,hid,B", [(64, 256, 40), (16, 128, 1), (32, 512, 96)])
+def test_fused_hidden_layers_equal_separate_gemms(pd, n_in, hid, B):
+    """The forward pass runs both hidden layers in one launch when the shapes
+    allow it; it must give the same bits as the three separate GEMM launches
+    (BF16 theta, layer 1 with bias and ReLU, layer 2, output layer), which the
+    GEMM test above holds to the oracle."""
+    rng = np.random.default_rng(n_in + hid + B)
+    n_out = 72
+    sizes = [hid * n_in, hid, hid * hid, hid, n_out * hid, n_out]
+    p = np.concatenate([rng.standard_normal(k) * 0.2 for k in sizes]).astype(np.float32)
+    net = pd.MLP(n_in, hid, n_out, p, max_batch=128)
+    theta = rng.standard_normal((B, n_in)).astype(np.float32)
+    out = torch.empty((B, n_out), dtype=torch.float32, device="cuda")
+    net.forward(torch.from_numpy(theta).cuda(), out)
+    offs = np.cumsum([0] + sizes)
+    part = [p[offs[i]:offs[i + 1]] for i in range(6)]
+    w1, b1, w2, b2, w3, b3 = (part[0], part[1], part[2], part[3], part[4], part[5])
+    dev32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    xb = bits_dev(OM.bf16(theta.astype(np.float64)))
+    h1 = torch.empty((B, hid), dtype=torch.float32, device="cuda")
+    h1b = torch.empty((B, hid), dtype=torch.int16, device="cuda")
+    pd.gemm_bf16(xb, bits_dev(OM.bf16(w1.astype(np.float64))), B, hid, n_in, ta=0, tb=1,
+                 bias_dev=dev32(b1), relu=True, c32_dev=h1, c16_dev=h1b)
+    h2 = torch.empty((B, hid), dtype=torch.float32, device="cuda")
+    h2b = torch.empty((B, hid), dtype=torch.int16, device="cuda")
+    pd.gemm_bf16(h1b, bits_dev(OM.bf16(w2.astype(np.float64))), B, hid, hid, ta=0, tb=1,
+                 bias_dev=dev32(b2), relu=True, c32_dev=h2, c16_dev=h2b)
+    ref = torch.empty((B, n_out), dtype=torch.float32, device="cuda")
+    pd.gemm_bf16(h2b, bits_dev(OM.bf16(w3.astype(np.float64))), B, n_out, hid, ta=0, tb=1,
+                 bias_dev=dev32(b3), relu=False, c32_dev=ref)
+    torch.cuda.synchronize()
+    net.close()
+    assert np.array_equal(out.cpu().numpy(), ref.cpu().numpy())
