@@ -265,10 +265,8 @@ def projection_sweeps(pdcs, torch, total=1_200_000_000, soc_counts=None, exp_cou
     onto a growing number of exponential cones.  Each point: median of 5 HIP-
     event-timed projections on a reused plan, each from a fresh copy of the
     same input; bytes = one read and one write of the vector."""
-    # below 100 cones (dimensions above 1.2e7) each cone is one workgroup's
-    # serial work for seconds: the grid-wide class that would serve it is not
-    # built, so the default sweep starts at 100
-    soc_counts = soc_counts or [100, 1000, 10_000, 100_000, 1_000_000, 10_000_000]
+    # 1 and 10 cones (dimensions 1.2e9 and 1.2e8): grid-level blocks of 512 parts
+    soc_counts = soc_counts or [1, 10, 100, 1000, 10_000, 100_000, 1_000_000, 10_000_000]
     exp_counts = exp_counts or [10 ** k for k in range(2, 8)]
 
     def timed(types, dims):
@@ -593,7 +591,9 @@ def config4(args):
                     "optimal": sum(r["status"] == 0 for r in rb),
                     "sgm10_s": round(sgm(done), 3),
                     "iterations_median": int(np.median(its)), "iterations_max": int(max(its)),
-                    "finish_s_quantiles": [round(float(q), 2) for q in np.quantile(done, [0.1, 0.5, 0.9, 1.0])]})
+                    "finish_s_quantiles": [round(float(q), 2) for q in np.quantile(done, [0.1, 0.5, 0.9, 1.0])],
+                    "finish_s": [round(float(t), 3) for t in done], "status": [int(r["status"]) for r in rb],
+                    "iterations": [int(i) for i in its]})
     else:
         times, its, ok = [], [], 0
         for k, inst in zip(idx, insts):
@@ -640,7 +640,7 @@ def main():
                     help="assets of the warm-start family (0: skip the warm-start measurement)")
     ap.add_argument("--family-train", type=int, default=2048)
     ap.add_argument("--family-test", type=int, default=256)
-    ap.add_argument("--batch-count", type=int, default=32,
+    ap.add_argument("--batch-count", type=int, default=128,
                     help="instances of the batched-form measurement (0: skip it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (the reference kernel "

@@ -78,17 +78,32 @@ __device__ __forceinline__ double exp_hs_value(const ExpPt &c, double rho) {
 __device__ double exp_root(const ExpPt &c, double xneg, double xpos, double start) {
     double rho = (start >= fmin(xneg, xpos) && start <= fmax(xneg, xpos)) ? start : 0.5 * (xneg + xpos);
     double dxold = fabs(xpos - xneg), dx = dxold;
+    bool vneg = false, vpos = false;   // an evaluation here has confirmed the end's sign
     double f, df;
     exp_hs(c, rho, f, df);
     for (int it = 0; it < 200; ++it) {
         if (f == 0.0) return rho;
         if (f < 0.0)
-            xneg = rho;
+            xneg = rho, vneg = true;
         else
-            xpos = rho;
+            xpos = rho, vpos = true;
         const bool finite = isfinite(f) && isfinite(df) && df != 0.0;
         const bool out = !finite || ((rho - xpos) * df - f) * ((rho - xneg) * df - f) > 0.0;
         const bool slow = !finite || fabs(2.0 * f) > fabs(dxold * df);
+        if (out && finite) {
+            // Newton aims past an end that no evaluation here has confirmed
+            // (an end of the case-4 interval): when h has the wrong sign there,
+            // the root is that end to rounding, which bisection would reach
+            // one bit per step
+            const double tgt = rho - f / df;
+            if (!vpos && (tgt - xpos) * (xpos - xneg) >= 0.0) {
+                vpos = true;
+                if (!(exp_hs_value(c, xpos) > 0.0)) return xpos;
+            } else if (!vneg && (tgt - xneg) * (xneg - xpos) >= 0.0) {
+                vneg = true;
+                if (!(exp_hs_value(c, xneg) < 0.0)) return xneg;
+            }
+        }
         dxold = dx;
         if (out || slow) {
             dx = 0.5 * (xpos - xneg);
