@@ -332,7 +332,10 @@ pdcs_status pdcs_kkt(pdcs_problem *p, const double *x_dev, const double *y_dev, 
  * SOC, Theorem 3 for EXP, the Appendix A.2 remark for EXP_DUAL; RSOC as
  * T P_SOC(T v), D = I only).  types and dims are host arrays; d_dev (device,
  * nullable = identity) is the diagonal of D.  dual != 0 projects onto the
- * product of the dual cones instead.
+ * product of the dual cones instead.  With d_dev null, an SOC block outside
+ * the cone and its polar takes the closed form of the identity case,
+ * s = (t + ||x||)/2 (the root of Theorem 1's equation when D = I), instead
+ * of the root search.
  * Errors: INVALID_ARG, DIMENSION, HIP (also when a grid-level block timed out
  * waiting for its workgroups); NOT_SUPPORTED for RSOC with d_dev. */
 pdcs_status pdcs_project(int64_t nblocks, const int32_t *types, const int64_t *dims, int dual,
@@ -364,7 +367,7 @@ pdcs_status pdcs_project_fp32(int64_t nblocks, const int32_t *types, const int64
  * cone list needs more scratch than the array holds (the message gives both
  * sizes).  Per unit: 12 bytes per SOC block plus 72 bytes per tile of up to
  * 32 blocks, 8 bytes per exponential cone plus 72 per 64 cones, 72 bytes per
- * 2048 elementwise entries, about 5 KB per SOC block of 8192 entries or more
+ * 2048 elementwise entries, about 40 KB per SOC block of 8192 entries or more
  * (when at most 256 such blocks are present), 8 bytes per rotated block;
  * 1e5 SOC blocks of dim <= 8 thus take about 1.4 MB. */
 #define PDCS_PROJECT_NOALLOC_SCRATCH_BYTES (16u << 20)

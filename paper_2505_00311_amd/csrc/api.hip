@@ -151,11 +151,17 @@ static void append_plan(HostPlan &P, int32_t inst, int64_t box0, int64_t n_box, 
         for (auto &p : soc[c]) P.soc_off.push_back(p.first), P.soc_dim.push_back((int32_t)p.second);
         const int64_t cnt = (int64_t)soc[c].size();
         if (class_kind[c] == kTileSocGrid) {
+            // parts per block: one per kSocGridChunk entries, capped so that
+            // all blocks together take about kSocGridTargetParts workgroups
+            // (a block waits at each barrier for its slowest part, and parts
+            // beyond what the chip keeps resident only queue behind it)
+            const int64_t cap = std::max<int64_t>(
+                kSocGridMinCap, std::min<int64_t>(kSocGridMaxParts, kSocGridTargetParts / std::max<int64_t>(cnt, 1)));
             for (int64_t i = 0; i < cnt; ++i) {
                 const int64_t d = soc[c][i].second;
-                const int G = (int)std::min<int64_t>(kSocGridMaxParts, (d + kSocGridChunk - 1) / kSocGridChunk);
+                const int G = (int)std::min<int64_t>(cap, (d + kSocGridChunk - 1) / kSocGridChunk);
                 for (int p = 0; p < G; ++p)
-                    P.tiles.push_back(Tile{kTileSocGrid, p + 256 * G, first + i, inst, (int32_t)P.n_grid});
+                    P.tiles.push_back(Tile{kTileSocGrid, p + kSocGridPartCode * G, first + i, inst, (int32_t)P.n_grid});
                 ++P.n_grid;
             }
             continue;

@@ -120,9 +120,15 @@ struct Ld {
 // kWarm: the op runs once per step attempt on slowly changing inputs, so the
 // roots of the SOC and exponential cases are kept per block between launches
 // and start the next root search.
+// kUnit: D = I is known when the kernel is built (scale(j) is the constant 1),
+// and the SOC blocks take the closed form of that case.
+// kInPlace: load(j) returns scratch()[j] unchanged, so the workgroup SOC path
+// reads its input where it lies instead of copying it to the scratch first.
 
 struct OpPrimal {  // x^ = Proj_X(x - tau (c~ - G~^T y)), acc.s0 += (x^ - x)^2
     static constexpr bool kWarm = true;
+    static constexpr bool kUnit = false;
+    static constexpr bool kInPlace = false;
     PrimalArgs a;
     double tau;
     const DevState *st;
@@ -163,6 +169,8 @@ struct OpPrimal {  // x^ = Proj_X(x - tau (c~ - G~^T y)), acc.s0 += (x^ - x)^2
 
 struct OpDual {  // y^ = Proj_Y(y + sigma (h~ - 2 G~x^ + G~x)), acc: |dy|^2, <dy, G~dx>
     static constexpr bool kWarm = true;
+    static constexpr bool kUnit = false;
+    static constexpr bool kInPlace = false;
     DualArgs a;
     double sigma;
     const DevState *st;
@@ -212,6 +220,8 @@ struct OpDual {  // y^ = Proj_Y(y + sigma (h~ - 2 G~x^ + G~x)), acc: |dy|^2, <dy
 
 struct OpCand {  // dst = Proj(src / div), div = 1 or the sum of step weights
     static constexpr bool kWarm = false;
+    static constexpr bool kUnit = false;
+    static constexpr bool kInPlace = false;
     static constexpr bool kCarry = false;
     CandArgs a;
     double div;
@@ -229,6 +239,8 @@ struct OpCand {  // dst = Proj(src / div), div = 1 or the sum of step weights
 // rows of eq. (PDCS_terminate_tolerance): r = G x - h (unscaled), P(r) onto K_d^*
 struct OpKktRows {
     static constexpr bool kWarm = false;
+    static constexpr bool kUnit = false;
+    static constexpr bool kInPlace = false;
     static constexpr bool kCarry = false;
     KktRowsArgs a;
     __device__ void begin(int) {}
@@ -253,6 +265,8 @@ struct OpKktRows {
 // of eq. (defn_Lambda1), cone entries against K_p^*
 struct OpKktCols {
     static constexpr bool kWarm = false;
+    static constexpr bool kUnit = false;
+    static constexpr bool kInPlace = false;
     static constexpr bool kCarry = false;
     KktColsArgs a;
     __device__ void begin(int) {}
@@ -285,6 +299,8 @@ struct OpKktCols {
 
 struct OpProject {
     static constexpr bool kWarm = false;
+    static constexpr bool kUnit = false;
+    static constexpr bool kInPlace = true;
     static constexpr bool kCarry = false;
     ProjArgs a;
     __device__ void begin(int) {}
@@ -296,6 +312,12 @@ struct OpProject {
     __device__ void store(int64_t j, double, double p, Acc &) const { a.v[j] = p; }
     __device__ void store_box(int64_t j, double v, double p, Acc &acc) const { store(j, v, p, acc); }
     __device__ double *scratch() const { return a.v; }
+};
+
+// A projection call without scaling vector (d == nullptr).
+struct OpProjectUnit : OpProject {
+    static constexpr bool kUnit = true;
+    __device__ double scale(int64_t) const { return 1.0; }
 };
 
 template <class Op>
@@ -314,6 +336,49 @@ __device__ __forceinline__ void store_ld(const Op &op, int64_t j, const Ld &l, d
 }
 
 // ------------------------------------------------- workgroup-per-SOC block
+// D = I: the equation of the root-finding case of Theorem 1 becomes
+// ||x|| = 2s - t, so s = (t + ||x||)/2 and x is scaled by s/||x||.  One
+// reduction (||x||^2 over entries [lo, hi) of the block) and one store pass;
+// blocks inside the cone are left as they are.  Every part has read t before
+// part 0 stores the new t: the reduction's barrier lies between the two.
+template <class Op, class Red>
+__device__ void soc_block_range_unit(Op &op, int64_t off, int lo, int hi, Acc &acc, Red &red) {
+    static_assert(Op::kInPlace, "the closed form reads its input in place");
+    // A thread takes its entries U at a time (kBlock apart) and issues the U
+    // loads, predicated on the range, before it uses any of them, so that
+    // enough bytes are in flight per workgroup.  When the range fits in one
+    // such batch (at most U kBlock entries), the store pass reuses the values
+    // the norm pass loaded instead of reading them again.
+    constexpr int U = 8;
+    const int tid = threadIdx.x;
+    const bool one = hi - lo <= U * kBlock;
+    const double t = op.load(off);
+    double sq[1] = {0.0};
+    double x[U];
+    for (int64_t e = lo + tid; e < hi; e += U * kBlock) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = e + u * kBlock < hi ? op.load(off + e + u * kBlock) : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) sq[0] += e + u * kBlock == 0 ? 0.0 : x[u] * x[u];
+    }
+    red.sum(sq);
+    const double nx = sqrt(sq[0]);
+    if (nx <= t) return;                                  // case 2: inside
+    const bool polar = t <= 0.0 && nx <= -t;              // case 1: polar -> 0
+    const double s = polar ? 0.0 : 0.5 * (t + nx), c = polar ? 0.0 : s / nx;
+    for (int64_t e = lo + tid; e < hi; e += U * kBlock) {
+        if (!one) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) x[u] = e + u * kBlock < hi ? op.load(off + e + u * kBlock) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t eu = e + u * kBlock;
+            if (eu < hi) op.store(off + eu, x[u], eu == 0 ? s : x[u] * c, acc);
+        }
+    }
+}
+
 // The workgroup projects entries [lo, hi) of the block at `off` (the whole
 // block for the workgroup class, one part for the grid class); every sum over
 // the block goes through red.sum, which returns the block total to every
@@ -323,10 +388,16 @@ __device__ __forceinline__ void store_ld(const Op &op, int64_t j, const Ld &l, d
 template <class Op, class Red>
 __device__ void soc_block_range(Op &op, int64_t off, int dim, int lo, int hi, Acc &acc,
                                 double *root, Red &red) {
+    if constexpr (Op::kUnit) {
+        soc_block_range_unit(op, off, lo, hi, acc, red);
+        return;
+    }
     double *buf = op.scratch();
     const int tid = threadIdx.x;
-    for (int e = lo + tid; e < hi; e += kBlock) buf[off + e] = op.load(off + e);
-    __syncthreads();
+    if constexpr (!Op::kInPlace) {
+        for (int e = lo + tid; e < hi; e += kBlock) buf[off + e] = op.load(off + e);
+        __syncthreads();
+    }
     const double t = lo == 0 ? buf[off] : op.load(off);
     const double d0 = op.scale(off);
     const int e0 = (lo == 0 ? 1 : lo) + tid;
@@ -521,7 +592,6 @@ struct GridRed {
     template <int K>
     __device__ void sum(double (&v)[K]) {
         static_assert(K <= kSocGridSlot, "a reduction round holds kSocGridSlot values per part");
-        __shared__ double sh[kSocGridMaxParts * kSocGridSlot];
         block_sum_all<K>(v);
         double *buf = g.part + ((int64_t)slot * 2 + (round & 1)) * (kSocGridMaxParts * kSocGridSlot);
         if (threadIdx.x == 0) {
@@ -531,16 +601,15 @@ struct GridRed {
                                    __HIP_MEMORY_SCOPE_AGENT);
         }
         if (ok) ok = grid_barrier(g.ctr + slot, parts, g.err);
-        for (int i = threadIdx.x; i < parts * kSocGridSlot; i += kBlock)
-            sh[i] = __hip_atomic_load(buf + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
+        // thread t adds the slots of parts t, t + kBlock, ... in order, then the
+        // workgroup sums those in a fixed order: every part forms the same bits
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            double s = 0.0;
-            for (int q = 0; q < parts; ++q) s += sh[q * kSocGridSlot + k];
-            v[k] = s;
-        }
-        __syncthreads();
+        for (int k = 0; k < K; ++k) v[k] = 0.0;
+        for (int q = threadIdx.x; q < parts; q += kBlock)
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                v[k] += __hip_atomic_load(buf + q * kSocGridSlot + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        block_sum_all<K>(v);
         ++round;
     }
 };
@@ -549,7 +618,7 @@ template <class Op>
 __device__ void soc_grid_part(Op &op, const Tile &tl, const int64_t *__restrict__ soc_off,
                               const int32_t *__restrict__ soc_dim, double *soc_root,
                               const GridSync &gs, Acc &acc) {
-    const int part = tl.count % 256, parts = tl.count / 256;
+    const int part = tl.count % kSocGridPartCode, parts = tl.count / kSocGridPartCode;
     const int64_t b = tl.start;
     const int dim = soc_dim[b];
     const int chunk = (dim + parts - 1) / parts;
@@ -588,7 +657,9 @@ __device__ __forceinline__ void soc_tile(Op &op, const Tile &tl, const int64_t *
         d[r] = on ? d[r] : 1.0;
     }
     double s_new;
-    if constexpr (F32)
+    if constexpr (Op::kUnit)
+        soc_project_group_unit<LPB, R>(dim, v, p, s_new);
+    else if constexpr (F32)
         soc_project_group_f<LPB, R>(dim, v, d, p, guess, s_new);
     else
         soc_project_group<LPB, R>(dim, v, d, p, guess, s_new);
@@ -749,10 +820,18 @@ void pass_kkt_cols(const ConePlan &p, const KktColsArgs &a, double *partials, hi
 }
 void pass_project(const ConePlan &p, bool dual, const ProjArgs &a, double *partials,
                   hipStream_t s) {
-    if (dual)
+    if (!a.d) {
+        OpProjectUnit op;
+        op.a = a;
+        if (dual)
+            launch<OpProjectUnit, true>(p, op, partials, s);
+        else
+            launch<OpProjectUnit, false>(p, op, partials, s);
+    } else if (dual) {
         launch<OpProject, true>(p, OpProject{a}, partials, s);
-    else
+    } else {
         launch<OpProject, false>(p, OpProject{a}, partials, s);
+    }
 }
 
 }  // namespace pdcs

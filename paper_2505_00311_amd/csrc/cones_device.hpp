@@ -292,6 +292,36 @@ __device__ __forceinline__ double group_sum(double v) {
     return v;
 }
 
+// soc_project_group below with D = I: the root of the last case of Theorem 1
+// is s = (t + ||x||)/2 in closed form, and x is scaled by s/||x||.
+template <int LPB, int R>
+__device__ void soc_project_group_unit(int dim, const double (&v)[R], double (&p)[R],
+                                       double &s_out) {
+    s_out = __builtin_nan("");
+    const int lane = threadIdx.x % kWave;
+    const int g = lane % LPB;
+    const double t = __shfl(v[0], lane - g, kWave);
+    double snx = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = g + LPB * r;
+        const double x = e >= 1 && e < dim ? v[r] : 0.0;
+        snx += x * x;
+    }
+    const double nx = sqrt(group_sum<LPB>(snx));
+    if (nx <= t) {                                        // case 2: inside
+#pragma unroll
+        for (int r = 0; r < R; ++r) p[r] = v[r];
+        return;
+    }
+    const bool polar = t <= 0.0 && nx <= -t;              // case 1: polar -> 0
+    const double s = polar ? 0.0 : 0.5 * (t + nx), c = polar ? 0.0 : s / nx;
+#pragma unroll
+    for (int r = 0; r < R; ++r) p[r] = v[r] * c;
+    if (g == 0) p[0] = s;
+    if (!polar) s_out = s;
+}
+
 // One block per aligned group of LPB lanes; lane g of the group holds entries
 // g + LPB r, r < R; entry 0 (t) is in the group's first lane.  Inactive slots
 // carry v = 0, d = 1.  Several blocks share a wavefront when LPB < 64, so small

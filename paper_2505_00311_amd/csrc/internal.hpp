@@ -24,7 +24,10 @@ constexpr int kPartials = 6;         // per-tile partial slots: 3 sums, 3 maxima
 // workgroups (one per kSocGridChunk entries, at most kSocGridMaxParts)
 constexpr int kSocGridMin = 8192;
 constexpr int kSocGridChunk = 4096;
-constexpr int kSocGridMaxParts = 64;
+constexpr int kSocGridMaxParts = 512;   // at most the workgroups one launch keeps resident
+constexpr int kSocGridTargetParts = 1536;  // parts of all grid-level blocks of a cone list
+constexpr int kSocGridMinCap = 4;        // the part cap when many such blocks share it
+constexpr int kSocGridPartCode = 1024;  // a grid tile's count: part + kSocGridPartCode * parts
 constexpr int kSocGridMaxBlocks = 256;   // more large blocks than this: one workgroup each
 constexpr int kSocGridSlot = 5;          // values per part in one reduction round
 
@@ -48,7 +51,7 @@ enum TileKind : int32_t {
     kTileSoc128 = 12,    // dim <= 128, 32 lanes with 4 entries each (8 per tile)
     kTileSoc256 = 13,    // dim <= 256, one wavefront, 4 entries per lane (4 per tile)
     kTileSocGrid = 14    // one part of an SOC block of dim >= kSocGridMin (start = block,
-                         // count = part + 256 * parts, pad = grid slot)
+                         // count = part + kSocGridPartCode * parts, pad = grid slot)
 };
 
 struct Tile {
