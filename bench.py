@@ -595,14 +595,16 @@ def config4(args):
         log(f"  batch created in {out['create_s']}s")
         del insts
         t0 = time.perf_counter()
-        rb = batch.solve(pdcs.settings_default(precision=1, autotune=1, time_limit=args.c4_time_limit,
+        rb = batch.solve(pdcs.settings_default(precision=args.c4_precision, autotune=1, batch_dropout=args.c4_dropout,
+                                                 time_limit=args.c4_time_limit,
                                                  log_every=30.0))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         batch.close()
         done = [r["done_s"] if r["status"] == 0 else args.c4_time_limit for r in rb]
         its = [r["iterations"] for r in rb]
-        out.update({"form": "batched, FP32 products + FP64 checks and polish, autotuned layouts",
+        out.update({"form": ("batched, FP32 products + FP64 checks and polish, autotuned layouts" if args.c4_precision
+                             else "batched, plain FP64, autotuned layouts"),
                     "wall_s": round(wall, 2), "solve_s": round(rb[0]["solve_s"], 2),
                     "setup_s": round(rb[0]["setup_s"], 2),
                     "optimal": sum(r["status"] == 0 for r in rb),
@@ -666,6 +668,11 @@ def main():
                     help="only the batched configuration at its size (512 instances, ~4.3e9 "
                          "nonzeros; many minutes), printing its own JSON line")
     ap.add_argument("--c4-mode", choices=["batch", "single"], default="batch")
+    ap.add_argument("--c4-dropout", type=int, default=2,
+                    help="settings.batch_dropout of the batched solve (2: hand stragglers over when the "
+                         "batch-wide launches cost 4x their own work)")
+    ap.add_argument("--c4-precision", type=int, default=1,
+                    help="settings.precision of the batched solve: 0 plain FP64, 1 FP32 products")
     ap.add_argument("--c4-count", type=int, default=512)
     ap.add_argument("--c4-stride", type=int, default=16)
     ap.add_argument("--c4-time-limit", type=float, default=300.0)

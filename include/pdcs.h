@@ -139,8 +139,9 @@ typedef struct {
      * FP64 products and projections for good (the polish phase) once the
      * chosen candidate's max(err_p, err_d, err_gap) <= polish_tol, or after
      * polish_stall checks in a row without a new best; the kept products
-     * G~x, G~^T y and those of the anchor are then recomputed in FP64.
-     * precision 0 is plain FP64. */
+     * G~x, G~^T y and those of the anchor are then recomputed in FP64.  A
+     * batch switches as a whole, as soon as any of its running instances
+     * meets that rule.  precision 0 is plain FP64. */
     int32_t precision;
     double polish_tol;
     int32_t polish_stall;
@@ -151,9 +152,14 @@ typedef struct {
     int32_t autotune;
     /* Batches: 1 hands the instances still running to problems of their own
      * (restarted at their chosen candidate with their primal weight) once they
-     * hold at most 1/8 of the batch's nonzeros (not in the paper).  Default 0:
-     * the restart at the hand-over can cost a straggler more iterations than
-     * the batch-wide launches cost it. */
+     * hold at most 1/8 of the batch's nonzeros (not in the paper).  2 does so
+     * only when, in addition, a step attempt over the batch has come to cost
+     * more than 4 times what the running instances' own attempts would (their
+     * share of the nonzeros times the cost per attempt at the first check, at
+     * least 25 us each), measured between checks: the launches then mostly
+     * dispatch workgroups of finished instances.  Default 0: the restart at
+     * the hand-over can cost a straggler more iterations than the batch-wide
+     * launches cost it. */
     int32_t batch_dropout;
     /* 1: the baseline PDHG the paper compares PDCS with (its appendix on PDHG
      * versus PDCS): step step_fixed / ||G~||_2 on both sides (omega = 1 unless
@@ -366,7 +372,7 @@ pdcs_status pdcs_project_fp32(int64_t nblocks, const int32_t *types, const int64
  * waits for its stream.  Errors: as pdcs_project, plus NOT_SUPPORTED when the
  * cone list needs more scratch than the array holds (the message gives both
  * sizes).  Per unit: 12 bytes per SOC block plus 72 bytes per tile of up to
- * 32 blocks, 8 bytes per exponential cone plus 72 per 64 cones, 72 bytes per
+ * 32 blocks, 8 bytes per exponential cone plus 72 per tile of 64 to 256 cones, 72 bytes per
  * 2048 elementwise entries, about 40 KB per SOC block of 8192 entries or more
  * (when at most 256 such blocks are present), 8 bytes per rotated block;
  * 1e5 SOC blocks of dim <= 8 thus take about 1.4 MB. */

@@ -172,10 +172,18 @@ static void append_plan(HostPlan &P, int32_t inst, int64_t box0, int64_t n_box, 
     const int64_t e0 = (int64_t)P.exp_off.size();
     for (auto o : ep) P.exp_off.push_back(o);
     for (auto o : ed) P.exp_off.push_back(o);
-    for (int64_t i = 0; i < (int64_t)ep.size(); i += kExpPerTile)
-        P.tiles.push_back(tile(kTileExp, std::min<int64_t>(kExpPerTile, ep.size() - i), e0 + i));
-    for (int64_t i = 0; i < (int64_t)ed.size(); i += kExpPerTile)
-        P.tiles.push_back(tile(kTileExpDual, std::min<int64_t>(kExpPerTile, ed.size() - i),
+    // a tile of 64 cones keeps one of its four wavefronts busy: with many
+    // cones, wider tiles keep more root searches in flight per CU
+    auto exp_per_tile = [](int64_t cnt) {
+        for (int per : {4 * kExpPerTile, 2 * kExpPerTile})
+            if (cnt >= (int64_t)per * kExpMinTiles) return (int64_t)per;
+        return (int64_t)kExpPerTile;
+    };
+    const int64_t pe = exp_per_tile((int64_t)ep.size()), pd = exp_per_tile((int64_t)ed.size());
+    for (int64_t i = 0; i < (int64_t)ep.size(); i += pe)
+        P.tiles.push_back(tile(kTileExp, std::min<int64_t>(pe, ep.size() - i), e0 + i));
+    for (int64_t i = 0; i < (int64_t)ed.size(); i += pd)
+        P.tiles.push_back(tile(kTileExpDual, std::min<int64_t>(pd, ed.size() - i),
                                e0 + (int64_t)ep.size() + i));
     for (auto &t : elem) P.tiles.push_back(t);
     P.inst_tiles.push_back((int64_t)P.tiles.size());
@@ -589,6 +597,8 @@ struct pdcs_mlp {
 };
 
 constexpr int kGraphBatch = 64;   // step attempts per captured graph
+// the least a step attempt of one instance costs on its own (five launches)
+constexpr double kAloneAttemptS = 25e-6;
 
 static void validate_cones(int64_t nblk, const int32_t *t, const int64_t *d, int64_t expect,
                            const char *what, std::vector<int32_t> &ot, std::vector<int64_t> &od) {
@@ -1532,7 +1542,8 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
     if (S->check_every < 1 || S->ruiz_iters < 0 || S->max_attempts < 1 || !(S->tol >= 0.0) ||
         S->step_mode < 0 || S->step_mode > 1 || (S->step_mode == 1 && !(S->step_fixed > 0.0)) ||
         S->precision < 0 || S->precision > 2 || !(S->polish_tol >= 0.0) || S->polish_stall < 1 ||
-        S->plain_pdhg < 0 || S->plain_pdhg > 1 || (S->plain_pdhg == 1 && !(S->step_fixed > 0.0)))
+        S->plain_pdhg < 0 || S->plain_pdhg > 1 || (S->plain_pdhg == 1 && !(S->step_fixed > 0.0)) ||
+        S->batch_dropout < 0 || S->batch_dropout > 2)
         fail(PDCS_ERR_INVALID_ARG, "bad settings");
     if (tr && B != 1) fail(PDCS_ERR_INVALID_ARG, "a trace is for a single problem");
     if (tr && (tr->cap < 0 || tr->n_snap < 0 || (tr->n_snap > 0 && (!tr->snap_iter || !tr->snap_x || !tr->snap_y)) ||
@@ -1692,6 +1703,10 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
     std::vector<pdcs_info> handed(B);     // results of instances finished on their own
     std::vector<double> done(B, -1.0);    // seconds until each instance stopped
     std::vector<char> was_handed(B, 0);
+    // seconds per attempt over the batch: at the first check (the whole batch
+    // running) and since the last check, for the hand-over rule of dropout 2
+    double full_att_s = -1.0, t_last_check = 0.0;
+    long long att_since = 0;
     while (any_active()) {
         // ---- step attempts until every running instance asks for a check ----
         while (any_running()) {
@@ -1700,6 +1715,7 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
                 if (active(b) && !hs[b].halt)
                     todo = std::min<long long>(todo, S->check_every - hs[b].kin % S->check_every);
             const long long batch = stepwise ? 1 : std::max<long long>(1, todo);
+            att_since += batch;
             if (S->time_kernels) {
                 enqueue_attempts(P, batch, mode, s, P->tev.data());
             } else if (S->use_graph && batch == kGraphBatch) {
@@ -1763,7 +1779,11 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
         if (gerr[0] || gerr[1])
             fail(PDCS_ERR_HIP, "a grid-level SOC projection timed out waiting for its workgroups");
         const double elapsed = std::chrono::duration<double>(clk::now() - t_iter).count();
-        bool any_restart = false, switch_ok = mixed;
+        // the products are one launch over the batch, so the batch switches to
+        // FP64 together: as soon as any instance meets the rule (waiting for
+        // all of them kept the instances that were ready in FP32 products,
+        // short of the tolerance, until the slowest one caught up)
+        bool any_restart = false, switch_ok = false;
         int64_t log_running = 0, log_iter = 0;
         double log_kkt = 0.0;
         for (int64_t b = 0; b < B; ++b) {
@@ -1844,7 +1864,7 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
             if (mixed) {
                 if (kc.mx() < best_mixed[b]) best_mixed[b] = kc.mx(), stall[b] = 0;
                 else ++stall[b];
-                if (!(kc.mx() <= S->polish_tol || stall[b] >= S->polish_stall)) switch_ok = false;
+                if (kc.mx() <= S->polish_tol || stall[b] >= S->polish_stall) switch_ok = true;
             }
         }
         if (S->log_every > 0.0 && elapsed - last_log >= S->log_every) {
@@ -1881,11 +1901,22 @@ static void solve_batch(pdcs_problem *P, const pdcs_settings *S, const double *c
         // of its own, restarted at its chosen candidate with its primal weight
         // (a restart, as Algorithm 1 may take at any check), with the rest of
         // the iteration and time budget.
+        // dropout 1: at that share.  dropout 2: also only once an attempt over
+        // the batch costs more than 4x what the running instances' own
+        // attempts would (their share of the first check's cost per attempt,
+        // at least kAloneAttemptS each): the launches then mostly dispatch
+        // workgroups of finished instances, which return at once.
+        const double att_s = att_since > 0 ? (elapsed - t_last_check) / (double)att_since : 0.0;
+        if (full_att_s < 0.0) full_att_s = att_s;
+        t_last_check = elapsed, att_since = 0;
         if (B > 1 && S->batch_dropout && any_active()) {
-            int64_t act_nnz = 0;
+            int64_t act_nnz = 0, act_cnt = 0;
             for (int64_t b = 0; b < B; ++b)
-                if (active(b)) act_nnz += P->inst[b].nnz;
-            if (8 * act_nnz <= P->nnz) {
+                if (active(b)) act_nnz += P->inst[b].nnz, ++act_cnt;
+            const double own_s = std::max(full_att_s * (double)act_nnz / (double)std::max<int64_t>(P->nnz, 1),
+                                          kAloneAttemptS * (double)act_cnt);
+            const bool costly = S->batch_dropout != 2 || att_s > 4.0 * own_s;
+            if (8 * act_nnz <= P->nnz && costly) {
                 for (int64_t b = 0; b < B; ++b) {
                     if (!active(b)) continue;
                     const InstDims &I = P->inst[b];

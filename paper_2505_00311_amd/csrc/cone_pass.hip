@@ -7,7 +7,7 @@
 // Each workgroup reads one tile of the side's cone plan: a run of elementwise
 // entries (box / zero / free / nonnegative, thread per entry), SOC blocks of
 // one size class (an aligned group of 8, 16, 32 or 64 lanes per block, up to
-// 256 entries), one larger SOC block (whole workgroup), or up to 64
+// 256 entries), one larger SOC block (whole workgroup), or up to 256
 // exponential cones (one thread each) -- the thread-, block- and grid-level
 // strategies of Section 4 mapped to CDNA wavefronts.
 #include "cones_device.hpp"

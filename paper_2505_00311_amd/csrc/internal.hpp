@@ -18,7 +18,11 @@ constexpr int kBlock = 256;          // threads per workgroup of every pass kern
 constexpr int kWave = 64;            // CDNA wavefront
 constexpr int kSocWaveMax = 256;     // SOC blocks up to this dim: a lane group each
 constexpr int kElemPerTile = 2048;   // entries per elementwise tile
-constexpr int kExpPerTile = 64;      // exponential cones per tile (one thread each)
+// exponential cones per tile (one thread each): 256 (four wavefronts) when a
+// cone list still gets kExpMinTiles tiles that way, else 128, else 64
+constexpr int kExpPerTile = 64;
+constexpr int kExpMinTiles = 512;
+static_assert(4 * kExpPerTile <= kBlock, "an exponential tile holds at most one cone per thread");
 constexpr int kPartials = 6;         // per-tile partial slots: 3 sums, 3 maxima
 // SOC blocks of at least kSocGridMin entries are spread over several
 // workgroups (one per kSocGridChunk entries, at most kSocGridMaxParts)

@@ -23,7 +23,7 @@ def mix():
 OBJ_REL = 3e-5
 
 
-@pytest.mark.parametrize("autotune,dropout", [(0, 0), (1, 0), (1, 1)])
+@pytest.mark.parametrize("autotune,dropout", [(0, 0), (1, 0), (1, 1), (1, 2)])
 def test_batch_solves_each_instance_to_tolerance(pd, orc, autotune, dropout):
     insts = mix()
     batch = pd.Batch(insts)
