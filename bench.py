@@ -103,9 +103,12 @@ def exp_fp64_flops():
     if not m:
         return None
     rec = json.loads(m.group(1))
-    src = os.path.join(ROOT, rec["source"])
-    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["sha256"]:
+    if not isinstance(rec.get("sources"), dict):
         return None
+    for path, sha in rec["sources"].items():
+        src = os.path.join(ROOT, path)
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != sha:
+            return None
     return rec["fp64_flop_per_launch"]
 
 
