@@ -120,6 +120,26 @@ def test_project_unscaled_extreme_exp(pd, orc):
         assert np.all(np.isfinite(got)) and err <= 1e-12, (dual, err)
 
 
+@pytest.mark.parametrize("nb", [70_000, 140_000])
+def test_project_exp_wide_tiles(pd, orc, nb):
+    """Cone lists long enough for 128 (7e4 cones) and 256 (1.4e5 cones)
+    exponential cones per tile, with a ragged last tile: every cone against
+    the oracle, primal and dual, scaled and unscaled."""
+    rng = np.random.default_rng(nb)
+    v = rng.standard_normal(3 * nb) * 10 ** rng.uniform(-2, 2, 3 * nb)
+    d = 10 ** rng.uniform(-1.0, 1.0, 3 * nb)
+    for dual in (False, True):
+        for scaled in (False, True):
+            ref = orc.proj_blocks([4] * nb, [3] * nb, v, d if scaled else None, dual=dual)
+            vd = dev(v)
+            pd.project([4] * nb, [3] * nb, vd, dev(d) if scaled else None, dual=dual)
+            got = vd.cpu().numpy().reshape(nb, 3)
+            sc = np.maximum(1.0, np.linalg.norm(v.reshape(nb, 3), axis=1))
+            err = (np.abs(got - ref.reshape(nb, 3)).max(axis=1) / sc).max()
+            say("wide exp tiles", nb, dual, scaled, "max err", err)
+            assert np.all(np.isfinite(got)) and err <= 1e-12, (nb, dual, scaled, err)
+
+
 # ---------------------------------------------------------------- products
 @pytest.mark.parametrize("maker", ["small", "lp_soc", "powerlaw"])
 def test_spmv_matches_oracle(pd, orc, maker):
