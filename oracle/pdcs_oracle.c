@@ -208,8 +208,16 @@ static double exp_root(const exp_ctx *c, double xneg, double xpos) {
     return rho;
 }
 
+/* Reading (floating point, not in the paper): entries below 2^-960 in magnitude
+ * are taken as 0.  The case tests divide the entries by the scales and the
+ * interval ends divide entries by entries; with denormal entries those
+ * quotients round to 0 and misclassify the point (or give 0/0).  Zeroing them
+ * moves the projection by at most their size (a projection onto a closed
+ * convex set is nonexpansive). */
+static double exp_flush(double x) { return fabs(x) < 0x1p-960 ? 0.0 : x; }
+
 int orc_proj_exp(const double *v, const double *d, double *out) {
-    double r0 = v[0], s0 = v[1], t0 = v[2];
+    double r0 = exp_flush(v[0]), s0 = exp_flush(v[1]), t0 = exp_flush(v[2]);
     double dr = d ? d[0] : 1.0, ds = d ? d[1] : 1.0, dt = d ? d[2] : 1.0;
     /* case 1: v0 in D K_exp, i.e. D^-1 v0 in K_exp */
     if (in_kexp(r0 / dr, s0 / ds, t0 / dt)) {
@@ -236,11 +244,13 @@ int orc_proj_exp(const double *v, const double *d, double *out) {
     const double R = 700.0;
     exp_ctx c = {r0, s0, t0, dr, ds, dt, ds / dr};
     double xneg, xpos;
+    /* a3 = (r0/s0)(ds/dr), a4 = 1 - (s0/r0)(ds/dr) as ratios: the products
+     * s0 dr and r0 dr round to 0 for denormal s0 or r0, and 0/0 is NaN */
     if (r0 > 0.0 && s0 > 0.0) {
-        xpos = fmin(r0 * ds / (s0 * dr), R);
-        xneg = fmax(1.0 - s0 * ds / (r0 * dr), -R);
+        xpos = fmin((r0 / s0) * c.tau, R);
+        xneg = fmax(1.0 - (s0 / r0) * c.tau, -R);
     } else if (s0 > 0.0) { /* r0 <= 0: (-inf, a3) */
-        double a3 = r0 * ds / (s0 * dr);
+        double a3 = (r0 / s0) * c.tau;
         if (!(a3 >= -R)) {
             out[0] = r0, out[1] = s0, out[2] = dt * (s0 / ds) * exp(a3);
             return 4;
@@ -253,7 +263,7 @@ int orc_proj_exp(const double *v, const double *d, double *out) {
             xneg = fmax(xpos - step, -R);
         }
     } else { /* r0 > 0, s0 <= 0: (a4, inf) */
-        double a4 = 1.0 - s0 * ds / (r0 * dr);
+        double a4 = 1.0 - (s0 / r0) * c.tau;
         if (!(a4 <= R)) {
             out[0] = 0.0, out[1] = 0.0, out[2] = t0 > 0.0 ? t0 : 0.0;
             return 4;

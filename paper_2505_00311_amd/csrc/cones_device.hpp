@@ -30,6 +30,8 @@ __device__ __forceinline__ bool in_kexp_dual(double r, double s, double t) {
     return r == 0.0 && s >= 0.0 && t >= 0.0;
 }
 
+__device__ __forceinline__ double exp_flush(double x) { return fabs(x) < 0x1p-960 ? 0.0 : x; }
+
 struct ExpPt {
     double r0, s0, t0, dr, ds, dt, tau, idr, idt;
 };
@@ -152,6 +154,11 @@ __device__ __forceinline__ void exp_local_bracket(const ExpPt &c, double g, doub
 __device__ void exp_project(double r0, double s0, double t0, double dr, double ds, double dt,
                             double &pr, double &ps, double &pt, double guess, double &rho_out) {
     rho_out = __builtin_nan("");
+    // entries below 2^-960 are taken as 0: the case tests divide them by the
+    // scales and the interval ends divide them by each other, and denormal
+    // quotients misclassify the point or give 0/0 (zeroing moves the
+    // projection by at most their size: it is nonexpansive)
+    r0 = exp_flush(r0), s0 = exp_flush(s0), t0 = exp_flush(t0);
     if (in_kexp(r0 / dr, s0 / ds, t0 / dt)) {              // case 1
         pr = r0, ps = s0, pt = t0;
         return;
@@ -172,19 +179,22 @@ __device__ void exp_project(double r0, double s0, double t0, double dr, double d
     const ExpPt c{r0, s0, t0, dr, ds, dt, ds / dr, 1.0 / dr, 1.0 / dt};
     double xneg, xpos, lo, hi;   // [lo, hi]: the case-4 interval kept inside |rho| <= R
     int side;                    // 0: both ends finite, 1: (-inf, a3), 2: (a4, inf)
+    // the ends from the ratios r0/s0 and s0/r0: with a denormal s0 or r0 the
+    // product s0 dr (r0 dr) can round to 0 and 0/0 would give NaN
+    const double tau = ds / dr;
     if (r0 > 0.0 && s0 > 0.0) {
-        hi = fmin(r0 * ds / (s0 * dr), R);
-        lo = fmax(1.0 - s0 * ds / (r0 * dr), -R);
+        hi = fmin((r0 / s0) * tau, R);
+        lo = fmax(1.0 - (s0 / r0) * tau, -R);
         side = 0;
     } else if (s0 > 0.0) {
-        const double a3 = r0 * ds / (s0 * dr);
+        const double a3 = (r0 / s0) * tau;
         if (!(a3 >= -R)) {
             pr = r0, ps = s0, pt = dt * (s0 / ds) * exp(a3);
             return;
         }
         lo = -R, hi = a3, side = 1;
     } else {
-        const double a4 = 1.0 - s0 * ds / (r0 * dr);
+        const double a4 = 1.0 - (s0 / r0) * tau;
         if (!(a4 <= R)) {
             pr = 0.0, ps = 0.0, pt = t0 > 0.0 ? t0 : 0.0;
             return;
@@ -638,14 +648,15 @@ __device__ __noinline__ void exp_project_fallback(double r0, double s0, double t
 __device__ void exp_project_f(double r0, double s0, double t0, double dr, double ds, double dt,
                               double &pr, double &ps, double &pt, double guess, double &rho_out) {
     constexpr double RF = 40.0;
+    r0 = exp_flush(r0), s0 = exp_flush(s0), t0 = exp_flush(t0);   // as exp_project
     const bool c4 = !in_kexp(r0 / dr, s0 / ds, t0 / dt) && !in_kexp_dual(-dr * r0, -ds * s0, -dt * t0) &&
                     !(r0 <= 0.0 && s0 <= 0.0);
     double lo = 0.0, hi = 0.0;
     bool fits = false;
     if (c4) {
         if (r0 > 0.0 && s0 > 0.0) {
-            hi = r0 * ds / (s0 * dr);
-            lo = 1.0 - s0 * ds / (r0 * dr);
+            hi = (r0 / s0) * (ds / dr);
+            lo = 1.0 - (s0 / r0) * (ds / dr);
             fits = lo >= -RF && hi <= RF;
         }
     }
@@ -704,9 +715,14 @@ __device__ void exp_project_f(double r0, double s0, double t0, double dr, double
     }
     float cf = (c.r0 * w0 + c.s0 * w1 + c.t0 * w2) / (w0 * w0 + w1 * w1 + w2 * w2);
     if (!(cf > 0.0f)) cf = 0.0f;
-    pr = (double)(cf * w0);
-    ps = (double)(cf * w1);
-    pt = (double)(cf * w2);
+    const float qr = cf * w0, qs = cf * w1, qt = cf * w2;
+    if (!(isfinite(qr) && isfinite(qs) && isfinite(qt))) {   // the ray left the FP32 range
+        exp_project_fallback(r0, s0, t0, dr, ds, dt, pr, ps, pt, guess, rho_out);
+        return;
+    }
+    pr = (double)qr;
+    ps = (double)qs;
+    pt = (double)qt;
 }
 
 __device__ __forceinline__ void exp_dual_project_f(double r0, double s0, double t0, double dr,

@@ -120,6 +120,34 @@ def test_project_unscaled_extreme_exp(pd, orc):
         assert np.all(np.isfinite(got)) and err <= 1e-12, (dual, err)
 
 
+def test_project_exp_denormal_entries(pd, orc):
+    """Exponential cones with entries that are 0 or denormal (the input that
+    once gave NaN: a restart candidate (0, -5e-324, 0.99999999) under scales
+    (4.64, 1, 1)), FP64 and FP32 passes, primal and dual, against the oracle."""
+    rng = np.random.default_rng(23)
+    nb = 20000
+    # magnitudes and scales over 10^+-1, as in the FP32 bound test of the mixed form
+    v = rng.standard_normal((nb, 3)) * 10 ** rng.uniform(-1, 1, (nb, 1))
+    tiny = np.array([5e-324, -5e-324, 1e-310, -1e-310, 1e-300, -1e-300, 0.0, -0.0])
+    mask = rng.random((nb, 3)) < 0.4
+    v[mask] = rng.choice(tiny, size=int(mask.sum()))
+    v[0] = [0.0, -5e-324, 0.9999999903850852]
+    v = v.ravel()
+    d = 10 ** rng.uniform(-1, 1, 3 * nb)
+    d[:3] = [4.644325615449967, 1.0, 1.0]
+    for dual in (False, True):
+        ref = orc.proj_blocks([4] * nb, [3] * nb, v, d, dual=dual)
+        for fp32 in (False, True):
+            vd = dev(v)
+            (pd.project_fp32 if fp32 else pd.project)([4] * nb, [3] * nb, vd, dev(d), dual=dual)
+            got = vd.cpu().numpy().reshape(nb, 3)
+            sc = np.maximum(1.0, np.linalg.norm(v.reshape(nb, 3), axis=1))
+            err = np.abs(got - ref.reshape(nb, 3)).max(axis=1) / sc
+            say("denormal exp", dual, fp32, "max err", err.max())
+            assert np.all(np.isfinite(got)), (dual, fp32)
+            assert err.max() <= (2e-5 if fp32 else 1e-12), (dual, fp32, err.max())
+
+
 @pytest.mark.parametrize("nb", [70_000, 140_000])
 def test_project_exp_wide_tiles(pd, orc, nb):
     """Cone lists long enough for 128 (7e4 cones) and 256 (1.4e5 cones)

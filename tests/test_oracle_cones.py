@@ -270,6 +270,34 @@ def test_exp_far_brackets_stay_finite(orc):
             assert np.linalg.norm(v - q) <= np.linalg.norm(v) * (1 + 1e-12)
 
 
+def test_exp_denormal_entries(orc):
+    """Entries that are 0 or denormal.  The case-4 interval end a3 = r0 ds/(s0 dr)
+    (or a4) was once formed as a product over a product: with s0 = -5e-324 (met
+    by a restart candidate of the logistic workload, scales (4.64, 1, 1)) s0 dr
+    rounds to 0 and a3 became 0/0.  A projection onto a closed convex set is
+    nonexpansive, so replacing the tiny entry by 0 moves the projection by at
+    most that entry: every output finite and within |delta| (+ rounding)."""
+    p, _ = orc.proj_exp_dual(np.array([0.0, -5e-324, 0.9999999903850852]),
+                             np.array([4.644325615449967, 1.0, 1.0]))
+    assert np.all(np.isfinite(p)) and abs(p[2] - 0.9999999903850852) <= 1e-15
+    rng = np.random.default_rng(19)
+    tiny = [5e-324, -5e-324, 1e-310, -1e-310, 1e-300, -1e-300, 0.0, -0.0]
+    for _ in range(4000):
+        v = rng.standard_normal(3) * 10 ** rng.uniform(-2, 2, 3)
+        d = 10 ** rng.uniform(-2, 2, 3)
+        k = rng.integers(0, 3, size=rng.integers(1, 3))
+        w = v.copy()
+        w[k] = rng.choice(tiny, size=k.size)
+        w0 = w.copy()
+        w0[k] = 0.0
+        for fn in (orc.proj_exp, orc.proj_exp_dual):
+            q, _ = fn(w, d)
+            q0, _ = fn(w0, d)
+            assert np.all(np.isfinite(q)), (w, d)
+            bound = np.linalg.norm(w - w0) + 1e-14 * max(1.0, np.linalg.norm(w))
+            assert np.linalg.norm(q - q0) <= bound, (w, d, q, q0)
+
+
 def test_exp_idempotent(orc):
     rng = np.random.default_rng(16)
     for _ in range(500):
