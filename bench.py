@@ -89,6 +89,25 @@ def counter_traffic(kernel):
     return rec["kernels"][kernel]["bytes_per_launch"]
 
 
+def batched_512_record():
+    """The committed record of the batched configuration at its size (512
+    instances, 4.5e9 nonzeros; `--config4` reproduces it), or None.  Not
+    measured in this run: it takes about seven minutes of GPU time."""
+    import re
+    path = os.path.join(ROOT, "profiles", "batched_512_instances.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"<!-- record: (\{.*?\}) -->", open(path).read())
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    rec.update({"recorded": True, "measured_in_this_run": False,
+                "source": "profiles/batched_512_instances.md",
+                "command": "python bench.py --config4 --c4-mode batch --c4-time-limit 420; "
+                           "python bench.py --config4 --c4-mode single --c4-stride 16 --c4-time-limit 90"})
+    return rec
+
+
 def exp_fp64_flops():
     """FP64 operations per launch of the 2e5-cone dual exponential projection of
     the logistic workload, from the committed rocprofv3 counter summary (FMA
@@ -837,6 +856,9 @@ def main():
 
     if args.batch_count > 0:
         out["batched"] = batched_form(pdcs, instances, torch, args.batch_count)
+    rec512 = batched_512_record()
+    if rec512 is not None:
+        out["batched_512_recorded"] = rec512
     if args.family_assets > 0:
         out["warm_start"] = warm_start_form(pdcs, instances, torch, args.family_assets,
                                             args.family_train, args.family_test)

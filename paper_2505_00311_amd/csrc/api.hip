@@ -594,6 +594,9 @@ struct pdcs_mlp {
     // padded leading dimension of the output gradient (a multiple of 8)
     uint16_t *ta, *tb, *wt;
     int64_t ldo = 0;
+    // split-K partial products of dH2 = dO W3 (M = batch, K = the outputs)
+    float *ws = nullptr;
+    int64_t ws_elems = 0;
 };
 
 constexpr int kGraphBatch = 64;   // step attempts per captured graph
@@ -2536,6 +2539,8 @@ pdcs_status pdcs_mlp_create(int64_t in, int64_t hid, int64_t out, int64_t max_ba
         M->tb = D.alloc<uint16_t>(std::max(hid, in) * B);
         M->wt = D.alloc<uint16_t>(hid * std::max(M->ldo, hid));
         M->dh = D.alloc<float>(B * hid);
+        M->ws_elems = 32 * B * hid;
+        M->ws = D.alloc<float>(M->ws_elems);
         M->part = D.alloc<double>((B * std::max(out, hid) + 255) / 256);
         PDCS_HIP(hipStreamSynchronize(s));
         *mlp = M.release();
@@ -2573,7 +2578,9 @@ static double mlp_gradient(pdcs_mlp *M, const float *theta, const float *target,
     gemm_bf16(0, 1, O, hid, B, M->ta, B, M->tb, B, nullptr, 0, g + M->off[4], nullptr, hid, s);
     colsum(M->d32, B, O, g + M->off[5], s);
     transpose_bf16(M->p16 + M->off[4], O, hid, hid, M->wt, ldo, s);
-    gemm_bf16(0, 1, B, hid, O, M->d16, ldo, M->wt, ldo, nullptr, 0, M->dh, nullptr, hid, s);
+    if (!gemm_bf16_split(B, hid, O, M->d16, ldo, M->wt, ldo, nullptr, 0, M->dh, nullptr, hid, M->ws,
+                         M->ws_elems, s))
+        gemm_bf16(0, 1, B, hid, O, M->d16, ldo, M->wt, ldo, nullptr, 0, M->dh, nullptr, hid, s);
     // layer 2
     relu_back(M->dh, M->h2, B * hid, M->d32, M->d16, s);
     transpose_bf16(M->d16, B, hid, hid, M->ta, B, s);

@@ -415,6 +415,13 @@ void unscale(const double *xs, const double *f, double *out, int64_t n, hipStrea
 void gemm_bf16(int ta, int tb, int64_t M, int64_t N, int64_t K, const uint16_t *a, int64_t lda,
                const uint16_t *b, int64_t ldb, const float *bias, int relu, float *c32,
                uint16_t *c16, int64_t ldc, hipStream_t s);
+// gemm_bf16 for ta = 0, tb = 1 with K split over chunks whose partial products
+// go to ws (ws_elems floats), added in chunk order by a second kernel; false
+// (nothing launched) when the shape has enough output tiles, K is short, the
+// operands are not 16-byte aligned or ws holds fewer than two chunks.
+bool gemm_bf16_split(int64_t M, int64_t N, int64_t K, const uint16_t *a, int64_t lda,
+                     const uint16_t *b, int64_t ldb, const float *bias, int relu, float *c32,
+                     uint16_t *c16, int64_t ldc, float *ws, int64_t ws_elems, hipStream_t s);
 void to_bf16(const float *in, uint16_t *out, int64_t n, hipStream_t s);
 // Both hidden layers of the network in one launch (theta FP32 in; theta's BF16
 // copy, h1 and h2 in FP32 and BF16 out); false (nothing launched) for shapes

@@ -19,6 +19,7 @@
 #include <cstdint>
 
 #include "device_common.hpp"
+#include <algorithm>
 
 namespace pdcs {
 
@@ -135,6 +136,10 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int64_t M, int64_t N, in
 // current one in LDS, so the load latency overlaps the MFMAs instead of
 // preceding them.  Same tile and MFMA layout as gemm_bf16_kernel.
 constexpr int kKStepP = 64, kLdsKP = 72;   // LDS row: 64 k-values + 8 padding
+// split K (gemm_bf16_split): only for products of at most kSplitMaxTiles output
+// tiles over at least kSplitMinK (too few workgroups for a long k loop), in
+// chunks of about kSplitChunk
+constexpr int64_t kSplitMaxTiles = 64, kSplitMinK = 4096, kSplitChunk = 1024;
 
 // op(X)[r0 .. r0+127][k0 .. k0+63] (X read along k, 8-aligned rows) into four
 // 16-byte registers per thread, zero outside.
@@ -170,14 +175,24 @@ __device__ __forceinline__ void put_k64(uint16_t (*S)[kLdsKP], const uint4 (&r)[
     }
 }
 
+// kchunk > 0 (split K): workgroup z takes k in [z kchunk, (z + 1) kchunk) and
+// writes its raw partial product to the M x N block z of c32 (no bias, ReLU
+// or BF16 copy: splitk_sum_kernel adds the blocks and applies them).
 __global__ __launch_bounds__(256) void gemm_bf16_pipe_kernel(int64_t M, int64_t N, int64_t K,
                                                              const uint16_t *__restrict__ a, int64_t lda,
                                                              const uint16_t *__restrict__ b, int64_t ldb,
                                                              const float *__restrict__ bias, int relu,
                                                              float *__restrict__ c32,
-                                                             uint16_t *__restrict__ c16, int64_t ldc) {
+                                                             uint16_t *__restrict__ c16, int64_t ldc,
+                                                             int64_t kchunk) {
     __shared__ __attribute__((aligned(16))) uint16_t As[kTile][kLdsKP];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[kTile][kLdsKP];
+    if (kchunk > 0) {
+        const int64_t k0 = (int64_t)blockIdx.z * kchunk;
+        a += k0, b += k0;
+        K = K - k0 < kchunk ? K - k0 : kchunk;
+        c32 += (int64_t)blockIdx.z * M * ldc;
+    }
     const int t = threadIdx.x, lane = t % 64, w = t / 64;
     const int wm = w / 2, wn = w % 2;
     const int64_t m0 = (int64_t)blockIdx.y * kTile, n0 = (int64_t)blockIdx.x * kTile;
@@ -243,7 +258,7 @@ void gemm_bf16(int ta, int tb, int64_t M, int64_t N, int64_t K, const uint16_t *
     if (ta == 0 && tb == 1) {
         if (va && vb)
             hipLaunchKernelGGL(gemm_bf16_pipe_kernel, grid, dim3(256), 0, s, M, N, K, a, lda, b, ldb,
-                               bias, relu, c32, c16, ldc);
+                               bias, relu, c32, c16, ldc, (int64_t)0);
         else if (va) PDCS_GEMM(0, 1, true, false);
         else if (vb) PDCS_GEMM(0, 1, false, true);
         else PDCS_GEMM(0, 1, false, false);
@@ -258,6 +273,43 @@ void gemm_bf16(int ta, int tb, int64_t M, int64_t N, int64_t K, const uint16_t *
     }
 #undef PDCS_GEMM
     PDCS_HIP(hipGetLastError());
+}
+
+// The split-K blocks of gemm_bf16_split added in block order (so the result
+// does not depend on scheduling), then bias, ReLU and the FP32 / BF16 stores.
+__global__ void splitk_sum_kernel(const float *__restrict__ ws, int64_t S, int64_t M, int64_t N,
+                                  const float *__restrict__ bias, int relu, float *__restrict__ c32,
+                                  uint16_t *__restrict__ c16, int64_t ldc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M * N) return;
+    const int64_t m = i / N, n = i % N;
+    float v = 0.0f;
+    for (int64_t z = 0; z < S; ++z) v += ws[z * M * N + i];
+    if (bias) v += bias[n];
+    if (relu && v < 0.0f) v = 0.0f;
+    if (c32) c32[m * ldc + n] = v;
+    if (c16) c16[m * ldc + n] = f32_to_bf16(v);
+}
+
+bool gemm_bf16_split(int64_t M, int64_t N, int64_t K, const uint16_t *a, int64_t lda,
+                     const uint16_t *b, int64_t ldb, const float *bias, int relu, float *c32,
+                     uint16_t *c16, int64_t ldc, float *ws, int64_t ws_elems, hipStream_t s) {
+    const int64_t tiles = ((M + kTile - 1) / kTile) * ((N + kTile - 1) / kTile);
+    const bool vec = lda % 8 == 0 && ldb % 8 == 0 && ((uintptr_t)a % 16) == 0 && ((uintptr_t)b % 16) == 0;
+    if (!ws || !vec || M < 1 || N < 1 || tiles > kSplitMaxTiles || K < kSplitMinK) return false;
+    // chunks of whole 64-wide k-steps, about kSplitChunk each, as many as ws holds
+    int64_t S = std::min<int64_t>((K + kSplitChunk - 1) / kSplitChunk, ws_elems / (M * N));
+    if (S < 2) return false;
+    const int64_t kchunk = ((K + S - 1) / S + kKStepP - 1) / kKStepP * kKStepP;
+    S = (K + kchunk - 1) / kchunk;
+    const dim3 grid((unsigned)((N + kTile - 1) / kTile), (unsigned)((M + kTile - 1) / kTile), (unsigned)S);
+    hipLaunchKernelGGL(gemm_bf16_pipe_kernel, grid, dim3(256), 0, s, M, N, K, a, lda, b, ldb,
+                       (const float *)nullptr, 0, ws, (uint16_t *)nullptr, N, kchunk);
+    PDCS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(splitk_sum_kernel, dim3((unsigned)((M * N + 255) / 256)), dim3(256), 0, s, ws, S,
+                       M, N, bias, relu, c32, c16, ldc);
+    PDCS_HIP(hipGetLastError());
+    return true;
 }
 
 // ------------------------------------------------ fused hidden layers
@@ -428,11 +480,22 @@ __global__ void relu_back_kernel(const float *dh, const float *z, int64_t n, flo
 }
 
 // db[j] = sum over rows of d[r, j], rows in order
+// Column sums, rows added in order; a thread issues 16 rows' loads before
+// adding them, so a short, wide sum waits on few memory latencies.
 __global__ void colsum_kernel(const float *d, int64_t rows, int64_t cols, float *db) {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= cols) return;
+    constexpr int U = 16;
     float acc = 0.0f;
-    for (int64_t r = 0; r < rows; ++r) acc += d[r * cols + j];
+    int64_t r = 0;
+    for (; r + U <= rows; r += U) {
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = d[(r + u) * cols + j];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += v[u];
+    }
+    for (; r < rows; ++r) acc += d[r * cols + j];
     db[j] = acc;
 }
 

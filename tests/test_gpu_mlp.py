@@ -48,13 +48,16 @@ def test_gemm_matches_oracle(pd, ta, tb, shape):
     assert np.array_equal(from_bits(c16), OM.bf16(got))
 
 
-def test_network_gradient_matches_oracle(pd):
+@pytest.mark.parametrize("n_out", [300, 5000])
+def test_network_gradient_matches_oracle(pd, n_out):
     """The GPU gradient against the oracle's backpropagation with the same BF16
     rounding points.  Both sides may round an intermediate to neighbouring BF16
     values where FP32 and FP64 sums straddle a rounding boundary, so each
-    parameter block is held to one BF16 unit (2^-8) in relative 2-norm."""
+    parameter block is held to one BF16 unit (2^-8) in relative 2-norm.  With
+    5000 outputs the product dH2 = dO W3 (k = the outputs) takes the split-K
+    path: partial products of 1024-wide k chunks added in chunk order."""
     rng = np.random.default_rng(3)
-    n_in, hid, n_out, B = 64, 128, 300, 32
+    n_in, hid, B = 64, 128, 32
     npar = hid * n_in + hid + hid * hid + hid + n_out * hid + n_out
     p = np.concatenate([rng.standard_normal(hid * n_in) * np.sqrt(2 / n_in), np.zeros(hid) + 0.1,
                         rng.standard_normal(hid * hid) * np.sqrt(2 / hid), np.zeros(hid) + 0.1,
