@@ -41,7 +41,7 @@ typedef enum {
     PDCS_ERR_NONFINITE = -3,     /* NaN/inf in G, c or h (l, u may hold +-inf)         */
     PDCS_ERR_OOM = -4,           /* device allocation failed                           */
     PDCS_ERR_HIP = -5,           /* a HIP runtime call failed                          */
-    PDCS_ERR_NOT_SUPPORTED = -6  /* valid request outside what this build implements   */
+    PDCS_ERR_NOT_SUPPORTED = -6  /* valid request outside what the library implements */
 } pdcs_status;
 
 /* Disciplined cones of Section 1.2.  A block of dimension d.
