@@ -67,6 +67,30 @@ def test_grid_projection_matches_oracle(pd, orc, dual, scaled):
         o += k
 
 
+@pytest.mark.parametrize("scaled", [False, True])
+def test_grid_projection_capped_parts(pd, orc, scaled):
+    """200 grid-level blocks of 40 001 entries: the parts of all such blocks are
+    capped near 1536 in all, so each block gets 7 parts of 5715 or more entries
+    instead of 10 of 4096 (a ragged last part), against the oracle."""
+    rng = np.random.default_rng(41 + scaled)
+    dims = [40001] * 200
+    types = [SOC] * len(dims)
+    v = np.concatenate([rng.standard_normal(k) * 10 ** rng.uniform(-1, 1) for k in dims])
+    offs = np.concatenate([[0], np.cumsum(dims)])
+    for b in range(0, len(dims), 4):          # every fourth block on the boundary's far side
+        nx = np.linalg.norm(v[offs[b] + 1:offs[b + 1]])
+        v[offs[b]] = (-0.5 if b % 8 else 0.5) * nx
+    d = 10 ** rng.uniform(-0.5, 0.5, v.size)
+    say("grid capped parts", scaled, v.size)
+    ref = orc.proj_blocks(types, dims, v, d if scaled else None)
+    vd = dev(v)
+    pd.project(types, dims, vd, dev(d) if scaled else None)
+    got = vd.cpu().numpy()
+    worst = max(np.abs(got[a:b] - ref[a:b]).max() / max(1.0, np.linalg.norm(v[a:b]))
+                for a, b in zip(offs[:-1], offs[1:]))
+    assert worst <= 1e-12, worst
+
+
 def test_grid_projection_repeats_bit_for_bit(pd):
     """One plan, five projections in a row (the barrier counters keep
     growing across launches): the same bits each time, and the same as a
