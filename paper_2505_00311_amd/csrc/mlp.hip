@@ -317,9 +317,10 @@ bool gemm_bf16_split(int64_t M, int64_t N, int64_t K, const uint16_t *a, int64_t
 // launch: h1 = relu(W1 theta + b1) for all hid units of those rows (theta
 // rounded to BF16 on the way in, h1 kept in LDS as BF16), then h2 = relu(W2 h1
 // + b2) for 128 of the hid units, one 32 x 32 block of the matrix cores per
-// wavefront.  Workgroup (x, y) takes rows 32 y .. and units 128 x ..; the
-// workgroups with x = 0 also write theta's BF16 copy and h1 (FP32 and BF16)
-// for the backward pass.  The weights (B operands) are read straight from
+// wavefront.  Workgroup (x, y) takes rows 32 y .. and units 128 x ..; for the
+// backward pass the workgroups with x = 0 also write theta's BF16 copy, and
+// each workgroup of a row block writes its share of h1 (FP32 and BF16), so
+// that no workgroup carries all of those stores.  The weights (B operands) are read straight from
 // global memory with the lane layout of gemm_bf16_kernel; the products
 // accumulate over k in ascending steps of 16 as in that kernel, so the
 // results are the same bits as the three separate launches.
@@ -357,6 +358,9 @@ __global__ __launch_bounds__(256) void mlp_hidden_kernel(int64_t B, int in, int 
         }
         const int col = jb * 32 + idx;
         const float bn = b1[col];
+        // h1 for the backward pass: each 32-unit block written by one of the
+        // workgroups of this row block (block jb by workgroup jb mod gridDim.x)
+        const bool mine = jb % (int)gridDim.x == (int)blockIdx.x;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int row = 8 * (r / 4) + 4 * half + (r % 4);
@@ -364,7 +368,7 @@ __global__ __launch_bounds__(256) void mlp_hidden_kernel(int64_t B, int in, int 
             if (v < 0.0f) v = 0.0f;
             const uint16_t v16 = f32_to_bf16(v);
             hs[row][col] = v16;
-            if (first && r0 + row < B) {
+            if (mine && r0 + row < B) {
                 h1[(r0 + row) * hid + col] = v;
                 h1b[(r0 + row) * hid + col] = v16;
             }
