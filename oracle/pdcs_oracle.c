@@ -15,7 +15,9 @@
  *   - termination measures: Section 5 eq. (PDCS_terminate_tolerance).
  * Where the paper defers a rule to its companion technical note (step size,
  * reflection parameter, restart trigger, primal weight, rescaling scheme) the
- * code states the reading it takes next to the rule.
+ * code states the reading it takes next to the rule.  The tests pin those rules
+ * to hand-worked examples of the readings; against the paper itself they are
+ * parity unpinned (the paper does not state them).
  *
  * Vectors are handled whole, in the order the paper writes the steps; nothing
  * is fused, blocked or reordered.
